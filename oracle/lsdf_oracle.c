@@ -1,0 +1,420 @@
+/*
+ * lsdf_oracle.c -- plain, slow CPU reference for batched robot-to-obstacle
+ * clearance against link-local signed distance grids.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; it is used by the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark.  It shares no code, header or constant
+ * with the HIP library: the two are written independently from the method's
+ * definition (paper Sec. III-A) and compared.
+ *
+ * What it computes (paper Sec. III-A, problem statement and Fig. 3):
+ *   for each configuration c, each link i and each obstacle point x_j,
+ *   the link-local SDF of link i evaluated at the point expressed in link
+ *   i's frame, T_{i,c}^{-1} x_j; the clearance of c is the minimum over
+ *   points and links.  The link SDF is a grid of signed distances sampled
+ *   at nodes of the link's box (the "Link SDFs" of Sec. III-A) and read
+ *   between nodes by trilinear interpolation (the affine-grid sampling the
+ *   paper borrows from spatial transformer networks, Sec. III-A).
+ *
+ * Readings where the paper is silent (listed with their justification in
+ * the design notes): nodes sit on the box corners (node-centred grid);
+ * points outside a link's box contribute +infinity; the SDF is negative
+ * inside; a link made of several closed parts takes the minimum over the
+ * parts; argmin ties go to the lowest link index; -0 is returned as +0.
+ *
+ * Precision: everything is double, except orc_query_f32, the single-
+ * precision twin of the query used to take the argmin decision in the
+ * precision of the GPU kernel.  Compile with -ffp-contract=off: every fused
+ * multiply-add below is written out as fma()/fmaf().
+ *
+ * Parallelism: OpenMP over independent outer loops only (grid nodes,
+ * configurations); the arithmetic of each element is unchanged by it.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_EXPORT __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------------ */
+/* small vector helpers (double)                                             */
+/* ------------------------------------------------------------------------ */
+static void v_sub(const double a[3], const double b[3], double r[3]) {
+    r[0] = a[0] - b[0]; r[1] = a[1] - b[1]; r[2] = a[2] - b[2];
+}
+static double v_dot(const double a[3], const double b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static void v_cross(const double a[3], const double b[3], double r[3]) {
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double v_norm(const double a[3]) { return sqrt(v_dot(a, a)); }
+
+/* ------------------------------------------------------------------------ */
+/* Point-to-triangle distance, by definition: the closest point of a         */
+/* triangle is either the orthogonal projection onto its plane (when that    */
+/* projection lies inside the triangle) or a point of one of its three       */
+/* edges.  So the distance is the minimum of those candidates.               */
+/* ------------------------------------------------------------------------ */
+static double dist_point_segment(const double p[3], const double a[3], const double b[3]) {
+    double ab[3], ap[3];
+    v_sub(b, a, ab);
+    v_sub(p, a, ap);
+    double L2 = v_dot(ab, ab);
+    double t = L2 > 0.0 ? v_dot(ap, ab) / L2 : 0.0;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    double q[3] = {a[0] + t * ab[0] - p[0], a[1] + t * ab[1] - p[1], a[2] + t * ab[2] - p[2]};
+    return v_norm(q);
+}
+
+ORC_EXPORT double orc_point_triangle_distance(const double* p, const double* a,
+                                              const double* b, const double* c) {
+    double best = dist_point_segment(p, a, b);
+    double e = dist_point_segment(p, b, c);
+    if (e < best) best = e;
+    e = dist_point_segment(p, c, a);
+    if (e < best) best = e;
+    /* interior candidate: barycentric coordinates of the projection */
+    double ab[3], ac[3], ap[3], nrm[3];
+    v_sub(b, a, ab);
+    v_sub(c, a, ac);
+    v_sub(p, a, ap);
+    v_cross(ab, ac, nrm);
+    double nn = v_dot(nrm, nrm);
+    if (nn > 0.0) {
+        double h = v_dot(ap, nrm) / nn;                    /* signed height / |n| */
+        double proj[3] = {ap[0] - h * nrm[0], ap[1] - h * nrm[1], ap[2] - h * nrm[2]};
+        double tmp[3];
+        v_cross(proj, ac, tmp);
+        double beta = v_dot(tmp, nrm) / nn;                /* weight of b */
+        v_cross(ab, proj, tmp);
+        double gamma = v_dot(tmp, nrm) / nn;               /* weight of c */
+        double alpha = 1.0 - beta - gamma;
+        if (alpha >= 0.0 && beta >= 0.0 && gamma >= 0.0) {
+            double dplane = fabs(h) * sqrt(nn);
+            if (dplane < best) best = dplane;
+        }
+    }
+    return best;
+}
+
+/* Solid angle subtended at p by triangle (a, b, c), signed by orientation:
+ * tan(Omega / 2) = det[A B C] / (|A||B||C| + (A.B)|C| + (A.C)|B| + (B.C)|A|)
+ * with A = a - p etc. (Van Oosterom & Strackee, IEEE TBME 1983). */
+static double solid_angle(const double p[3], const double a[3], const double b[3], const double c[3]) {
+    double A[3], B[3], C[3], bc[3];
+    v_sub(a, p, A);
+    v_sub(b, p, B);
+    v_sub(c, p, C);
+    v_cross(B, C, bc);
+    double det = v_dot(A, bc);
+    double la = v_norm(A), lb = v_norm(B), lc = v_norm(C);
+    double den = la * lb * lc + v_dot(A, B) * lc + v_dot(A, C) * lb + v_dot(B, C) * la;
+    return 2.0 * atan2(det, den);
+}
+
+/* Generalised winding number of a closed, outward-oriented triangle set
+ * (Jacobson et al., SIGGRAPH 2013): total signed solid angle / (4 pi).
+ * 1 inside, 0 outside. */
+ORC_EXPORT double orc_winding_number(const double* p, const double* V, const int32_t* T,
+                                     int32_t t0, int32_t t1) {
+    double sum = 0.0;
+    for (int32_t t = t0; t < t1; ++t)
+        sum += solid_angle(p, V + 3 * T[3 * t], V + 3 * T[3 * t + 1], V + 3 * T[3 * t + 2]);
+    return sum / (4.0 * M_PI);
+}
+
+/* Signed distance of p to a link made of closed parts [comp_first[k],
+ * comp_first[k+1]): each part's distance is the unsigned distance to its
+ * triangles, negated when the winding number says p is inside; the link
+ * takes the minimum over its parts. */
+ORC_EXPORT double orc_mesh_sdf(const double* p, const double* V, const int32_t* T,
+                               const int32_t* comp_first, int32_t ncomp) {
+    double s = INFINITY;
+    for (int32_t k = 0; k < ncomp; ++k) {
+        double u = INFINITY;
+        for (int32_t t = comp_first[k]; t < comp_first[k + 1]; ++t) {
+            double d = orc_point_triangle_distance(p, V + 3 * T[3 * t], V + 3 * T[3 * t + 1],
+                                                   V + 3 * T[3 * t + 2]);
+            if (d < u) u = d;
+        }
+        double w = orc_winding_number(p, V, T, comp_first[k], comp_first[k + 1]);
+        double sk = (w > 0.5) ? -u : u;
+        if (sk < s) s = sk;
+    }
+    return s;
+}
+
+ORC_EXPORT void orc_mesh_sdf_many(const double* P, int64_t np, const double* V, const int32_t* T,
+                                  const int32_t* comp_first, int32_t ncomp, double* out) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t j = 0; j < np; ++j) out[j] = orc_mesh_sdf(P + 3 * j, V, T, comp_first, ncomp);
+}
+
+/* Link SDF grid: node k = (kx, ky, kz) sits at lo + k * h with
+ * h = (hi - lo) / (n - 1) per axis; storage index (kz * ny + ky) * nx + kx. */
+ORC_EXPORT void orc_build_grid(const double* V, const int32_t* T, const int32_t* comp_first,
+                               int32_t ncomp, const double* lo, const double* hi, const int32_t* n,
+                               double* out) {
+    const int64_t nx = n[0], ny = n[1], nz = n[2];
+    double h[3];
+    for (int a = 0; a < 3; ++a) h[a] = (hi[a] - lo[a]) / (double)(n[a] - 1);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t idx = 0; idx < nx * ny * nz; ++idx) {
+        int64_t kx = idx % nx, ky = (idx / nx) % ny, kz = idx / (nx * ny);
+        double p[3] = {lo[0] + kx * h[0], lo[1] + ky * h[1], lo[2] + kz * h[2]};
+        out[idx] = orc_mesh_sdf(p, V, T, comp_first, ncomp);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward kinematics (paper Sec. III-A: link poses T_{i,c} of every link i  */
+/* at every configuration c).  Standard DH: frame k = frame k-1 moved by     */
+/* Rz(theta) Tz(d) Tx(a) Rx(alpha), theta = q_k + theta_offset_k, written as  */
+/* a product of the four elementary 4x4 matrices.                            */
+/* ------------------------------------------------------------------------ */
+static void m4_mul(const double A[16], const double B[16], double R[16]) {
+    double t[16];
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k) s += A[4 * r + k] * B[4 * k + c];
+            t[4 * r + c] = s;
+        }
+    memcpy(R, t, sizeof(t));
+}
+static void m4_eye(double M[16]) {
+    memset(M, 0, 16 * sizeof(double));
+    M[0] = M[5] = M[10] = M[15] = 1.0;
+}
+static void m4_rotz(double th, double M[16]) {
+    m4_eye(M);
+    M[0] = cos(th); M[1] = -sin(th);
+    M[4] = sin(th); M[5] = cos(th);
+}
+static void m4_rotx(double al, double M[16]) {
+    m4_eye(M);
+    M[5] = cos(al); M[6] = -sin(al);
+    M[9] = sin(al); M[10] = cos(al);
+}
+static void m4_trans(double x, double y, double z, double M[16]) {
+    m4_eye(M);
+    M[3] = x; M[7] = y; M[11] = z;
+}
+
+/* dh: [dof][4] rows (a, alpha, d, theta_offset); base: 3x4 link-0 pose or
+ * NULL for identity; q: [C][dof]; T out: [C][dof+1][3][4], row-major [R | t],
+ * each mapping link-frame coordinates to world coordinates. */
+ORC_EXPORT void orc_fk(const double* dh, int32_t dof, const double* base, const double* q,
+                       int32_t C, double* T) {
+    for (int32_t c = 0; c < C; ++c) {
+        double cur[16];
+        m4_eye(cur);
+        if (base) for (int r = 0; r < 3; ++r) for (int k = 0; k < 4; ++k) cur[4 * r + k] = base[4 * r + k];
+        double* out = T + (int64_t)c * (dof + 1) * 12;
+        memcpy(out, cur, 12 * sizeof(double));
+        for (int32_t k = 0; k < dof; ++k) {
+            double a = dh[4 * k], alpha = dh[4 * k + 1], d = dh[4 * k + 2], off = dh[4 * k + 3];
+            double th = q[(int64_t)c * dof + k] + off;
+            double A[16], E[16];
+            m4_rotz(th, A);
+            m4_trans(0.0, 0.0, d, E);  m4_mul(A, E, A);
+            m4_trans(a, 0.0, 0.0, E);  m4_mul(A, E, A);
+            m4_rotx(alpha, E);         m4_mul(A, E, A);
+            m4_mul(cur, A, cur);
+            memcpy(out + 12 * (k + 1), cur, 12 * sizeof(double));
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Query in double: per (c, i) the minimum over points of the trilinear      */
+/* interpolant g_i at l = R^T (x - t), +inf when no point lies in the box.   */
+/* ------------------------------------------------------------------------ */
+
+/* Trilinear interpolation written as the weighted sum of the 8 cell corners
+ * (weights are products of f or 1 - f per axis).  u: grid coordinates,
+ * already known to satisfy 0 <= u_a <= n_a - 1. */
+ORC_EXPORT double orc_trilinear_f64(const double* grid, const int32_t* n, const double* u) {
+    int64_t i[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        int64_t k = (int64_t)floor(u[a]);
+        if (k > n[a] - 2) k = n[a] - 2;
+        i[a] = k;
+        f[a] = u[a] - (double)k;
+    }
+    double v = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+                int64_t idx = ((i[2] + dz) * n[1] + (i[1] + dy)) * (int64_t)n[0] + (i[0] + dx);
+                v += w * grid[idx];
+            }
+    return v;
+}
+
+/* T: [C][L][3][4] double poses; lo/hi: [L][3]; n: [L][3]; grids packed with
+ * link i starting at offs[i]; P: [M][3]; out: [C][L] per-link minima. */
+ORC_EXPORT void orc_query_f64(const double* T, int32_t C, int32_t L, const double* lo,
+                              const double* hi, const int32_t* n, const double* grids,
+                              const int64_t* offs, const double* P, int64_t M, double* out) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t c = 0; c < C; ++c) {
+        for (int32_t i = 0; i < L; ++i) {
+            const double* Ti = T + ((int64_t)c * L + i) * 12;
+            const double* lo_i = lo + 3 * i;
+            const double* hi_i = hi + 3 * i;
+            const int32_t* n_i = n + 3 * i;
+            double h[3];
+            for (int a = 0; a < 3; ++a) h[a] = (hi_i[a] - lo_i[a]) / (double)(n_i[a] - 1);
+            double best = INFINITY;
+            for (int64_t j = 0; j < M; ++j) {
+                double d[3] = {P[3 * j] - Ti[3], P[3 * j + 1] - Ti[7], P[3 * j + 2] - Ti[11]};
+                double u[3];
+                int inside = 1;
+                for (int a = 0; a < 3; ++a) {
+                    /* l_a = sum_r R[r][a] d_r  (R^T d) */
+                    double l = Ti[0 + a] * d[0] + Ti[4 + a] * d[1] + Ti[8 + a] * d[2];
+                    u[a] = (l - lo_i[a]) / h[a];
+                    if (!(u[a] >= 0.0 && u[a] <= (double)(n_i[a] - 1))) inside = 0;
+                }
+                if (!inside) continue;
+                double v = orc_trilinear_f64(grids + offs[i], n_i, u);
+                if (v < best) best = v;
+            }
+            out[(int64_t)c * L + i] = best;
+        }
+    }
+}
+
+/* Exact (grid-free) per-link minima: the mesh SDF of link i at every point
+ * expressed in link i's frame, over all points (no box).  Brute force, for
+ * tiny inputs. */
+ORC_EXPORT void orc_exact_min(const double* T, int32_t C, int32_t L, const double* const* Vs,
+                              const int32_t* const* Ts, const int32_t* const* comps,
+                              const int32_t* ncomps, const double* P, int64_t M, double* out) {
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+    for (int32_t c = 0; c < C; ++c) {
+        for (int32_t i = 0; i < L; ++i) {
+            const double* Ti = T + ((int64_t)c * L + i) * 12;
+            double best = INFINITY;
+            for (int64_t j = 0; j < M; ++j) {
+                double d[3] = {P[3 * j] - Ti[3], P[3 * j + 1] - Ti[7], P[3 * j + 2] - Ti[11]};
+                double l[3];
+                for (int a = 0; a < 3; ++a) l[a] = Ti[0 + a] * d[0] + Ti[4 + a] * d[1] + Ti[8 + a] * d[2];
+                double s = orc_mesh_sdf(l, Vs[i], Ts[i], comps[i], ncomps[i]);
+                if (s < best) best = s;
+            }
+            out[(int64_t)c * L + i] = best;
+        }
+    }
+}
+
+/* Per configuration: minimum over links and the lowest link index that
+ * attains it; (+inf, -1) when every link is +inf. */
+ORC_EXPORT void orc_reduce_f64(const double* cl, int32_t C, int32_t L, double* d, int32_t* link) {
+    for (int32_t c = 0; c < C; ++c) {
+        double best = INFINITY;
+        int32_t arg = -1;
+        for (int32_t i = 0; i < L; ++i) {
+            double v = cl[(int64_t)c * L + i];
+            if (v < best) { best = v; arg = i; }
+        }
+        d[c] = best;
+        link[c] = arg;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-precision twin of the query.  Every operation is one IEEE binary32 */
+/* operation in a fixed order, so that the argmin decision is taken in the   */
+/* same precision as the GPU kernel:                                         */
+/*   per axis a: invh_a = (float)((n_a-1) / (hi_a - lo_a))  [double, 1 round] */
+/*               nlo_a  = (float)(-lo_a * invh_a)            [double, 1 round] */
+/*   per (c, i): the world-to-grid affine map of the inverse pose, as one     */
+/*     homogeneous matrix (the form of paper Eq. 4):                          */
+/*       M[a][b] = invh_a * R[b][a]                                           */
+/*       w_a = fma(-invh_a, fma(R[0][a], t0, fma(R[1][a], t1, R[2][a]*t2)),   */
+/*                 nlo_a)                                                     */
+/*   per point: u_a = fma(M[a][0], x, fma(M[a][1], y, fma(M[a][2], z, w_a)))  */
+/*     inside iff 0 <= u_a <= n_a - 1 for every a                             */
+/*     i_a = min(floor(u_a), n_a - 2), f_a = u_a - i_a (exact)               */
+/*     lerp(p, q, f) = fma(f, q, fma(-f, p, p)) (exact at f = 0 and f = 1):   */
+/*     four along x, two along y, one along z                                 */
+/*     value + 0.0f (turns -0 into +0); running minimum.                      */
+/* ------------------------------------------------------------------------ */
+static float lerpf_(float p, float q, float f) { return fmaf(f, q, fmaf(-f, p, p)); }
+
+ORC_EXPORT void orc_query_f32(const float* T, int32_t C, int32_t L, const float* lo,
+                              const float* hi, const int32_t* n, const float* grids,
+                              const int64_t* offs, const float* P, int64_t M, float* out) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t c = 0; c < C; ++c) {
+        for (int32_t i = 0; i < L; ++i) {
+            const float* Ti = T + ((int64_t)c * L + i) * 12;
+            const int32_t* n_i = n + 3 * i;
+            const float* G = grids + offs[i];
+            float invh[3], nlo[3], Mx[3][3], w[3];
+            for (int a = 0; a < 3; ++a) {
+                invh[a] = (float)((double)(n_i[a] - 1) / ((double)hi[3 * i + a] - (double)lo[3 * i + a]));
+                nlo[a] = (float)(-(double)lo[3 * i + a] * (double)invh[a]);
+            }
+            for (int a = 0; a < 3; ++a) {
+                for (int b = 0; b < 3; ++b) Mx[a][b] = invh[a] * Ti[4 * b + a];
+                float rt = fmaf(Ti[0 + a], Ti[3], fmaf(Ti[4 + a], Ti[7], Ti[8 + a] * Ti[11]));
+                w[a] = fmaf(-invh[a], rt, nlo[a]);
+            }
+            float best = INFINITY;
+            for (int64_t j = 0; j < M; ++j) {
+                float x = P[3 * j], y = P[3 * j + 1], z = P[3 * j + 2];
+                float u[3];
+                int inside = 1;
+                for (int a = 0; a < 3; ++a) {
+                    u[a] = fmaf(Mx[a][0], x, fmaf(Mx[a][1], y, fmaf(Mx[a][2], z, w[a])));
+                    if (!(u[a] >= 0.0f && u[a] <= (float)(n_i[a] - 1))) inside = 0;
+                }
+                if (!inside) continue;
+                int64_t k[3];
+                float f[3];
+                for (int a = 0; a < 3; ++a) {
+                    int64_t q = (int64_t)floorf(u[a]);
+                    if (q > n_i[a] - 2) q = n_i[a] - 2;
+                    k[a] = q;
+                    f[a] = u[a] - (float)q;
+                }
+                const int64_t nx = n_i[0], ny = n_i[1];
+#define GV(dx, dy, dz) G[((k[2] + (dz)) * ny + (k[1] + (dy))) * nx + (k[0] + (dx))]
+                float e00 = lerpf_(GV(0, 0, 0), GV(1, 0, 0), f[0]);
+                float e10 = lerpf_(GV(0, 1, 0), GV(1, 1, 0), f[0]);
+                float e01 = lerpf_(GV(0, 0, 1), GV(1, 0, 1), f[0]);
+                float e11 = lerpf_(GV(0, 1, 1), GV(1, 1, 1), f[0]);
+#undef GV
+                float e0 = lerpf_(e00, e10, f[1]);
+                float e1 = lerpf_(e01, e11, f[1]);
+                float v = lerpf_(e0, e1, f[2]) + 0.0f;
+                if (v < best) best = v;
+            }
+            out[(int64_t)c * L + i] = best;
+        }
+    }
+}
+
+ORC_EXPORT void orc_reduce_f32(const float* cl, int32_t C, int32_t L, float* d, int32_t* link) {
+    for (int32_t c = 0; c < C; ++c) {
+        float best = INFINITY;
+        int32_t arg = -1;
+        for (int32_t i = 0; i < L; ++i) {
+            float v = cl[(int64_t)c * L + i];
+            if (v < best) { best = v; arg = i; }
+        }
+        d[c] = best;
+        link[c] = arg;
+    }
+}

@@ -1,0 +1,237 @@
+"""ctypes front end of the C oracle (lsdf_oracle.c) plus numpy glue.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg; never by the product library.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "lsdf_oracle.c")
+LIB = os.path.join(HERE, "liblsdf_oracle.so")
+
+_lib = None
+
+_dp = ct.POINTER(ct.c_double)
+_fp = ct.POINTER(ct.c_float)
+_ip = ct.POINTER(ct.c_int32)
+_lp = ct.POINTER(ct.c_int64)
+
+
+def build_oracle(force: bool = True) -> str:
+    """Compile the oracle with gcc: no fast-math, no FMA contraction."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-std=gnu11", "-o", LIB + ".tmp", SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        build_oracle()
+    lib = ct.CDLL(LIB)
+    lib.orc_point_triangle_distance.restype = ct.c_double
+    lib.orc_point_triangle_distance.argtypes = [_dp, _dp, _dp, _dp]
+    lib.orc_winding_number.restype = ct.c_double
+    lib.orc_winding_number.argtypes = [_dp, _dp, _ip, ct.c_int32, ct.c_int32]
+    lib.orc_mesh_sdf.restype = ct.c_double
+    lib.orc_mesh_sdf.argtypes = [_dp, _dp, _ip, _ip, ct.c_int32]
+    lib.orc_mesh_sdf_many.restype = None
+    lib.orc_mesh_sdf_many.argtypes = [_dp, ct.c_int64, _dp, _ip, _ip, ct.c_int32, _dp]
+    lib.orc_build_grid.restype = None
+    lib.orc_build_grid.argtypes = [_dp, _ip, _ip, ct.c_int32, _dp, _dp, _ip, _dp]
+    lib.orc_fk.restype = None
+    lib.orc_fk.argtypes = [_dp, ct.c_int32, _dp, _dp, ct.c_int32, _dp]
+    lib.orc_trilinear_f64.restype = ct.c_double
+    lib.orc_trilinear_f64.argtypes = [_dp, _ip, _dp]
+    lib.orc_query_f64.restype = None
+    lib.orc_query_f64.argtypes = [_dp, ct.c_int32, ct.c_int32, _dp, _dp, _ip, _dp, _lp, _dp,
+                                  ct.c_int64, _dp]
+    lib.orc_query_f32.restype = None
+    lib.orc_query_f32.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _fp, _ip, _fp, _lp, _fp,
+                                  ct.c_int64, _fp]
+    lib.orc_exact_min.restype = None
+    lib.orc_exact_min.argtypes = [_dp, ct.c_int32, ct.c_int32, ct.POINTER(_dp), ct.POINTER(_ip),
+                                  ct.POINTER(_ip), _ip, _dp, ct.c_int64, _dp]
+    lib.orc_reduce_f64.restype = None
+    lib.orc_reduce_f64.argtypes = [_dp, ct.c_int32, ct.c_int32, _dp, _ip]
+    lib.orc_reduce_f32.restype = None
+    lib.orc_reduce_f32.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _ip]
+    _lib = lib
+    return lib
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a, typ):
+    return a.ctypes.data_as(typ)
+
+
+# ---------------------------------------------------------------------------
+# mesh distance
+# ---------------------------------------------------------------------------
+
+def point_triangle_distance(p, a, b, c) -> float:
+    lib = load()
+    arrs = [_c(x, np.float64) for x in (p, a, b, c)]
+    return float(lib.orc_point_triangle_distance(*[_ptr(x, _dp) for x in arrs]))
+
+
+def winding_number(p, verts, tris, t0=0, t1=None) -> float:
+    lib = load()
+    p, V, T = _c(p, np.float64), _c(verts, np.float64), _c(tris, np.int32)
+    t1 = T.shape[0] if t1 is None else t1
+    return float(lib.orc_winding_number(_ptr(p, _dp), _ptr(V, _dp), _ptr(T, _ip), t0, t1))
+
+
+def mesh_sdf(points, verts, tris, comp_first=None) -> np.ndarray:
+    """Signed distance of each point [N][3] to a union of closed parts."""
+    lib = load()
+    P = _c(np.atleast_2d(points), np.float64)
+    V, T = _c(verts, np.float64), _c(tris, np.int32)
+    cf = _c([0, T.shape[0]] if comp_first is None else comp_first, np.int32)
+    out = np.empty(P.shape[0], dtype=np.float64)
+    lib.orc_mesh_sdf_many(_ptr(P, _dp), P.shape[0], _ptr(V, _dp), _ptr(T, _ip), _ptr(cf, _ip),
+                          cf.shape[0] - 1, _ptr(out, _dp))
+    return out
+
+
+def build_grid(mesh, lo, hi, n) -> np.ndarray:
+    """float64 grid [nz][ny][nx] of the link's signed distance at the nodes."""
+    lib = load()
+    V, T, cf = _c(mesh.verts, np.float64), _c(mesh.tris, np.int32), _c(mesh.comp_first, np.int32)
+    lo, hi, n = _c(lo, np.float64), _c(hi, np.float64), _c(n, np.int32)
+    out = np.empty(int(n[2]) * int(n[1]) * int(n[0]), dtype=np.float64)
+    lib.orc_build_grid(_ptr(V, _dp), _ptr(T, _ip), _ptr(cf, _ip), cf.shape[0] - 1, _ptr(lo, _dp),
+                       _ptr(hi, _dp), _ptr(n, _ip), _ptr(out, _dp))
+    return out.reshape(int(n[2]), int(n[1]), int(n[0]))
+
+
+def grid_bound(h) -> float:
+    """Largest interpolation error of a 1-Lipschitz field on a cell with
+    spacing h: half the cell diagonal (the |r_r|/2 term of Sec. III-B)."""
+    h = np.asarray(h, dtype=np.float64)
+    return 0.5 * float(np.sqrt((h * h).sum()))
+
+
+# ---------------------------------------------------------------------------
+# kinematics and queries
+# ---------------------------------------------------------------------------
+
+def fk(dh, q, base=None) -> np.ndarray:
+    """float64 [C][dof+1][3][4] link-to-world poses."""
+    lib = load()
+    dh = _c(dh, np.float64)
+    q = _c(np.atleast_2d(q), np.float64)
+    C, dof = q.shape
+    base_p = None
+    if base is not None:
+        base = _c(base, np.float64)
+        base_p = _ptr(base, _dp)
+    T = np.empty((C, dof + 1, 3, 4), dtype=np.float64)
+    lib.orc_fk(_ptr(dh, _dp), dof, base_p, _ptr(q, _dp), C, _ptr(T, _dp))
+    return T
+
+
+def _pack(grids, dtype):
+    offs = np.zeros(len(grids), dtype=np.int64)
+    tot = 0
+    for i, g in enumerate(grids):
+        offs[i] = tot
+        tot += g.size
+    buf = np.concatenate([np.ravel(g).astype(dtype) for g in grids]) if grids else np.zeros(0, dtype)
+    return _c(buf, dtype), offs
+
+
+def query_f64(T, lo, hi, n, grids, points) -> np.ndarray:
+    """Per-link minima [C][L] in double (trilinear as a weighted sum)."""
+    lib = load()
+    T = _c(T, np.float64)
+    C, L = T.shape[0], T.shape[1]
+    lo, hi, n = _c(lo, np.float64), _c(hi, np.float64), _c(n, np.int32)
+    buf, offs = _pack(grids, np.float64)
+    P = _c(points, np.float64).reshape(-1, 3)
+    out = np.empty((C, L), dtype=np.float64)
+    lib.orc_query_f64(_ptr(T, _dp), C, L, _ptr(lo, _dp), _ptr(hi, _dp), _ptr(n, _ip),
+                      _ptr(buf, _dp), _ptr(offs, _lp), _ptr(P, _dp), P.shape[0], _ptr(out, _dp))
+    return out
+
+
+def query_f32(T, lo, hi, n, grids, points) -> np.ndarray:
+    """Per-link minima [C][L] in the fixed single-precision operation order."""
+    lib = load()
+    T = _c(T, np.float32)
+    C, L = T.shape[0], T.shape[1]
+    lo, hi, n = _c(lo, np.float32), _c(hi, np.float32), _c(n, np.int32)
+    buf, offs = _pack(grids, np.float32)
+    P = _c(points, np.float32).reshape(-1, 3)
+    out = np.empty((C, L), dtype=np.float32)
+    lib.orc_query_f32(_ptr(T, _fp), C, L, _ptr(lo, _fp), _ptr(hi, _fp), _ptr(n, _ip),
+                      _ptr(buf, _fp), _ptr(offs, _lp), _ptr(P, _fp), P.shape[0], _ptr(out, _fp))
+    return out
+
+
+def exact_min(T, meshes, points) -> np.ndarray:
+    """Grid-free per-link minima [C][L]: exact mesh SDF at every point."""
+    lib = load()
+    T = _c(T, np.float64)
+    C, L = T.shape[0], T.shape[1]
+    Vs = [_c(m.verts, np.float64) for m in meshes]
+    Ts = [_c(m.tris, np.int32) for m in meshes]
+    Cs = [_c(m.comp_first, np.int32) for m in meshes]
+    nc = _c([m.comp_first.shape[0] - 1 for m in meshes], np.int32)
+    Vp = (_dp * L)(*[_ptr(v, _dp) for v in Vs])
+    Tp = (_ip * L)(*[_ptr(t, _ip) for t in Ts])
+    Cp = (_ip * L)(*[_ptr(c, _ip) for c in Cs])
+    P = _c(points, np.float64).reshape(-1, 3)
+    out = np.empty((C, L), dtype=np.float64)
+    lib.orc_exact_min(_ptr(T, _dp), C, L, Vp, Tp, Cp, _ptr(nc, _ip), _ptr(P, _dp), P.shape[0],
+                      _ptr(out, _dp))
+    return out
+
+
+def reduce(cl):
+    """Per configuration: (min over links, lowest argmin link or -1)."""
+    lib = load()
+    C, L = cl.shape
+    link = np.empty(C, dtype=np.int32)
+    if cl.dtype == np.float32:
+        cl = _c(cl, np.float32)
+        d = np.empty(C, dtype=np.float32)
+        lib.orc_reduce_f32(_ptr(cl, _fp), C, L, _ptr(d, _fp), _ptr(link, _ip))
+    else:
+        cl = _c(cl, np.float64)
+        d = np.empty(C, dtype=np.float64)
+        lib.orc_reduce_f64(_ptr(cl, _dp), C, L, _ptr(d, _dp), _ptr(link, _ip))
+    return d, link
+
+
+def trilinear_f64(grid, u) -> float:
+    lib = load()
+    g = _c(grid, np.float64)
+    n = _c([g.shape[2], g.shape[1], g.shape[0]], np.int32)
+    u = _c(u, np.float64)
+    return float(lib.orc_trilinear_f64(_ptr(g, _dp), _ptr(n, _ip), _ptr(u, _dp)))
+
+
+def workload_grids(w, dtype=np.float64):
+    """Oracle grids for every link of a synthetic workload."""
+    return [build_grid(m, w.grid_lo[i].astype(np.float64), w.grid_hi[i].astype(np.float64),
+                       w.grid_n[i]).astype(dtype)
+            for i, m in enumerate(w.robot.links)]
+
+
+__all__ = ["build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
+           "query_f32", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids"]

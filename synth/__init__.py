@@ -1,0 +1,88 @@
+"""Seeded synthetic inputs shared by the library's tests, the benchmark and
+the oracle's tests.  This package holds input generation only (robot
+parameters and meshes, waypoints, obstacle clouds, grid boxes); none of the
+distance method's arithmetic is here.
+
+Base seed 230912543; sub-streams: DH and meshes S+0, waypoints S+2+100*traj,
+scene S+3+100*traj.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from .robot import GRID_PAD, Mesh, Robot, box_mesh, capsule_mesh, grid_box, make_robot, sphere_mesh, union_mesh
+from .scene import human_table, uniform_cube
+from .traj import make_waypoints
+
+BASE_SEED = 230912543
+
+
+@dataclass
+class Workload:
+    name: str
+    robot: Robot
+    q: np.ndarray            # float64 [C][dof]
+    points: np.ndarray       # float64 [M][3] (values exactly representable in float32)
+    grid_lo: np.ndarray      # float32 [L][3]
+    grid_hi: np.ndarray      # float32 [L][3]
+    grid_n: np.ndarray       # int32 [L][3]
+    info: dict
+
+    @property
+    def C(self) -> int:
+        return int(self.q.shape[0])
+
+    @property
+    def M(self) -> int:
+        return int(self.points.shape[0])
+
+    @property
+    def L(self) -> int:
+        return self.robot.n_links
+
+
+# name -> (C, M, cloud kind, voxel size, grid nodes per axis)
+WORKLOADS = {
+    # 50 waypoints x 2,000 points uniform in a 2 m cube, 32^3 grids
+    "tiny": (50, 2000, "cube", None, 32),
+    # 500 waypoints x 20,000 points (2 cm voxels of a person + table), 64^3 grids
+    "paper": (500, 20000, "scene", 0.02, 64),
+    # 500 waypoints x 100,000 points (1 cm voxels), 128^3 grids (precision study)
+    "precision": (500, 100000, "scene", 0.01, 128),
+    # 500 waypoints x 100,000 points (1 cm voxels), 64^3 grids (learned variant)
+    "learned": (500, 100000, "scene", 0.01, 64),
+}
+
+
+def make_workload(name: str = "tiny", C: int | None = None, M: int | None = None,
+                  n: int | None = None, traj: int = 0, seed: int = BASE_SEED) -> Workload:
+    C0, M0, kind, voxel, n0 = WORKLOADS[name]
+    C = C0 if C is None else C
+    M = M0 if M is None else M
+    n = n0 if n is None else n
+    robot = make_robot(seed + 0)
+    q = make_waypoints(robot.qmin, robot.qmax, C, seed + 2 + 100 * traj)
+    info = {"workload": name, "C": C, "M": M, "n": n}
+    if kind == "cube":
+        pts = uniform_cube(M, seed + 3 + 100 * traj)
+    else:
+        pts, sinfo = human_table(M, voxel, seed + 3 + 100 * traj, return_info=True)
+        info.update(sinfo)
+        info["voxel_m"] = voxel
+    pts = pts.astype(np.float32).astype(np.float64)
+    los, his = [], []
+    for mesh in robot.links:
+        lo, hi = grid_box(mesh)
+        los.append(lo)
+        his.append(hi)
+    grid_lo = np.array(los, dtype=np.float32)
+    grid_hi = np.array(his, dtype=np.float32)
+    grid_n = np.full((robot.n_links, 3), n, dtype=np.int32)
+    return Workload(name, robot, q, pts, grid_lo, grid_hi, grid_n, info)
+
+
+__all__ = ["BASE_SEED", "GRID_PAD", "Mesh", "Robot", "Workload", "WORKLOADS", "box_mesh",
+           "capsule_mesh", "grid_box", "human_table", "make_robot", "make_waypoints",
+           "make_workload", "sphere_mesh", "uniform_cube", "union_mesh"]
