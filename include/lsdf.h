@@ -1,0 +1,156 @@
+/*
+ * lsdf.h -- C ABI of liblsdf.so: batched robot-to-obstacle clearance against
+ * link-local signed distance grids on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Fujii & Pham, "Real-time Batched Distance Computation for
+ * Time-Optimal Safe Path Tracking", Sec. III-A): for every configuration
+ * theta_c of a D-DoF arm, forward kinematics gives the pose T_{i,c} of every
+ * link i; the distance between the robot and the obstacles at theta_c is the
+ * minimum, over the occupied obstacle voxels x_j and the links i, of link
+ * i's precomputed signed distance field ("Link SDF") read at the obstacle
+ * expressed in the link's frame.  This library evaluates that minimum
+ * directly per point (each point is moved into every link frame by the
+ * inverse pose of Sec. III-B-1, Eq. 4, and the link grid is sampled by
+ * trilinear interpolation), rather than through the paper's pre-aligned
+ * per-configuration robot grids.
+ *
+ * Conventions shared by every call
+ *   - Return value: LSDF_OK (0) or a negative LSDF_E_* code.  No exception
+ *     crosses the ABI.  lsdf_last_error() gives a message for the last
+ *     failure on the calling thread.
+ *   - Argument errors are detected on the host before anything is enqueued;
+ *     on error nothing is launched and no output is touched.
+ *   - Device pointers refer to memory of the current HIP device.  All work
+ *     is enqueued asynchronously on `stream` (a hipStream_t passed as void*;
+ *     NULL = the legacy default stream).  Device faults surface at the
+ *     caller's next synchronisation.
+ *   - The library never allocates memory.  All buffers are owned by the
+ *     caller; scratch memory comes from a caller-provided workspace.
+ *   - Inputs must be finite.  Units are metres and radians.
+ *   - Poses are row-major 3x4 [R | t] mapping link-frame coordinates to world
+ *     coordinates: x_world = R x_link + t.
+ */
+#ifndef LSDF_H
+#define LSDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define LSDF_OK             0
+#define LSDF_E_INVALID_ARG (-1)   /* NULL pointer, non-finite or out-of-range value */
+#define LSDF_E_SHAPE       (-2)   /* inconsistent sizes, workspace too small */
+#define LSDF_E_UNSUPPORTED (-3)   /* unknown dtype or flag */
+#define LSDF_E_DEVICE      (-4)   /* a HIP call failed (launch error, bad stream) */
+
+/* ---- grid storage types -------------------------------------------------- */
+#define LSDF_F32  0
+#define LSDF_BF16 1
+#define LSDF_F16  2
+
+/* ---- limits --------------------------------------------------------------- */
+#define LSDF_MAX_LINKS      16    /* links per query (dof + 1 for a serial arm) */
+#define LSDF_MAX_DOF        15
+#define LSDF_MAX_COMPONENTS 16    /* closed parts per link mesh */
+
+/* One link's SDF grid (the "Link SDF" of Sec. III-A: extent e_r, resolution
+ * r_r, in the link's own frame).  Node-centred: node k = (kx, ky, kz),
+ * 0 <= k_a < n_a, holds the signed distance at lo + k * h with
+ * h_a = (hi_a - lo_a) / (n_a - 1); the box [lo, hi] is the capture range.
+ * Storage: element (kz * n_y + ky) * n_x + kx (x fastest), `dtype` elements,
+ * starting `elem_offset` elements into the shared grid buffer.  Negative
+ * inside the link, positive outside. */
+typedef struct lsdf_grid {
+    float   lo[3];
+    float   hi[3];
+    int32_t n[3];          /* nodes per axis, each >= 2 */
+    int32_t dtype;         /* LSDF_F32 (LSDF_BF16 / LSDF_F16 reserved) */
+    int64_t elem_offset;   /* >= 0, in elements of `dtype` */
+} lsdf_grid;
+
+/* One joint of a standard (distal) Denavit-Hartenberg chain: frame k is
+ * frame k-1 moved by Rz(q_k + theta_offset) Tz(d) Tx(a) Rx(alpha). */
+typedef struct lsdf_dh {
+    float a;
+    float alpha;
+    float d;
+    float theta_offset;
+} lsdf_dh;
+
+/* Library version, (major << 16) | (minor << 8) | patch. */
+int lsdf_version(void);
+
+/* Message describing the last failed call on this thread ("" if none).  The
+ * pointer stays valid until the next library call on the same thread. */
+const char* lsdf_last_error(void);
+
+/* ---- forward kinematics ----------------------------------------------------
+ * Sec. III-A: the transformations T_{i,c} of every link i at every
+ * configuration c, by forward kinematics run in parallel over c.
+ *   dh      host [dof] joint parameters, 1 <= dof <= LSDF_MAX_DOF
+ *   base_T  host [3][4] pose of link 0 (the fixed base), or NULL = identity
+ *   q       device float [C][dof] joint angles (radians)
+ *   link_T  device float [C][dof+1][3][4] output; link 0 is base_T, link k
+ *           (1 <= k <= dof) is the frame after joint k
+ * C = 0 enqueues nothing.  Computed in FP32. */
+int lsdf_fk_batch(const lsdf_dh* dh, int32_t dof, const float* base_T,
+                  const float* q, int32_t C, float* link_T, void* stream);
+
+/* ---- clearance query -------------------------------------------------------
+ * Sec. III-A: per configuration c, the minimum over obstacle points x_j and
+ * links i of g_i(R_{i,c}^T (x_j - t_{i,c})), where g_i is the trilinear
+ * interpolant of link i's grid inside its box and +infinity outside it.
+ *   link_T        device float [C][L][3][4] link poses (e.g. from lsdf_fk_batch)
+ *   grids         host [L] grid descriptors, 1 <= L <= LSDF_MAX_LINKS
+ *   grid_buf      device buffer holding every link's grid
+ *   points        device float [M][3] obstacle points (world frame)
+ *   out_dist      device float [C]: the clearance (+inf when no point lies in
+ *                 any link's box)
+ *   out_link      device int32 [C]: lowest link index attaining out_dist, -1
+ *                 when out_dist is +inf
+ *   out_link_dist device float [C][L] per-link minima, or NULL
+ *   flags         must be 0
+ *   workspace     device scratch of at least lsdf_query_workspace_size()
+ *                 bytes, 256-byte aligned, ZERO-FILLED before its first use
+ *                 and not written by the caller afterwards: every call
+ *                 returns it to all-zero when it completes.  Calls that share
+ *                 a workspace must not overlap in time (same stream is fine).
+ * -0 is returned as +0.  M = 0 gives (+inf, -1) everywhere; C = 0 enqueues
+ * nothing.  The arithmetic is FP32 in a fixed operation order (per link and
+ * configuration the world-to-grid map is formed once as one affine matrix,
+ * the form of Eq. 4; the lerp is fma(f, b, fma(-f, a, a))), so results are
+ * reproducible bit for bit. */
+int lsdf_query_workspace_size(int32_t C, int32_t L, int64_t M, size_t* bytes);
+
+int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L,
+                            const lsdf_grid* grids, const void* grid_buf,
+                            const float* points, int64_t M,
+                            float* out_dist, int32_t* out_link, float* out_link_dist,
+                            uint32_t flags, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- link SDF construction -------------------------------------------------
+ * Sec. III-A: "we pre-compute Signed Distance Fields for each link on its
+ * local coordinates" (the construction method is not given; this one is a
+ * brute-force exact signed distance to a closed triangle mesh).
+ *   verts       device float [nv][3] vertices in the link frame
+ *   tris        device int32 [nt][3] triangles, outward (counter-clockwise)
+ *   comp_first  host int32 [ncomp+1]: triangles [comp_first[k],
+ *               comp_first[k+1]) form closed part k; NULL = one part of all
+ *               nt triangles.  The link's distance is the minimum over parts.
+ *   desc        host descriptor of the grid to fill (dtype LSDF_F32)
+ *   grid_buf    device buffer; nodes are written at desc->elem_offset
+ * Inside/outside is decided by the generalised winding number of each part
+ * (negative inside). */
+int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* tris, int32_t nt,
+                        const int32_t* comp_first, int32_t ncomp, const lsdf_grid* desc,
+                        void* grid_buf, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSDF_H */

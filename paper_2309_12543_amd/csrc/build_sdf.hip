@@ -1,0 +1,175 @@
+// Link SDF construction (Sec. III-A: per-link signed distance fields
+// precomputed on the link's local grid).  Brute force: every node visits
+// every triangle of every closed part of the link mesh.
+//   * unsigned distance: closest point on a triangle by the Voronoi-region
+//     walk of Ericson, Real-Time Collision Detection (2005), Sec. 5.1.5;
+//   * inside/outside: generalised winding number (Jacobson et al. 2013), the
+//     sum of signed solid angles (Van Oosterom & Strackee 1983) over 4 pi;
+//   * a link made of several closed parts takes the minimum over parts.
+// One lane per node; triangles are staged through LDS in chunks.
+#include "lsdf_internal.hpp"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+struct BuildArgs {
+    int32_t comp_first[LSDF_MAX_COMPONENTS + 1];
+    float lo[3];
+    float h[3];
+    int32_t n[3];
+    int32_t ncomp;
+    int32_t nv;
+    const float* verts;
+    const int32_t* tris;
+    float* out;
+};
+
+struct V3 {
+    float x, y, z;
+};
+__device__ inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+__device__ inline V3 axpy(float s, V3 d, V3 o) { return {o.x + s * d.x, o.y + s * d.y, o.z + s * d.z}; }
+
+// Squared distance from p to triangle (a, b, c), by the Voronoi regions of
+// its vertices, edges and face.
+__device__ float dist2_point_triangle(V3 p, V3 a, V3 b, V3 c) {
+    const V3 ab = sub(b, a), ac = sub(c, a), ap = sub(p, a);
+    const float d1 = dot(ab, ap), d2 = dot(ac, ap);
+    V3 q;
+    if (d1 <= 0.0f && d2 <= 0.0f) {
+        q = a;
+    } else {
+        const V3 bp = sub(p, b);
+        const float d3 = dot(ab, bp), d4 = dot(ac, bp);
+        const V3 cp = sub(p, c);
+        const float d5 = dot(ab, cp), d6 = dot(ac, cp);
+        const float vc = d1 * d4 - d3 * d2;
+        const float vb = d5 * d2 - d1 * d6;
+        const float va = d3 * d6 - d5 * d4;
+        if (d3 >= 0.0f && d4 <= d3) {
+            q = b;
+        } else if (vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f) {
+            q = axpy(d1 / (d1 - d3), ab, a);
+        } else if (d6 >= 0.0f && d5 <= d6) {
+            q = c;
+        } else if (vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f) {
+            q = axpy(d2 / (d2 - d6), ac, a);
+        } else if (va <= 0.0f && (d4 - d3) >= 0.0f && (d5 - d6) >= 0.0f) {
+            q = axpy((d4 - d3) / ((d4 - d3) + (d5 - d6)), sub(c, b), b);
+        } else {
+            const float s = va + vb + vc;
+            if (s > 0.0f) {
+                const float inv = 1.0f / s;
+                q = axpy(vc * inv, ac, axpy(vb * inv, ab, a));
+            } else {
+                q = a;   // degenerate triangle: its edges were already tried
+            }
+        }
+    }
+    const V3 d = sub(p, q);
+    return dot(d, d);
+}
+
+// Signed solid angle of triangle (a, b, c) seen from p:
+// tan(Omega/2) = det[A B C] / (|A||B||C| + (A.B)|C| + (A.C)|B| + (B.C)|A|).
+__device__ float solid_angle(V3 p, V3 a, V3 b, V3 c) {
+    const V3 A = sub(a, p), B = sub(b, p), C = sub(c, p);
+    const float det = dot(A, cross(B, C));
+    const float la = sqrtf(dot(A, A)), lb = sqrtf(dot(B, B)), lc = sqrtf(dot(C, C));
+    const float den = la * lb * lc + dot(A, B) * lc + dot(A, C) * lb + dot(B, C) * la;
+    return 2.0f * atan2f(det, den);
+}
+
+__global__ __launch_bounds__(kBlock) void build_sdf_kernel(BuildArgs p) {
+    __shared__ float s_tri[kBlock][9];
+    const int64_t nodes = (int64_t)p.n[0] * p.n[1] * p.n[2];
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool active = idx < nodes;
+    const int64_t kx = idx % p.n[0];
+    const int64_t ky = (idx / p.n[0]) % p.n[1];
+    const int64_t kz = idx / ((int64_t)p.n[0] * p.n[1]);
+    const V3 pt = {fmaf((float)kx, p.h[0], p.lo[0]), fmaf((float)ky, p.h[1], p.lo[1]),
+                   fmaf((float)kz, p.h[2], p.lo[2])};
+    float sdf = INFINITY;
+    for (int comp = 0; comp < p.ncomp; ++comp) {
+        const int t0 = p.comp_first[comp], t1 = p.comp_first[comp + 1];
+        float best2 = INFINITY;
+        float omega = 0.0f;
+        for (int base = t0; base < t1; base += kBlock) {
+            __syncthreads();
+            const int t = base + threadIdx.x;
+            if (t < t1) {
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    // vertex indices clamped into range: a bad mesh gives a
+                    // wrong grid, never an out-of-bounds read
+                    const int vi = min(max(p.tris[3 * t + v], 0), p.nv - 1);
+                    s_tri[threadIdx.x][3 * v + 0] = p.verts[3 * vi + 0];
+                    s_tri[threadIdx.x][3 * v + 1] = p.verts[3 * vi + 1];
+                    s_tri[threadIdx.x][3 * v + 2] = p.verts[3 * vi + 2];
+                }
+            }
+            __syncthreads();
+            const int cnt = min(kBlock, t1 - base);
+            for (int k = 0; k < cnt; ++k) {
+                const V3 a = {s_tri[k][0], s_tri[k][1], s_tri[k][2]};
+                const V3 b = {s_tri[k][3], s_tri[k][4], s_tri[k][5]};
+                const V3 c = {s_tri[k][6], s_tri[k][7], s_tri[k][8]};
+                best2 = fminf(best2, dist2_point_triangle(pt, a, b, c));
+                omega += solid_angle(pt, a, b, c);
+            }
+        }
+        const float u = sqrtf(best2);
+        const float winding = omega * (float)(0.25 / M_PI);
+        sdf = fminf(sdf, winding > 0.5f ? -u : u);
+    }
+    if (active) p.out[idx] = sdf;
+}
+
+}  // namespace
+
+LSDF_API int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* tris, int32_t nt,
+                                 const int32_t* comp_first, int32_t ncomp, const lsdf_grid* desc,
+                                 void* grid_buf, void* stream) {
+    using namespace lsdf;
+    clear_error();
+    if (!desc) return fail(LSDF_E_INVALID_ARG, "build_link_sdf: desc is NULL");
+    if (nv < 1 || nt < 1) return fail(LSDF_E_SHAPE, "build_link_sdf: empty mesh (nv = %d, nt = %d)", (int)nv, (int)nt);
+    if (!verts || !tris || !grid_buf) return fail(LSDF_E_INVALID_ARG, "build_link_sdf: NULL device pointer");
+    BuildArgs p{};
+    if (comp_first) {
+        if (ncomp < 1 || ncomp > LSDF_MAX_COMPONENTS)
+            return fail(LSDF_E_SHAPE, "build_link_sdf: ncomp = %d out of [1, %d]", (int)ncomp, LSDF_MAX_COMPONENTS);
+        if (comp_first[0] != 0 || comp_first[ncomp] != nt)
+            return fail(LSDF_E_SHAPE, "build_link_sdf: comp_first must run from 0 to nt");
+        for (int k = 0; k <= ncomp; ++k) {
+            if (k > 0 && comp_first[k] <= comp_first[k - 1])
+                return fail(LSDF_E_SHAPE, "build_link_sdf: comp_first must increase strictly");
+            p.comp_first[k] = comp_first[k];
+        }
+        p.ncomp = ncomp;
+    } else {
+        p.comp_first[0] = 0;
+        p.comp_first[1] = nt;
+        p.ncomp = 1;
+    }
+    LinkGrid g;
+    int rc = prepare_link_grid(*desc, 0, &g);
+    if (rc != LSDF_OK) return rc;
+    for (int a = 0; a < 3; ++a) {
+        p.lo[a] = desc->lo[a];
+        p.h[a] = (float)(((double)desc->hi[a] - (double)desc->lo[a]) / (double)(desc->n[a] - 1));
+        p.n[a] = desc->n[a];
+    }
+    p.nv = nv;
+    p.verts = verts;
+    p.tris = tris;
+    p.out = static_cast<float*>(grid_buf) + desc->elem_offset;
+    const int64_t nodes = (int64_t)p.n[0] * p.n[1] * p.n[2];
+    hipLaunchKernelGGL(build_sdf_kernel, dim3((unsigned)((nodes + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       as_stream(stream), p);
+    return check_launch("build_link_sdf");
+}

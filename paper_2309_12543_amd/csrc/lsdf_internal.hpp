@@ -1,0 +1,61 @@
+// Internal helpers shared by the HIP translation units of liblsdf.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "lsdf.h"
+
+#define LSDF_API extern "C" __attribute__((visibility("default")))
+
+namespace lsdf {
+
+// Thread-local message of the last failure (lsdf_last_error).
+void clear_error();
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+inline int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LSDF_E_DEVICE, "%s: launch failed: %s", what, hipGetErrorString(e));
+    return LSDF_OK;
+}
+
+inline bool finite3(const float* v) {
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---- order-preserving float <-> uint32 map ----------------------------------
+// ordered(a) < ordered(b) iff a < b for non-NaN floats (-0 below +0; callers
+// canonicalise -0 to +0 first).  Keys in the query workspace are stored
+// complemented (~ordered) so that an all-zero workspace means "empty" and the
+// combining operation is an unsigned atomic max.
+__device__ inline uint32_t ordered_bits(float v) {
+    uint32_t b = __float_as_uint(v);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ inline float from_ordered_bits(uint32_t o) {
+    uint32_t b = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    return __uint_as_float(b);
+}
+
+// Per-link constants of the world-to-grid map, fixed on the host from the
+// grid descriptor in double and rounded once to float.
+struct LinkGrid {
+    float invh[3];   // (n_a - 1) / (hi_a - lo_a)
+    float nlo[3];    // -lo_a * invh_a
+    float umax[3];   // n_a - 1
+    int32_t n[3];
+    int32_t dtype;
+    int64_t offset;  // element offset into the grid buffer
+};
+
+int prepare_link_grid(const lsdf_grid& g, int index, LinkGrid* out);
+
+}  // namespace lsdf

@@ -1,0 +1,244 @@
+"""GPU parity of the clearance path (fk_batch, build_link_sdf,
+query_min_distance) against the CPU oracle, through the C ABI.
+
+* query stage: bit-exact against the oracle's single-precision twin when both
+  get the same FP32 poses and grids (out_dist, out_link and the per-link
+  minima, +inf patterns included);
+* fk_batch: within 5e-6 of the oracle's double-precision kinematics;
+* build_link_sdf: within 2e-6 m of the oracle's double-precision grid;
+* end to end (GPU kinematics, GPU grids, GPU query) against the all-double
+  oracle: within 1e-5 m, argmin equal outside near-ties.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_E2E = 1e-5        # metres, FP32 end to end vs the double oracle
+TIE = 2e-5            # link minima closer than this count as a tie
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_12543_amd import lsdf
+    lsdf.load_library()
+    return lsdf
+
+
+@pytest.fixture(scope="module")
+def paper():
+    return synth.make_workload("paper")
+
+
+@pytest.fixture(scope="module")
+def paper_grids(orc, paper):
+    return orc.workload_grids(paper)
+
+
+def upload_grids(B, w, grids64):
+    gs = B.GridSet(w.grid_lo, w.grid_hi, w.grid_n, device="cuda")
+    for i, g in enumerate(grids64):
+        gs.set_grid(i, g.astype(np.float32))
+    return gs
+
+
+def to_dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def run_query(B, T32, gs, pts32, link_dist=True):
+    say("query C=%d L=%d M=%d" % (T32.shape[0], T32.shape[1], pts32.shape[0]))
+    d, l, ld = B.query_min_distance(to_dev(T32), gs, to_dev(pts32.reshape(-1, 3)), link_dist=True)
+    torch.cuda.synchronize()
+    return d.cpu().numpy(), l.cpu().numpy(), ld.cpu().numpy()
+
+
+def twin(orc, w, T32, grids64, pts32):
+    cl = orc.query_f32(T32, w.grid_lo, w.grid_hi, w.grid_n, [g.astype(np.float32) for g in grids64], pts32)
+    d, l = orc.reduce(cl)
+    return d, l, cl
+
+
+def assert_bit_exact(gpu, ref):
+    gd, gl, gld = gpu
+    rd, rl, rcl = ref
+    assert np.array_equal(gld.view(np.uint32), rcl.view(np.uint32)), \
+        f"per-link minima differ at {np.argwhere(gld.view(np.uint32) != rcl.view(np.uint32))[:5]}"
+    assert np.array_equal(gd.view(np.uint32), rd.view(np.uint32))
+    assert np.array_equal(gl, rl)
+
+
+# ---------------------------------------------------------------------------
+# kinematics
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["tiny", "paper"])
+def test_fk_batch_matches_oracle(B, orc, name):
+    w = synth.make_workload(name)
+    rng = np.random.default_rng(30)
+    base = np.concatenate([np.linalg.qr(rng.normal(size=(3, 3)))[0] * [1, 1, 1], rng.normal(size=(3, 1)) * 0.2], 1)
+    if np.linalg.det(base[:, :3]) < 0:
+        base[:, 0] *= -1
+    for b in (None, base):
+        say("fk_batch", name, "C=%d" % w.C, "base" if b is not None else "identity")
+        T = B.fk_batch(w.robot.dh, to_dev(w.q), base_T=b)
+        torch.cuda.synchronize()
+        ref = orc.fk(w.robot.dh, w.q, b)
+        err = np.abs(T.cpu().numpy().astype(np.float64) - ref)
+        assert err[..., 3].max() < 5e-6, err[..., 3].max()      # metres
+        assert err[..., :3].max() < 5e-6, err[..., :3].max()    # rotation entries
+
+
+def test_fk_batch_ragged_and_empty(B, orc, tiny):
+    for C in (1, 63, 65, 257):
+        q = tiny.q[np.arange(C) % tiny.C]
+        T = B.fk_batch(tiny.robot.dh, to_dev(q))
+        torch.cuda.synchronize()
+        assert np.abs(T.cpu().numpy() - orc.fk(tiny.robot.dh, q)).max() < 5e-6
+    T = B.fk_batch(tiny.robot.dh, torch.zeros((0, 6), dtype=torch.float32, device="cuda"))
+    assert T.shape == (0, 7, 3, 4)
+
+
+# ---------------------------------------------------------------------------
+# query stage: bit-exact against the single-precision twin
+# ---------------------------------------------------------------------------
+
+def test_query_bit_exact_tiny(B, orc, tiny, tiny_grids):
+    T32 = orc.fk(tiny.robot.dh, tiny.q, tiny.robot.base_T).astype(np.float32)
+    gs = upload_grids(B, tiny, tiny_grids)
+    pts = tiny.points.astype(np.float32)
+    assert_bit_exact(run_query(B, T32, gs, pts), twin(orc, tiny, T32, tiny_grids, pts))
+
+
+@pytest.mark.parametrize("C,M", [(37, 5000), (1, 1), (3, 2049), (129, 16385), (5, 0)])
+def test_query_bit_exact_ragged(B, orc, tiny, tiny_grids, C, M):
+    """Several point tiles with a ragged tail, ragged configuration tiles,
+    a single point, and the empty cloud."""
+    rng = np.random.default_rng(31 + C)
+    q = synth.make_waypoints(tiny.robot.qmin, tiny.robot.qmax, C, 99 + C)
+    T32 = orc.fk(tiny.robot.dh, q, tiny.robot.base_T).astype(np.float32)
+    # points near the arm, so that most links see some of them
+    origins = T32[:, :, :, 3].reshape(-1, 3).astype(np.float64)
+    pts = (origins[rng.integers(0, origins.shape[0], M)] + rng.normal(0, 0.15, size=(M, 3))).astype(np.float32)
+    gs = upload_grids(B, tiny, tiny_grids)
+    gpu = run_query(B, T32, gs, pts)
+    ref = twin(orc, tiny, T32, tiny_grids, pts)
+    assert_bit_exact(gpu, ref)
+    if M == 0:
+        assert np.all(gpu[0] == np.inf) and np.all(gpu[1] == -1)
+    elif M > 100:
+        assert np.isfinite(gpu[2]).mean() > 0.3
+
+
+def test_query_bit_exact_paper_scale(B, orc, paper, paper_grids):
+    """500 waypoints x 20,000 points x 7 links, 64^3 grids: the full size, in
+    the launch configuration the benchmark times."""
+    T32 = orc.fk(paper.robot.dh, paper.q, paper.robot.base_T).astype(np.float32)
+    gs = upload_grids(B, paper, paper_grids)
+    pts = paper.points.astype(np.float32)
+    gpu = run_query(B, T32, gs, pts)
+    ref = twin(orc, paper, T32, paper_grids, pts)
+    assert_bit_exact(gpu, ref)
+    assert np.isfinite(gpu[0]).mean() > 0.5
+
+
+def test_query_sixteen_links_and_one_link(B, orc, tiny, tiny_grids):
+    T = orc.fk(tiny.robot.dh, tiny.q, tiny.robot.base_T).astype(np.float32)
+    pts = tiny.points.astype(np.float32)
+    # 16 links: the 7 real ones repeated; ties must resolve to the lowest index
+    idx = np.arange(16) % 7
+    w16 = synth.Workload("t16", tiny.robot, tiny.q, tiny.points, tiny.grid_lo[idx], tiny.grid_hi[idx],
+                         tiny.grid_n[idx], {})
+    g16 = [tiny_grids[i] for i in idx]
+    gs = upload_grids(B, w16, g16)
+    gpu = run_query(B, np.ascontiguousarray(T[:, idx]), gs, pts)
+    ref = twin(orc, w16, np.ascontiguousarray(T[:, idx]), g16, pts)
+    assert_bit_exact(gpu, ref)
+    assert np.all(gpu[1] < 7)
+    w1 = synth.Workload("t1", tiny.robot, tiny.q, tiny.points, tiny.grid_lo[3:4], tiny.grid_hi[3:4],
+                        tiny.grid_n[3:4], {})
+    gs1 = upload_grids(B, w1, tiny_grids[3:4])
+    assert_bit_exact(run_query(B, np.ascontiguousarray(T[:, 3:4]), gs1, pts),
+                     twin(orc, w1, np.ascontiguousarray(T[:, 3:4]), tiny_grids[3:4], pts))
+
+
+def test_query_workspace_cleared_and_repeatable(B, orc, tiny, tiny_grids):
+    T32 = to_dev(orc.fk(tiny.robot.dh, tiny.q, tiny.robot.base_T).astype(np.float32))
+    gs = upload_grids(B, tiny, tiny_grids)
+    pts = to_dev(tiny.points.astype(np.float32))
+    ws = torch.zeros(B.query_workspace_size(tiny.C, 7, tiny.M), dtype=torch.uint8, device="cuda")
+    say("query repeat x3 with a private workspace")
+    outs = [B.query_min_distance(T32, gs, pts, link_dist=True, workspace=ws) for _ in range(3)]
+    torch.cuda.synchronize()
+    assert int(ws.count_nonzero()) == 0
+    for d, l, ld in outs[1:]:
+        assert torch.equal(d, outs[0][0]) and torch.equal(l, outs[0][1]) and torch.equal(ld, outs[0][2])
+    # permuting the cloud changes nothing, bit for bit
+    perm = torch.as_tensor(np.random.default_rng(32).permutation(tiny.M), device="cuda")
+    d2, l2, ld2 = B.query_min_distance(T32, gs, pts[perm].contiguous(), link_dist=True, workspace=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(ld2, outs[0][2]) and torch.equal(l2, outs[0][1])
+
+
+# ---------------------------------------------------------------------------
+# grid construction and the whole path
+# ---------------------------------------------------------------------------
+
+def test_build_link_sdf_matches_oracle(B, orc, tiny, tiny_grids):
+    say("build_link_sdf tiny, 7 links of 32^3")
+    gs = B.build_robot_grids(tiny.robot.links, tiny.grid_lo, tiny.grid_hi, tiny.grid_n)
+    torch.cuda.synchronize()
+    for i in range(tiny.L):
+        got = gs.grid(i).cpu().numpy().astype(np.float64)
+        err = np.abs(got - tiny_grids[i])
+        assert err.max() < 2e-6, (i, err.max())
+
+
+def face_min(grid):
+    return min(grid[0].min(), grid[-1].min(), grid[:, 0].min(), grid[:, -1].min(), grid[:, :, 0].min(),
+               grid[:, :, -1].min())
+
+
+@pytest.mark.parametrize("name", ["tiny", "paper"])
+def test_end_to_end_vs_double_oracle(B, orc, name, tiny_grids, paper_grids):
+    w = synth.make_workload(name)
+    grids64 = tiny_grids if name == "tiny" else paper_grids
+    say("end-to-end", name, "C=%d M=%d" % (w.C, w.M))
+    gs = B.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n)
+    T = B.fk_batch(w.robot.dh, to_dev(w.q), base_T=w.robot.base_T)
+    d, l, ld = B.query_min_distance(T, gs, to_dev(w.points), link_dist=True)
+    torch.cuda.synchronize()
+    d, l, ld = d.cpu().numpy().astype(np.float64), l.cpu().numpy(), ld.cpu().numpy().astype(np.float64)
+    T64 = orc.fk(w.robot.dh, w.q, w.robot.base_T)
+    cl = orc.query_f64(T64, w.grid_lo, w.grid_hi, w.grid_n, grids64, w.points)
+    rd, rl = orc.reduce(cl)
+    # A point lying within rounding of a box face can be in the box in one
+    # precision and out of it in the other (out-of-box counts as +inf).  Such
+    # a point's value is at least the smallest value on that box's faces, so
+    # a disagreement is only allowed above that band.
+    band = np.array([face_min(g) for g in grids64]) - TOL_E2E
+    same = (ld == cl) | (np.abs(ld - cl) <= TOL_E2E)
+    boundary = np.minimum(ld, cl) >= band[None, :]
+    assert np.all(same | boundary), np.argwhere(~(same | boundary))[:5]
+    dsame = (d == rd) | (np.abs(d - rd) <= TOL_E2E)
+    assert np.all(dsame | (np.minimum(d, rd) >= band.min()))
+    fin = np.isfinite(rd) & dsame
+    say("end-to-end max |d - d_oracle| = %.3g m over %d waypoints, %d outside the band rule" %
+        (np.max(np.abs(d[fin] - rd[fin])) if fin.any() else 0.0, fin.sum(), (~dsame).sum()))
+    # argmin: exact unless the oracle's two best links are within TIE
+    srt = np.sort(cl, axis=1)
+    clear = (srt[:, 1] - srt[:, 0] > TIE) & dsame & np.isfinite(rd)
+    assert np.array_equal(l[clear], rl[clear])
+    amb = dsame & np.isfinite(rd) & ~clear
+    for c in np.flatnonzero(amb):
+        assert cl[c, l[c]] <= rd[c] + TIE
+    assert np.all((l == -1) == ~np.isfinite(d))
