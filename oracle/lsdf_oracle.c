@@ -336,15 +336,17 @@ ORC_EXPORT void orc_reduce_f64(const double* cl, int32_t C, int32_t L, double* d
 /* Single-precision twin of the query.  Every operation is one IEEE binary32 */
 /* operation in a fixed order, so that the argmin decision is taken in the   */
 /* same precision as the GPU kernel:                                         */
-/*   per axis a: invh_a = (float)((n_a-1) / (hi_a - lo_a))  [double, 1 round] */
-/*               nlo_a  = (float)(-lo_a * invh_a)            [double, 1 round] */
-/*   per (c, i): the world-to-grid affine map of the inverse pose, as one     */
-/*     homogeneous matrix (the form of paper Eq. 4):                          */
+/*   per axis a (double, rounded once):                                       */
+/*     invh_a = (float)((n_a - 1) / (hi_a - lo_a)),  half_a = (n_a - 1) / 2    */
+/*     cen_a  = (float)(-lo_a * invh_a - half_a)                              */
+/*   per (c, i): the world-to-grid map of the inverse pose as one homogeneous */
+/*     matrix (the form of paper Eq. 4), centred on the box:                  */
 /*       M[a][b] = invh_a * R[b][a]                                           */
 /*       w_a = fma(-invh_a, fma(R[0][a], t0, fma(R[1][a], t1, R[2][a]*t2)),   */
-/*                 nlo_a)                                                     */
-/*   per point: u_a = fma(M[a][0], x, fma(M[a][1], y, fma(M[a][2], z, w_a)))  */
-/*     inside iff 0 <= u_a <= n_a - 1 for every a                             */
+/*                 cen_a)                                                     */
+/*   per point: v_a = fma(M[a][0], x, fma(M[a][1], y, fma(M[a][2], z, w_a)))  */
+/*     inside iff |v_a| <= half_a for every a                                 */
+/*     u_a = v_a + half_a (lies in [0, n_a - 1])                              */
 /*     i_a = min(floor(u_a), n_a - 2), f_a = u_a - i_a (exact)               */
 /*     lerp(p, q, f) = fma(f, q, fma(-f, p, p)) (exact at f = 0 and f = 1):   */
 /*     four along x, two along y, one along z                                 */
@@ -361,33 +363,35 @@ ORC_EXPORT void orc_query_f32(const float* T, int32_t C, int32_t L, const float*
             const float* Ti = T + ((int64_t)c * L + i) * 12;
             const int32_t* n_i = n + 3 * i;
             const float* G = grids + offs[i];
-            float invh[3], nlo[3], Mx[3][3], w[3];
+            float invh[3], half[3], cen[3], Mx[3][3], w[3];
             for (int a = 0; a < 3; ++a) {
                 invh[a] = (float)((double)(n_i[a] - 1) / ((double)hi[3 * i + a] - (double)lo[3 * i + a]));
-                nlo[a] = (float)(-(double)lo[3 * i + a] * (double)invh[a]);
+                half[a] = 0.5f * (float)(n_i[a] - 1);
+                cen[a] = (float)(-(double)lo[3 * i + a] * (double)invh[a] - (double)half[a]);
             }
             for (int a = 0; a < 3; ++a) {
                 for (int b = 0; b < 3; ++b) Mx[a][b] = invh[a] * Ti[4 * b + a];
                 float rt = fmaf(Ti[0 + a], Ti[3], fmaf(Ti[4 + a], Ti[7], Ti[8 + a] * Ti[11]));
-                w[a] = fmaf(-invh[a], rt, nlo[a]);
+                w[a] = fmaf(-invh[a], rt, cen[a]);
             }
             float best = INFINITY;
             for (int64_t j = 0; j < M; ++j) {
                 float x = P[3 * j], y = P[3 * j + 1], z = P[3 * j + 2];
-                float u[3];
+                float v[3];
                 int inside = 1;
                 for (int a = 0; a < 3; ++a) {
-                    u[a] = fmaf(Mx[a][0], x, fmaf(Mx[a][1], y, fmaf(Mx[a][2], z, w[a])));
-                    if (!(u[a] >= 0.0f && u[a] <= (float)(n_i[a] - 1))) inside = 0;
+                    v[a] = fmaf(Mx[a][0], x, fmaf(Mx[a][1], y, fmaf(Mx[a][2], z, w[a])));
+                    if (!(fabsf(v[a]) <= half[a])) inside = 0;
                 }
                 if (!inside) continue;
                 int64_t k[3];
                 float f[3];
                 for (int a = 0; a < 3; ++a) {
-                    int64_t q = (int64_t)floorf(u[a]);
+                    float u = v[a] + half[a];
+                    int64_t q = (int64_t)floorf(u);
                     if (q > n_i[a] - 2) q = n_i[a] - 2;
                     k[a] = q;
-                    f[a] = u[a] - (float)q;
+                    f[a] = u - (float)q;
                 }
                 const int64_t nx = n_i[0], ny = n_i[1];
 #define GV(dx, dy, dz) G[((k[2] + (dz)) * ny + (k[1] + (dy))) * nx + (k[0] + (dx))]
@@ -398,8 +402,8 @@ ORC_EXPORT void orc_query_f32(const float* T, int32_t C, int32_t L, const float*
 #undef GV
                 float e0 = lerpf_(e00, e10, f[1]);
                 float e1 = lerpf_(e01, e11, f[1]);
-                float v = lerpf_(e0, e1, f[2]) + 0.0f;
-                if (v < best) best = v;
+                float val = lerpf_(e0, e1, f[2]) + 0.0f;
+                if (val < best) best = val;
             }
             out[(int64_t)c * L + i] = best;
         }

@@ -26,19 +26,21 @@ int prepare_link_grid(const lsdf_grid& g, int index, LinkGrid* out) {
         return fail(LSDF_E_UNSUPPORTED, "grid %d: unsupported dtype %d", index, (int)g.dtype);
     if (g.elem_offset < 0) return fail(LSDF_E_INVALID_ARG, "grid %d: negative elem_offset", index);
     for (int a = 0; a < 3; ++a) {
-        if (g.n[a] < 2) return fail(LSDF_E_SHAPE, "grid %d: n[%d] = %d < 2", index, a, (int)g.n[a]);
+        if (g.n[a] < 2 || g.n[a] > (1 << 24))
+            return fail(LSDF_E_SHAPE, "grid %d: n[%d] = %d out of [2, 2^24]", index, a, (int)g.n[a]);
         if (!(g.hi[a] > g.lo[a])) return fail(LSDF_E_INVALID_ARG, "grid %d: hi[%d] <= lo[%d]", index, a, a);
     }
     if ((int64_t)g.n[0] * g.n[1] * g.n[2] > (int64_t)1 << 31)
         return fail(LSDF_E_SHAPE, "grid %d: more than 2^31 nodes", index);
     for (int a = 0; a < 3; ++a) {
         // fixed once in double from the float box, rounded once to float
-        double invh = (double)(g.n[a] - 1) / ((double)g.hi[a] - (double)g.lo[a]);
+        const double invh = (double)(g.n[a] - 1) / ((double)g.hi[a] - (double)g.lo[a]);
         out->invh[a] = (float)invh;
-        out->nlo[a] = (float)(-(double)g.lo[a] * (double)out->invh[a]);
-        out->umax[a] = (float)(g.n[a] - 1);
+        out->half[a] = 0.5f * (float)(g.n[a] - 1);
+        out->cen[a] = (float)(-(double)g.lo[a] * (double)out->invh[a] - (double)out->half[a]);
         out->n[a] = g.n[a];
     }
+    out->cubic = (g.n[0] == g.n[1] && g.n[1] == g.n[2]) ? 1 : 0;
     out->dtype = g.dtype;
     out->offset = g.elem_offset;
     return LSDF_OK;

@@ -46,13 +46,15 @@ __device__ inline float from_ordered_bits(uint32_t o) {
 }
 
 // Per-link constants of the world-to-grid map, fixed on the host from the
-// grid descriptor in double and rounded once to float.
+// grid descriptor in double and rounded once to float.  Grid coordinates are
+// centred on the box: v_a = u_a - half_a, inside iff |v_a| <= half_a.
 struct LinkGrid {
     float invh[3];   // (n_a - 1) / (hi_a - lo_a)
-    float nlo[3];    // -lo_a * invh_a
-    float umax[3];   // n_a - 1
+    float cen[3];    // -lo_a * invh_a - half_a
+    float half[3];   // (n_a - 1) / 2
     int32_t n[3];
     int32_t dtype;
+    int32_t cubic;   // n_x == n_y == n_z
     int64_t offset;  // element offset into the grid buffer
 };
 

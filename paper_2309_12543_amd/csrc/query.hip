@@ -2,19 +2,27 @@
 // obstacle points and links of link i's grid SDF read at the point moved into
 // link i's frame.
 //
-// One launch does the whole query:
-//   * a block owns a tile of CT configurations (all L links) and a tile of
-//     256*K points; each lane keeps its K points in registers;
-//   * the block forms the world-to-grid affine map of each of its
-//     (configuration, link) pairs once, in LDS (the inverse pose of Eq. 4 with
-//     the grid scaling folded in);
-//   * for every pair a lane maps its points (9 FMAs each), tests the box and
-//     gathers + interpolates only inside it; a wave-wide min and an LDS
-//     combine across the 4 waves leave one value per pair and block;
-//   * blocks merge per-pair minima with one unsigned atomic max on a
-//     complemented order-preserving key in the workspace;
-//   * the last block to finish (atomic ticket) turns the keys into the
-//     outputs and clears them, leaving the workspace all-zero again.
+// Work layout:
+//   * a wave owns one link i and 64 consecutive configurations (one per
+//     lane); each lane holds the world-to-grid affine map of its pose (the
+//     inverse pose of Eq. 4 with the grid scaling folded in) in 12 VGPRs;
+//   * obstacle points are wave-uniform: they stream through scalar loads into
+//     SGPRs, so mapping a point is 9 FMAs with no cross-lane traffic, and the
+//     per-pair minimum stays in one register per lane;
+//   * the box test is one max3 of absolute centred coordinates; lanes inside
+//     their box gather 8 corners and interpolate, with the loads of a batch
+//     of points issued together so that one wait covers them all;
+//   * the iteration space (link, 64-configuration group, point) is cut into
+//     chunks of 64 points; each XCD (blocks b = x mod 8) takes a contiguous
+//     slice of chunks, which keeps it on one or two links' grids in its L2,
+//     and deals its slice round-robin to its waves, which spreads dense
+//     regions of the cloud over many waves;
+//   * per-pair minima merge across waves with one unsigned atomic max on a
+//     complemented order-preserving key; a second small kernel turns the
+//     keys into the outputs and clears them, leaving the workspace zero (the
+//     kernel boundary orders it after every atomic, with no device fence).
+#include <algorithm>
+
 #include "lsdf_internal.hpp"
 
 namespace {
@@ -22,172 +30,227 @@ namespace {
 using lsdf::LinkGrid;
 
 constexpr int kBlock = 256;
-constexpr int kWaves = kBlock / 64;
-constexpr size_t kWsHeader = 256;   // ticket counter lives in the first bytes
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kXcds = 8;
+constexpr float kFar = 1e30f;       // centred coordinate of unused lanes: never inside
+constexpr int kBlocksPerCu = 8;
+
+#ifndef LSDF_QUERY_UNROLL
+#define LSDF_QUERY_UNROLL 8         // points per any-inside test
+#endif
+#ifndef LSDF_QUERY_GATHER
+#define LSDF_QUERY_GATHER 4         // points whose gathers are in flight together
+#endif
+#ifndef LSDF_QUERY_CHUNK
+#define LSDF_QUERY_CHUNK 32         // points per work chunk
+#endif
+constexpr int kUnroll = LSDF_QUERY_UNROLL;
+constexpr int kGather = LSDF_QUERY_GATHER;
+constexpr int kChunk = LSDF_QUERY_CHUNK;
+static_assert(kUnroll % kGather == 0, "gather batch must divide the unroll");
 
 struct QueryArgs {
     LinkGrid link[LSDF_MAX_LINKS];
     const float* link_T;
-    const float* grid;
-    const float* points;
+    uint32_t* keys;      // [C][L] complemented ordered keys, 0 = empty
+    int64_t M;
+    int64_t chunks;      // L * cgroups * chunks_per_group
+    int32_t chunks_per_group;
+    int32_t C;
+    int32_t L;
+    int32_t cgroups;     // ceil(C / 64)
+    int32_t blocks_per_xcd;
+};
+
+struct FinalizeArgs {
+    uint32_t* keys;
     float* out_dist;
     int32_t* out_link;
     float* out_link_dist;
-    uint32_t* keys;      // [C][L] complemented ordered keys, 0 = empty
-    uint32_t* ticket;
-    int64_t M;
     int32_t C;
     int32_t L;
-    int32_t point_tiles;
 };
 
 __device__ inline float lerp_exact_ends(float a, float b, float t) {
     return fmaf(t, b, fmaf(-t, a, a));
 }
 
-__device__ inline float wave_min(float v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
-    return v;
+template <bool CUBIC>
+__device__ inline bool inside(const LinkGrid& g, float v0, float v1, float v2) {
+    if (CUBIC) return fmaxf(fabsf(v0), fmaxf(fabsf(v1), fabsf(v2))) <= g.half[0];
+    return (fabsf(v0) <= g.half[0]) & (fabsf(v1) <= g.half[1]) & (fabsf(v2) <= g.half[2]);
 }
 
-template <int K, int CT>
-__global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p) {
-    __shared__ float s_aff[CT * LSDF_MAX_LINKS][12];
-    __shared__ float s_part[kWaves][CT * LSDF_MAX_LINKS];
-    __shared__ int s_last;
+// One cell gather: element index of the cell's lower corner and the three
+// fractions, from centred coordinates known to be inside the box.
+struct Cell {
+    int idx;
+    float fx, fy, fz;
+};
 
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int ptile = blockIdx.x % p.point_tiles;
-    const int c0 = (blockIdx.x / p.point_tiles) * CT;
-    const int L = p.L;
-    const int nc = min(CT, p.C - c0);
-    const int npairs = nc * L;
+__device__ inline Cell locate(const LinkGrid& g, float v0, float v1, float v2) {
+    const float u0 = v0 + g.half[0];
+    const float u1 = v1 + g.half[1];
+    const float u2 = v2 + g.half[2];
+    // u >= 0 here, so truncation is the floor
+    const int ix = min((int)u0, g.n[0] - 2);
+    const int iy = min((int)u1, g.n[1] - 2);
+    const int iz = min((int)u2, g.n[2] - 2);
+    Cell c;
+    c.fx = u0 - (float)ix;
+    c.fy = u1 - (float)iy;
+    c.fz = u2 - (float)iz;
+    c.idx = (iz * g.n[1] + iy) * g.n[0] + ix;
+    return c;
+}
 
-    // 1. affine maps u = A [x; 1] of this block's (configuration, link) pairs
-    if (tid < npairs) {
-        const int c = c0 + tid / L;
-        const int i = tid - (tid / L) * L;
-        const float* T = p.link_T + ((int64_t)c * L + i) * 12;
-        const LinkGrid& g = p.link[i];
-        float Tv[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) Tv[k] = T[k];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            // row a of R^T scaled by invh_a; offset -invh_a (R^T t)_a + nlo_a
-            s_aff[tid][4 * a + 0] = g.invh[a] * Tv[0 + a];
-            s_aff[tid][4 * a + 1] = g.invh[a] * Tv[4 + a];
-            s_aff[tid][4 * a + 2] = g.invh[a] * Tv[8 + a];
-            const float rt = fmaf(Tv[0 + a], Tv[3], fmaf(Tv[4 + a], Tv[7], Tv[8 + a] * Tv[11]));
-            s_aff[tid][4 * a + 3] = fmaf(-g.invh[a], rt, g.nlo[a]);
+// Trilinear value of a cell from its corners (x first, then y, then z).
+__device__ inline float interpolate(float c000, float c100, float c010, float c110, float c001, float c101,
+                                    float c011, float c111, const Cell& cl) {
+    const float e00 = lerp_exact_ends(c000, c100, cl.fx);
+    const float e10 = lerp_exact_ends(c010, c110, cl.fx);
+    const float e01 = lerp_exact_ends(c001, c101, cl.fx);
+    const float e11 = lerp_exact_ends(c011, c111, cl.fx);
+    const float e0 = lerp_exact_ends(e00, e10, cl.fy);
+    const float e1 = lerp_exact_ends(e01, e11, cl.fy);
+    return lerp_exact_ends(e0, e1, cl.fz) + 0.0f;   // -0 -> +0
+}
+
+template <bool CUBIC>
+__global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float* __restrict__ points,
+                                                       const float* __restrict__ grid) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int xcd = blockIdx.x % kXcds;
+    const int slot = blockIdx.x / kXcds;
+    const int waves_per_xcd = p.blocks_per_xcd * kWavesPerBlock;
+    const int wx = slot * kWavesPerBlock + wave;                 // wave index inside the XCD
+    const int64_t q_lo = p.chunks * xcd / kXcds;                // this XCD's slice of chunks
+    const int64_t q_hi = p.chunks * (xcd + 1) / kXcds;
+
+    for (int64_t q = q_lo + wx; q < q_hi; q += waves_per_xcd) {
+        const int64_t g = q / p.chunks_per_group;
+        const int64_t j0 = (q - g * p.chunks_per_group) * kChunk;
+        const int64_t j1 = min(p.M, j0 + kChunk);
+        const int i = (int)(g / p.cgroups);
+        const int cb = (int)(g - (int64_t)i * p.cgroups);
+        const int c = cb * 64 + lane;
+        const LinkGrid& lg = p.link[i];
+        const float* __restrict__ G = grid + lg.offset;
+
+        // this lane's map: v = M [x; y; z] + w (centred grid coordinates)
+        float m00 = 0.f, m01 = 0.f, m02 = 0.f, w0 = kFar;
+        float m10 = 0.f, m11 = 0.f, m12 = 0.f, w1 = kFar;
+        float m20 = 0.f, m21 = 0.f, m22 = 0.f, w2 = kFar;
+        if (c < p.C) {
+            const float* T = p.link_T + ((int64_t)c * p.L + i) * 12;
+            const float r00 = T[0], r01 = T[1], r02 = T[2], t0 = T[3];
+            const float r10 = T[4], r11 = T[5], r12 = T[6], t1 = T[7];
+            const float r20 = T[8], r21 = T[9], r22 = T[10], t2 = T[11];
+            // row a of R^T scaled by invh_a; offset -invh_a (R^T t)_a + cen_a
+            m00 = lg.invh[0] * r00; m01 = lg.invh[0] * r10; m02 = lg.invh[0] * r20;
+            m10 = lg.invh[1] * r01; m11 = lg.invh[1] * r11; m12 = lg.invh[1] * r21;
+            m20 = lg.invh[2] * r02; m21 = lg.invh[2] * r12; m22 = lg.invh[2] * r22;
+            w0 = fmaf(-lg.invh[0], fmaf(r00, t0, fmaf(r10, t1, r20 * t2)), lg.cen[0]);
+            w1 = fmaf(-lg.invh[1], fmaf(r01, t0, fmaf(r11, t1, r21 * t2)), lg.cen[1]);
+            w2 = fmaf(-lg.invh[2], fmaf(r02, t0, fmaf(r12, t1, r22 * t2)), lg.cen[2]);
         }
-    }
+        const int nx = lg.n[0];
+        const int nxy = lg.n[0] * lg.n[1];
 
-    // 2. this lane's points; NaN past the end is never inside a box
-    float px[K], py[K], pz[K];
-    const int64_t pbase = (int64_t)ptile * (kBlock * K);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int64_t j = pbase + (int64_t)k * kBlock + tid;
-        if (j < p.M) {
-            px[k] = p.points[3 * j + 0];
-            py[k] = p.points[3 * j + 1];
-            pz[k] = p.points[3 * j + 2];
-        } else {
-            px[k] = py[k] = pz[k] = __builtin_nanf("");
-        }
-    }
-    __syncthreads();
-
-    // 3. sweep the pairs
-    for (int q = 0; q < npairs; ++q) {
-        const int i = q % L;
-        const LinkGrid& g = p.link[i];
-        const float* G = p.grid + g.offset;
-        const int nx = g.n[0];
-        const int nxy = g.n[0] * g.n[1];
-        float A[12];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) A[k] = s_aff[q][k];
         float best = INFINITY;
+        const int64_t jfull = j0 + (j1 - j0) / kUnroll * kUnroll;
+        for (int64_t j = j0; j < jfull; j += kUnroll) {
+            float v0[kUnroll], v1[kUnroll], v2[kUnroll];
+            bool in[kUnroll];
+            bool any = false;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const float u0 = fmaf(A[0], px[k], fmaf(A[1], py[k], fmaf(A[2], pz[k], A[3])));
-            const float u1 = fmaf(A[4], px[k], fmaf(A[5], py[k], fmaf(A[6], pz[k], A[7])));
-            const float u2 = fmaf(A[8], px[k], fmaf(A[9], py[k], fmaf(A[10], pz[k], A[11])));
-            const bool inside = (u0 >= 0.0f) & (u0 <= g.umax[0]) & (u1 >= 0.0f) & (u1 <= g.umax[1]) &
-                                (u2 >= 0.0f) & (u2 <= g.umax[2]);
-            if (inside) {
-                // u >= 0 here, so truncation is the floor
-                const int ix = min((int)u0, g.n[0] - 2);
-                const int iy = min((int)u1, g.n[1] - 2);
-                const int iz = min((int)u2, g.n[2] - 2);
-                const float fx = u0 - (float)ix;
-                const float fy = u1 - (float)iy;
-                const float fz = u2 - (float)iz;
-                const float* c = G + (iz * nxy + iy * nx + ix);
-                const float c000 = c[0], c100 = c[1];
-                const float c010 = c[nx], c110 = c[nx + 1];
-                const float c001 = c[nxy], c101 = c[nxy + 1];
-                const float c011 = c[nxy + nx], c111 = c[nxy + nx + 1];
-                const float e00 = lerp_exact_ends(c000, c100, fx);
-                const float e10 = lerp_exact_ends(c010, c110, fx);
-                const float e01 = lerp_exact_ends(c001, c101, fx);
-                const float e11 = lerp_exact_ends(c011, c111, fx);
-                const float e0 = lerp_exact_ends(e00, e10, fy);
-                const float e1 = lerp_exact_ends(e01, e11, fy);
-                const float v = lerp_exact_ends(e0, e1, fz) + 0.0f;   // -0 -> +0
-                best = fminf(best, v);
+            for (int k = 0; k < kUnroll; ++k) {
+                const float x = points[3 * j + 3 * k + 0];
+                const float y = points[3 * j + 3 * k + 1];
+                const float z = points[3 * j + 3 * k + 2];
+                v0[k] = fmaf(m00, x, fmaf(m01, y, fmaf(m02, z, w0)));
+                v1[k] = fmaf(m10, x, fmaf(m11, y, fmaf(m12, z, w1)));
+                v2[k] = fmaf(m20, x, fmaf(m21, y, fmaf(m22, z, w2)));
+                in[k] = inside<CUBIC>(lg, v0[k], v1[k], v2[k]);
+                any |= in[k];
+            }
+            if (__ballot(any)) {
+#pragma unroll
+                for (int b = 0; b < kUnroll; b += kGather) {
+                    // issue every corner load of the batch, then interpolate
+                    float c00[kGather], c10[kGather], c01[kGather], c11[kGather];
+                    float d00[kGather], d10[kGather], d01[kGather], d11[kGather];
+                    Cell cell[kGather];
+#pragma unroll
+                    for (int k = 0; k < kGather; ++k) {
+                        cell[k] = locate(lg, v0[b + k], v1[b + k], v2[b + k]);
+                        // lanes outside the box read the first cell (discarded)
+                        const float* cp = G + (in[b + k] ? cell[k].idx : 0);
+                        c00[k] = cp[0];        d00[k] = cp[1];
+                        c10[k] = cp[nx];       d10[k] = cp[nx + 1];
+                        c01[k] = cp[nxy];      d01[k] = cp[nxy + 1];
+                        c11[k] = cp[nxy + nx]; d11[k] = cp[nxy + nx + 1];
+                    }
+#pragma unroll
+                    for (int k = 0; k < kGather; ++k) {
+                        const float val = interpolate(c00[k], d00[k], c10[k], d10[k], c01[k], d01[k], c11[k],
+                                                      d11[k], cell[k]);
+                        if (in[b + k]) best = fminf(best, val);
+                    }
+                }
             }
         }
-        float m = INFINITY;
-        if (__ballot(best < INFINITY)) m = wave_min(best);
-        if (lane == 0) s_part[wave][q] = m;
-    }
-    __syncthreads();
-
-    // 4. merge across waves, then across blocks
-    if (tid < npairs) {
-        float m = s_part[0][tid];
-#pragma unroll
-        for (int w = 1; w < kWaves; ++w) m = fminf(m, s_part[w][tid]);
-        if (m < INFINITY) {
-            const int c = c0 + tid / L;
-            const int i = tid - (tid / L) * L;
-            atomicMax(&p.keys[(int64_t)c * L + i], ~lsdf::ordered_bits(m));
+        for (int64_t j = jfull; j < j1; ++j) {   // fewer than kUnroll points left
+            const float x = points[3 * j + 0], y = points[3 * j + 1], z = points[3 * j + 2];
+            const float v0 = fmaf(m00, x, fmaf(m01, y, fmaf(m02, z, w0)));
+            const float v1 = fmaf(m10, x, fmaf(m11, y, fmaf(m12, z, w1)));
+            const float v2 = fmaf(m20, x, fmaf(m21, y, fmaf(m22, z, w2)));
+            if (inside<CUBIC>(lg, v0, v1, v2)) {
+                const Cell cl = locate(lg, v0, v1, v2);
+                const float* cp = G + cl.idx;
+                best = fminf(best, interpolate(cp[0], cp[1], cp[nx], cp[nx + 1], cp[nxy], cp[nxy + 1], cp[nxy + nx],
+                                               cp[nxy + nx + 1], cl));
+            }
         }
+        if (c < p.C && best < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(best));
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned total = gridDim.x;
-        s_last = (atomicInc(p.ticket, total - 1) == total - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
+}
 
-    // 5. last block: outputs, and the workspace back to zero
-    __threadfence();
-    for (int c = tid; c < p.C; c += kBlock) {
-        uint32_t bestk = 0;
-        int arg = -1;
-        for (int i = 0; i < L; ++i) {
-            const uint32_t k = atomicExch(&p.keys[(int64_t)c * L + i], 0u);
-            if (p.out_link_dist) p.out_link_dist[(int64_t)c * L + i] = k ? lsdf::from_ordered_bits(~k) : INFINITY;
-            if (k > bestk) {
-                bestk = k;
+// Keys -> outputs, one lane per configuration; clears the keys.
+__global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs p) {
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= p.C) return;
+    uint32_t* row = p.keys + (int64_t)c * p.L;
+    uint32_t k[LSDF_MAX_LINKS];
+#pragma unroll
+    for (int i = 0; i < LSDF_MAX_LINKS; ++i)
+        if (i < p.L) k[i] = row[i];
+    uint32_t bestk = 0;
+    int arg = -1;
+#pragma unroll
+    for (int i = 0; i < LSDF_MAX_LINKS; ++i) {
+        if (i < p.L) {
+            row[i] = 0u;
+            if (p.out_link_dist) p.out_link_dist[(int64_t)c * p.L + i] = k[i] ? lsdf::from_ordered_bits(~k[i]) : INFINITY;
+            if (k[i] > bestk) {   // strict: ties keep the lowest link
+                bestk = k[i];
                 arg = i;
             }
         }
-        p.out_dist[c] = bestk ? lsdf::from_ordered_bits(~bestk) : INFINITY;
-        p.out_link[c] = arg;
     }
+    p.out_dist[c] = bestk ? lsdf::from_ordered_bits(~bestk) : INFINITY;
+    p.out_link[c] = arg;
 }
 
 size_t keys_bytes(int64_t C, int64_t L) { return ((size_t)(C * L) * 4 + 255) / 256 * 256; }
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus;
+}
 
 }  // namespace
 
@@ -197,7 +260,7 @@ LSDF_API int lsdf_query_workspace_size(int32_t C, int32_t L, int64_t M, size_t* 
     if (!bytes) return fail(LSDF_E_INVALID_ARG, "query_workspace_size: bytes is NULL");
     if (C < 0 || M < 0) return fail(LSDF_E_SHAPE, "query_workspace_size: negative size");
     if (L < 1 || L > LSDF_MAX_LINKS) return fail(LSDF_E_SHAPE, "query_workspace_size: L = %d out of [1, %d]", (int)L, LSDF_MAX_LINKS);
-    *bytes = kWsHeader + keys_bytes(C, L);
+    *bytes = keys_bytes(C, L);
     return LSDF_OK;
 }
 
@@ -217,33 +280,43 @@ LSDF_API int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L, 
     if (M > 0 && !points) return fail(LSDF_E_INVALID_ARG, "query: points is NULL");
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return fail(LSDF_E_INVALID_ARG, "query: workspace is not 256-byte aligned");
-    const size_t need = kWsHeader + keys_bytes(C, L);
+    const size_t need = keys_bytes(C, L);
     if (ws_bytes < need) return fail(LSDF_E_SHAPE, "query: workspace has %zu bytes, needs %zu", ws_bytes, need);
 
-    constexpr int K = 8;
-    constexpr int CT = 2;
-    const int64_t point_tiles = M > 0 ? (M + kBlock * K - 1) / (kBlock * K) : 1;
-    const int64_t conf_tiles = (C + CT - 1) / CT;
-    if (point_tiles * conf_tiles > INT32_MAX) return fail(LSDF_E_SHAPE, "query: problem too large for one launch");
-
     QueryArgs p{};
+    bool cubic = true;
     for (int i = 0; i < L; ++i) {
         int rc = prepare_link_grid(grids[i], i, &p.link[i]);
         if (rc != LSDF_OK) return rc;
+        cubic = cubic && p.link[i].cubic;
     }
+    hipStream_t s = as_stream(stream);
     p.link_T = link_T;
-    p.grid = static_cast<const float*>(grid_buf);
-    p.points = points;
-    p.out_dist = out_dist;
-    p.out_link = out_link;
-    p.out_link_dist = out_link_dist;
-    p.ticket = static_cast<uint32_t*>(workspace);
-    p.keys = reinterpret_cast<uint32_t*>(static_cast<char*>(workspace) + kWsHeader);
+    p.keys = static_cast<uint32_t*>(workspace);
     p.M = M;
     p.C = C;
     p.L = L;
-    p.point_tiles = (int32_t)point_tiles;
-    hipLaunchKernelGGL((query_kernel<K, CT>), dim3((unsigned)(point_tiles * conf_tiles)), dim3(kBlock), 0,
-                       as_stream(stream), p);
-    return check_launch("query_min_distance");
+    p.cgroups = (C + 63) / 64;
+    p.chunks_per_group = (int32_t)((M + kChunk - 1) / kChunk);
+    p.chunks = (int64_t)L * p.cgroups * p.chunks_per_group;
+    if (p.chunks > 0) {
+        const int cus = device_cus();
+        if (cus <= 0) return fail(LSDF_E_DEVICE, "query: cannot read the device's compute-unit count");
+        // persistent grid: at most kBlocksPerCu blocks per CU, a multiple of
+        // the XCD count, and no more waves than chunks
+        int64_t blocks = std::min<int64_t>((int64_t)cus * kBlocksPerCu,
+                                           (p.chunks + kWavesPerBlock - 1) / kWavesPerBlock);
+        blocks = (blocks + kXcds - 1) / kXcds * kXcds;
+        p.blocks_per_xcd = (int32_t)(blocks / kXcds);
+        const float* G = static_cast<const float*>(grid_buf);
+        if (cubic)
+            hipLaunchKernelGGL((query_kernel<true>), dim3((unsigned)blocks), dim3(kBlock), 0, s, p, points, G);
+        else
+            hipLaunchKernelGGL((query_kernel<false>), dim3((unsigned)blocks), dim3(kBlock), 0, s, p, points, G);
+        int rc = check_launch("query_min_distance");
+        if (rc != LSDF_OK) return rc;
+    }
+    FinalizeArgs f{p.keys, out_dist, out_link, out_link_dist, C, L};
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((C + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, f);
+    return check_launch("query_min_distance (finalize)");
 }

@@ -171,6 +171,19 @@ def test_query_sixteen_links_and_one_link(B, orc, tiny, tiny_grids):
                      twin(orc, w1, np.ascontiguousarray(T[:, 3:4]), tiny_grids[3:4], pts))
 
 
+def test_query_bit_exact_non_cubic_grids(B, orc, tiny):
+    """Grids with different node counts per axis take the per-axis box test."""
+    n = np.array([[24, 32, 40], [40, 24, 32], [32, 40, 24], [24, 24, 40], [40, 40, 24], [33, 17, 29], [16, 48, 20]],
+                 dtype=np.int32)
+    w = synth.Workload("nc", tiny.robot, tiny.q, tiny.points, tiny.grid_lo, tiny.grid_hi, n, {})
+    grids = [orc.build_grid(m, w.grid_lo[i].astype(np.float64), w.grid_hi[i].astype(np.float64), n[i])
+             for i, m in enumerate(w.robot.links)]
+    T32 = orc.fk(w.robot.dh, w.q, w.robot.base_T).astype(np.float32)
+    gs = upload_grids(B, w, grids)
+    pts = w.points.astype(np.float32)
+    assert_bit_exact(run_query(B, T32, gs, pts), twin(orc, w, T32, grids, pts))
+
+
 def test_query_workspace_cleared_and_repeatable(B, orc, tiny, tiny_grids):
     T32 = to_dev(orc.fk(tiny.robot.dh, tiny.q, tiny.robot.base_T).astype(np.float32))
     gs = upload_grids(B, tiny, tiny_grids)
