@@ -30,6 +30,21 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(kernel_source: str, summary: str):
+    """HBM bytes per launch measured by the rocprofv3 FETCH_SIZE/WRITE_SIZE
+    runs recorded in the profile summary, or None when the kernel source has
+    changed since (the summary stores a hash of the source it measured)."""
+    import hashlib
+    try:
+        lines = dict(l.split(": ", 1) for l in open(summary).read().splitlines() if ": " in l)
+        src = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()[:16]
+        if lines.get("query_kernel_source_sha256_16", "").strip() != src:
+            return None
+        return int(float(lines["query_kernel_traffic_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def count_inbox_pairs(T: np.ndarray, lo, hi, points: np.ndarray) -> int:
     """Pairs (c, i, j) whose point lies in link i's box at waypoint c (double
     precision; used only to price the in-box work for the roofline)."""
@@ -75,6 +90,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="paper")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB mebibytes (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the clearance query is measured on a single MI355X "
@@ -86,9 +103,18 @@ def main():
     import synth
     from paper_2309_12543_amd import lsdf
 
-    lsdf.load_library()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 5 copies of {args.copy_probe} MiB")
+        return
+    lsdf.load_library()
     w = synth.make_workload(args.workload)
     log(f"workload {w.name}: C={w.C} M={w.M} L={w.L} n={int(w.grid_n[0, 0])}")
     gs = lsdf.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device=dev)
@@ -149,8 +175,11 @@ def main():
         "query_kernel_ms": round(kernel_ms, 5),
         "inbox_pair_fraction": round(inbox / pairs, 5),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
-                     "kernel": "query_kernel"},
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+                     "traffic": profiled_traffic(os.path.join(ROOT, "paper_2309_12543_amd", "csrc", "query.hip"),
+                                                 os.path.join(ROOT, "profiles", "query_kernel_paper.txt")),
+                     "kernel": "query_kernel (timed with its finalize kernel: one lsdf_query_min_distance call)",
+                     "algorithmic_flop": flop},
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
