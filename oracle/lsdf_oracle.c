@@ -422,3 +422,145 @@ ORC_EXPORT void orc_reduce_f32(const float* cl, int32_t C, int32_t L, float* d, 
         link[c] = arg;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Learned per-link SDF surrogate (not in the paper; the build's learned     */
+/* extension, checked against the grid and mesh distances above).            */
+/*   m(x) = w4 . h3 + b4,  h_k = SiLU(W_k h_{k-1} + b_k),  h_0 = x (3 values) */
+/*   widths 3 -> 128 -> 128 -> 128 -> 1,  SiLU(z) = z / (1 + exp(-z)).       */
+/* Parameter vector (33665 values): W1[128][3], b1[128], W2[128][128], b2,    */
+/* W3[128][128], b3, w4[128], b4.  Inputs are normalised coordinates.         */
+/* Loss: mean absolute error over the batch (the paper trains its own tiny   */
+/* network with an L1 loss and Adam, Sec. IV-B); subgradient sign(0) = 0.    */
+/* ------------------------------------------------------------------------ */
+#define ORC_H 128
+#define ORC_OFF_W1 0
+#define ORC_OFF_B1 (ORC_OFF_W1 + ORC_H * 3)
+#define ORC_OFF_W2 (ORC_OFF_B1 + ORC_H)
+#define ORC_OFF_B2 (ORC_OFF_W2 + ORC_H * ORC_H)
+#define ORC_OFF_W3 (ORC_OFF_B2 + ORC_H)
+#define ORC_OFF_B3 (ORC_OFF_W3 + ORC_H * ORC_H)
+#define ORC_OFF_W4 (ORC_OFF_B3 + ORC_H)
+#define ORC_OFF_B4 (ORC_OFF_W4 + ORC_H)
+#define ORC_NPARAM (ORC_OFF_B4 + 1)
+
+ORC_EXPORT int64_t orc_mlp_nparam(void) { return ORC_NPARAM; }
+
+static double silu(double z) { return z / (1.0 + exp(-z)); }
+static double silu_grad(double z) {
+    double s = 1.0 / (1.0 + exp(-z));
+    return s * (1.0 + z * (1.0 - s));
+}
+
+/* Round a double to the nearest bfloat16 (ties to even), via float. */
+static double bf16r(double x) {
+    float f = (float)x;
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    if ((b & 0x7f800000u) != 0x7f800000u) {
+        uint32_t lsb = (b >> 16) & 1u;
+        b = (b + 0x7fffu + lsb) & 0xffff0000u;
+    }
+    memcpy(&f, &b, 4);
+    return (double)f;
+}
+
+/* One sample, forward.  bf16 != 0 rounds to bfloat16 where the GPU kernels
+ * do (weights W1, W2, W3, w4; activations h1, h2, h3 before they are
+ * multiplied); everything else stays double.  Stores pre-activations z1..z3
+ * and activations h1..h3 (as used by the next layer). */
+static double mlp_forward_one(const double* P, const double* x, int bf16, double* z1, double* h1,
+                              double* z2, double* h2, double* z3, double* h3) {
+#define R(v) (bf16 ? bf16r(v) : (v))
+    for (int u = 0; u < ORC_H; ++u) {
+        double s = P[ORC_OFF_B1 + u];
+        for (int k = 0; k < 3; ++k) s += R(P[ORC_OFF_W1 + 3 * u + k]) * x[k];
+        z1[u] = s;
+        h1[u] = R(silu(s));
+    }
+    for (int u = 0; u < ORC_H; ++u) {
+        double s = 0.0;
+        for (int k = 0; k < ORC_H; ++k) s += R(P[ORC_OFF_W2 + ORC_H * u + k]) * h1[k];
+        z2[u] = s + P[ORC_OFF_B2 + u];
+        h2[u] = R(silu(z2[u]));
+    }
+    for (int u = 0; u < ORC_H; ++u) {
+        double s = 0.0;
+        for (int k = 0; k < ORC_H; ++k) s += R(P[ORC_OFF_W3 + ORC_H * u + k]) * h2[k];
+        z3[u] = s + P[ORC_OFF_B3 + u];
+        h3[u] = R(silu(z3[u]));
+    }
+    double m = P[ORC_OFF_B4];
+    for (int k = 0; k < ORC_H; ++k) m += R(P[ORC_OFF_W4 + k]) * h3[k];
+    return m;
+#undef R
+}
+
+ORC_EXPORT void orc_mlp_forward(const double* P, const double* X, int64_t N, int32_t bf16, double* out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < N; ++j) {
+        double z1[ORC_H], h1[ORC_H], z2[ORC_H], h2[ORC_H], z3[ORC_H], h3[ORC_H];
+        out[j] = mlp_forward_one(P, X + 3 * j, bf16, z1, h1, z2, h2, z3, h3);
+    }
+}
+
+/* Mean-absolute-error loss over N samples and its gradient (chain rule,
+ * layer by layer).  With bf16 != 0 the backward pass also rounds where the
+ * GPU kernels do: the delta vectors dz3 and dz2 before they are multiplied
+ * (weight gradients and the back-propagated deltas). */
+ORC_EXPORT double orc_mlp_loss_grad(const double* P, const double* X, const double* Y, int64_t N,
+                                    int32_t bf16, double* grad) {
+#define R(v) (bf16 ? bf16r(v) : (v))
+    memset(grad, 0, ORC_NPARAM * sizeof(double));
+    double loss = 0.0;
+    for (int64_t j = 0; j < N; ++j) {
+        double z1[ORC_H], h1[ORC_H], z2[ORC_H], h2[ORC_H], z3[ORC_H], h3[ORC_H];
+        double d3[ORC_H], d2[ORC_H], d1[ORC_H];
+        const double* x = X + 3 * j;
+        double m = mlp_forward_one(P, x, bf16, z1, h1, z2, h2, z3, h3);
+        double r = m - Y[j];
+        loss += fabs(r);
+        double dm = (r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0)) / (double)N;
+        grad[ORC_OFF_B4] += dm;
+        for (int k = 0; k < ORC_H; ++k) {
+            grad[ORC_OFF_W4 + k] += dm * h3[k];
+            d3[k] = R(dm * R(P[ORC_OFF_W4 + k]) * silu_grad(z3[k]));
+        }
+        for (int u = 0; u < ORC_H; ++u) {
+            grad[ORC_OFF_B3 + u] += d3[u];
+            for (int k = 0; k < ORC_H; ++k) grad[ORC_OFF_W3 + ORC_H * u + k] += d3[u] * h2[k];
+        }
+        for (int k = 0; k < ORC_H; ++k) {
+            double s = 0.0;
+            for (int u = 0; u < ORC_H; ++u) s += R(P[ORC_OFF_W3 + ORC_H * u + k]) * d3[u];
+            d2[k] = R(s * silu_grad(z2[k]));
+        }
+        for (int u = 0; u < ORC_H; ++u) {
+            grad[ORC_OFF_B2 + u] += d2[u];
+            for (int k = 0; k < ORC_H; ++k) grad[ORC_OFF_W2 + ORC_H * u + k] += d2[u] * h1[k];
+        }
+        for (int k = 0; k < ORC_H; ++k) {
+            double s = 0.0;
+            for (int u = 0; u < ORC_H; ++u) s += R(P[ORC_OFF_W2 + ORC_H * u + k]) * d2[u];
+            d1[k] = s * silu_grad(z1[k]);
+        }
+        for (int u = 0; u < ORC_H; ++u) {
+            grad[ORC_OFF_B1 + u] += d1[u];
+            for (int k = 0; k < 3; ++k) grad[ORC_OFF_W1 + 3 * u + k] += d1[u] * x[k];
+        }
+    }
+    return loss / (double)N;
+#undef R
+}
+
+/* Adam (Kingma & Ba 2015), step t >= 1, bias-corrected moments. */
+ORC_EXPORT void orc_adam_step(double* P, double* Mo, double* Vo, const double* G, int64_t n, int64_t t,
+                              double lr, double beta1, double beta2, double eps) {
+    double c1 = 1.0 - pow(beta1, (double)t), c2 = 1.0 - pow(beta2, (double)t);
+    for (int64_t k = 0; k < n; ++k) {
+        Mo[k] = beta1 * Mo[k] + (1.0 - beta1) * G[k];
+        Vo[k] = beta2 * Vo[k] + (1.0 - beta2) * G[k] * G[k];
+        double mh = Mo[k] / c1, vh = Vo[k] / c2;
+        P[k] -= lr * mh / (sqrt(vh) + eps);
+    }
+}

@@ -67,6 +67,15 @@ def load():
     lib.orc_reduce_f64.argtypes = [_dp, ct.c_int32, ct.c_int32, _dp, _ip]
     lib.orc_reduce_f32.restype = None
     lib.orc_reduce_f32.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _ip]
+    lib.orc_mlp_nparam.restype = ct.c_int64
+    lib.orc_mlp_nparam.argtypes = []
+    lib.orc_mlp_forward.restype = None
+    lib.orc_mlp_forward.argtypes = [_dp, _dp, ct.c_int64, ct.c_int32, _dp]
+    lib.orc_mlp_loss_grad.restype = ct.c_double
+    lib.orc_mlp_loss_grad.argtypes = [_dp, _dp, _dp, ct.c_int64, ct.c_int32, _dp]
+    lib.orc_adam_step.restype = None
+    lib.orc_adam_step.argtypes = [_dp, _dp, _dp, _dp, ct.c_int64, ct.c_int64, ct.c_double, ct.c_double,
+                                  ct.c_double, ct.c_double]
     _lib = lib
     return lib
 
@@ -233,5 +242,62 @@ def workload_grids(w, dtype=np.float64):
             for i, m in enumerate(w.robot.links)]
 
 
+# ---------------------------------------------------------------------------
+# learned per-link SDF (MLP 3 -> 128 -> 128 -> 128 -> 1, SiLU)
+# ---------------------------------------------------------------------------
+
+MLP_HIDDEN = 128
+
+
+def mlp_nparam() -> int:
+    return int(load().orc_mlp_nparam())
+
+
+def mlp_forward(params, X, bf16: bool = False) -> np.ndarray:
+    """Network output at normalised inputs X [N][3]; bf16=True rounds weights
+    and activations to bfloat16 where the GPU kernels do."""
+    lib = load()
+    P = _c(params, np.float64)
+    X = _c(np.atleast_2d(X), np.float64)
+    out = np.empty(X.shape[0], dtype=np.float64)
+    lib.orc_mlp_forward(_ptr(P, _dp), _ptr(X, _dp), X.shape[0], int(bf16), _ptr(out, _dp))
+    return out
+
+
+def mlp_loss_grad(params, X, Y, bf16: bool = False):
+    """(mean absolute error, gradient [nparam])."""
+    lib = load()
+    P = _c(params, np.float64)
+    X = _c(np.atleast_2d(X), np.float64)
+    Y = _c(Y, np.float64)
+    g = np.empty(P.shape[0], dtype=np.float64)
+    loss = lib.orc_mlp_loss_grad(_ptr(P, _dp), _ptr(X, _dp), _ptr(Y, _dp), X.shape[0], int(bf16), _ptr(g, _dp))
+    return float(loss), g
+
+
+def adam_step(params, m, v, grad, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of float64 arrays params, m, v."""
+    lib = load()
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _c(grad, np.float64)
+    lib.orc_adam_step(_ptr(params, _dp), _ptr(m, _dp), _ptr(v, _dp), _ptr(g, _dp), params.shape[0], int(t),
+                      float(lr), float(beta1), float(beta2), float(eps))
+
+
+def mlp_unpack(params):
+    """Views of the parameter vector: W1[128][3], b1, W2[128][128], b2, W3, b3, w4, b4."""
+    H = MLP_HIDDEN
+    P = np.asarray(params)
+    o = 0
+    out = []
+    for shape in ((H, 3), (H,), (H, H), (H,), (H, H), (H,), (H,), (1,)):
+        n = int(np.prod(shape))
+        out.append(P[o:o + n].reshape(shape))
+        o += n
+    return out
+
+
 __all__ = ["build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
-           "query_f32", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids"]
+           "query_f32", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids",
+           "MLP_HIDDEN", "adam_step", "mlp_forward", "mlp_loss_grad", "mlp_nparam", "mlp_unpack"]
