@@ -133,9 +133,9 @@ int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L,
                             uint32_t flags, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---- link SDF construction -------------------------------------------------
- * Sec. III-A: "we pre-compute Signed Distance Fields for each link on its
- * local coordinates" (the construction method is not given; this one is a
- * brute-force exact signed distance to a closed triangle mesh).
+ * Sec. III-A: each link's signed distance field is computed once, offline,
+ * on a grid in the link's own frame.  The paper does not say how; this call
+ * uses the brute-force exact signed distance to a closed triangle mesh.
  *   verts       device float [nv][3] vertices in the link frame
  *   tris        device int32 [nt][3] triangles, outward (counter-clockwise)
  *   comp_first  host int32 [ncomp+1]: triangles [comp_first[k],
@@ -148,6 +148,80 @@ int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L,
 int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* tris, int32_t nt,
                         const int32_t* comp_first, int32_t ncomp, const lsdf_grid* desc,
                         void* grid_buf, void* stream);
+
+/* ---- learned per-link SDF surrogate ---------------------------------------
+ * An extension of the method (not in the paper): per link, a small network
+ * m(x) = w4 . h3 + b4, h_k = SiLU(W_k h_{k-1} + b_k), widths 3 -> 128 -> 128
+ * -> 128 -> 1, SiLU(z) = z / (1 + exp(-z)), maps a link-frame point
+ * normalised to the link's domain to an estimate of the link's signed
+ * distance.  It answers queries beyond the grid box (the far field); the
+ * grid stays the answer for every pair whose estimate is below a safety
+ * margin, and the judge of the network's error.  The paper's own network
+ * (Sec. III-B-1) is a different one (it approximates the grid transform);
+ * its training recipe (L1 loss, Adam, Sec. IV-B) is reused here.
+ *
+ * Parameters: FP32 [L][LSDF_MLP_PARAMS] per link, laid out as
+ * W1[128][3], b1[128], W2[128][128], b2[128], W3[128][128], b3[128],
+ * w4[128], b4 (row-major [out][in]).  W1, W2, W3 and w4 are used rounded to
+ * bfloat16 (nearest even); activations are rounded to bfloat16 before each
+ * product; the input layer runs in FP32 and the 128x128 layers on bf16 MFMA
+ * with FP32 accumulation. */
+#define LSDF_MLP_HIDDEN 128
+#define LSDF_MLP_PARAMS 33665
+
+/* Normalisation of a link's network input: xhat = (x_link - centre) / half;
+ * the domain is |xhat_a| <= 1 on every axis. */
+typedef struct lsdf_mlp_domain {
+    float centre[3];
+    float half[3];     /* each > 0 */
+} lsdf_mlp_domain;
+
+/* Network outputs at N link-frame points of one link.
+ *   params  device float [LSDF_MLP_PARAMS]; domain host; points device [N][3];
+ *   out     device float [N] (evaluated also outside the domain). */
+int lsdf_mlp_eval(const float* params, const lsdf_mlp_domain* domain, const float* points, int64_t N,
+                  float* out, void* stream);
+
+/* Clearance with the learned surrogate: as lsdf_query_min_distance, but the
+ * value of pair (c, i, j) is m = the network of link i at the point (if the
+ * point lies in link i's domain; +inf otherwise), replaced by the grid value
+ * (+inf outside the grid box) when m < margin.  Same workspace as
+ * lsdf_query_min_distance (lsdf_query_workspace_size).  margin may be +inf
+ * (every pair takes the grid value) or -inf (none does).  A pair that takes
+ * the grid value gets exactly the bits lsdf_query_min_distance would give. */
+int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t L, const lsdf_grid* grids,
+                                const void* grid_buf, const float* mlp_params, const lsdf_mlp_domain* domains,
+                                float margin, const float* points, int64_t M, float* out_dist, int32_t* out_link,
+                                float* out_link_dist, uint32_t flags, void* workspace, size_t ws_bytes,
+                                void* stream);
+
+/* Training.  For each link i, B samples are taken from that link's N
+ * samples (link-frame points [L][N][3] with labels [L][N]) through
+ * batch_index [L][B] (NULL = the first B), and the mean absolute error of
+ * the network over them is differentiated (Sec. IV-B trains with an L1 loss).
+ *   lsdf_mlp_loss_grad: loss_out [L] (or NULL), grad_out [L][LSDF_MLP_PARAMS]
+ *   lsdf_mlp_train_step: the same, then one Adam step (Kingma & Ba) on
+ *     params with moments adam_m, adam_v (FP32, same shape, zero at t = 1),
+ *     step t >= 1; grad_out may be NULL.
+ * B must be a positive multiple of 512.  The workspace (any contents) has at
+ * least lsdf_mlp_train_workspace_size() bytes, 256-byte aligned. */
+int lsdf_mlp_train_workspace_size(int32_t L, int32_t B, size_t* bytes);
+int lsdf_mlp_loss_grad(const float* params, const lsdf_mlp_domain* domains, int32_t L, const float* samples,
+                       const float* labels, int64_t N, const int32_t* batch_index, int32_t B, float* loss_out,
+                       float* grad_out, void* workspace, size_t ws_bytes, void* stream);
+int lsdf_mlp_train_step(float* params, float* adam_m, float* adam_v, int64_t t, float lr, float beta1, float beta2,
+                        float eps, const lsdf_mlp_domain* domains, int32_t L, const float* samples,
+                        const float* labels, int64_t N, const int32_t* batch_index, int32_t B, float* loss_out,
+                        float* grad_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* Training labels at N link-frame points of one link: the grid value
+ * (lsdf_query_min_distance's arithmetic, identity pose) inside the grid box,
+ * the exact signed distance to the mesh outside it (brute force, as in
+ * lsdf_build_link_sdf).  Arguments as in lsdf_build_link_sdf; points device
+ * [N][3], out device [N]. */
+int lsdf_sdf_labels(const float* verts, int32_t nv, const int32_t* tris, int32_t nt, const int32_t* comp_first,
+                    int32_t ncomp, const lsdf_grid* desc, const void* grid_buf, const float* points, int64_t N,
+                    float* out, void* stream);
 
 #ifdef __cplusplus
 }

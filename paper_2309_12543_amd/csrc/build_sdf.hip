@@ -7,9 +7,11 @@
 //     sum of signed solid angles (Van Oosterom & Strackee 1983) over 4 pi;
 //   * a link made of several closed parts takes the minimum over parts.
 // One lane per node; triangles are staged through LDS in chunks.
-#include "lsdf_internal.hpp"
+#include "grid_sample.hpp"
 
 namespace {
+
+using namespace lsdf;
 
 constexpr int kBlock = 256;
 
@@ -83,16 +85,9 @@ __device__ float solid_angle(V3 p, V3 a, V3 b, V3 c) {
     return 2.0f * atan2f(det, den);
 }
 
-__global__ __launch_bounds__(kBlock) void build_sdf_kernel(BuildArgs p) {
-    __shared__ float s_tri[kBlock][9];
-    const int64_t nodes = (int64_t)p.n[0] * p.n[1] * p.n[2];
-    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool active = idx < nodes;
-    const int64_t kx = idx % p.n[0];
-    const int64_t ky = (idx / p.n[0]) % p.n[1];
-    const int64_t kz = idx / ((int64_t)p.n[0] * p.n[1]);
-    const V3 pt = {fmaf((float)kx, p.h[0], p.lo[0]), fmaf((float)ky, p.h[1], p.lo[1]),
-                   fmaf((float)kz, p.h[2], p.lo[2])};
+// Signed distance of pt to the mesh (every lane of the block takes part in
+// staging triangles through LDS; lanes with want == false skip the math).
+__device__ float mesh_sdf(const BuildArgs& p, float (*s_tri)[9], V3 pt, bool want) {
     float sdf = INFINITY;
     for (int comp = 0; comp < p.ncomp; ++comp) {
         const int t0 = p.comp_first[comp], t1 = p.comp_first[comp + 1];
@@ -113,23 +108,125 @@ __global__ __launch_bounds__(kBlock) void build_sdf_kernel(BuildArgs p) {
                 }
             }
             __syncthreads();
-            const int cnt = min(kBlock, t1 - base);
-            for (int k = 0; k < cnt; ++k) {
-                const V3 a = {s_tri[k][0], s_tri[k][1], s_tri[k][2]};
-                const V3 b = {s_tri[k][3], s_tri[k][4], s_tri[k][5]};
-                const V3 c = {s_tri[k][6], s_tri[k][7], s_tri[k][8]};
-                best2 = fminf(best2, dist2_point_triangle(pt, a, b, c));
-                omega += solid_angle(pt, a, b, c);
+            if (want) {
+                const int cnt = min(kBlock, t1 - base);
+                for (int k = 0; k < cnt; ++k) {
+                    const V3 a = {s_tri[k][0], s_tri[k][1], s_tri[k][2]};
+                    const V3 b = {s_tri[k][3], s_tri[k][4], s_tri[k][5]};
+                    const V3 c = {s_tri[k][6], s_tri[k][7], s_tri[k][8]};
+                    best2 = fminf(best2, dist2_point_triangle(pt, a, b, c));
+                    omega += solid_angle(pt, a, b, c);
+                }
             }
         }
         const float u = sqrtf(best2);
         const float winding = omega * (float)(0.25 / M_PI);
         sdf = fminf(sdf, winding > 0.5f ? -u : u);
     }
+    return sdf;
+}
+
+// Grid nodes: node idx of the grid described by p.
+__global__ __launch_bounds__(kBlock) void build_sdf_kernel(BuildArgs p) {
+    __shared__ float s_tri[kBlock][9];
+    const int64_t nodes = (int64_t)p.n[0] * p.n[1] * p.n[2];
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool active = idx < nodes;
+    const int64_t kx = idx % p.n[0];
+    const int64_t ky = (idx / p.n[0]) % p.n[1];
+    const int64_t kz = idx / ((int64_t)p.n[0] * p.n[1]);
+    const V3 pt = {fmaf((float)kx, p.h[0], p.lo[0]), fmaf((float)ky, p.h[1], p.lo[1]),
+                   fmaf((float)kz, p.h[2], p.lo[2])};
+    const float sdf = mesh_sdf(p, s_tri, pt, true);
     if (active) p.out[idx] = sdf;
 }
 
+struct LabelArgs {
+    BuildArgs mesh;
+    LinkGrid lg;
+    const float* grid;
+    const float* points;
+    float* out;
+    int64_t N;
+};
+
+// Labels: the grid value inside the grid box, the exact distance outside.
+template <bool CUBIC>
+__global__ __launch_bounds__(kBlock) void label_kernel(LabelArgs p) {
+    __shared__ float s_tri[kBlock][9];
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool active = j < p.N;
+    const int64_t jj = active ? j : p.N - 1;
+    const V3 pt = {p.points[3 * jj + 0], p.points[3 * jj + 1], p.points[3 * jj + 2]};
+    const float ident[12] = {1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f};
+    const GridMap gm = grid_map(p.lg, ident);
+    const float g = sample_or_inf<CUBIC>(p.grid + p.lg.offset, p.lg, gm, pt.x, pt.y, pt.z);
+    const bool exact = active && !(g < INFINITY);
+    float v = g;
+    if (__syncthreads_or(exact)) {
+        const float e = mesh_sdf(p.mesh, s_tri, pt, exact);
+        if (exact) v = e;
+    }
+    if (active) p.out[j] = v;
+}
+
 }  // namespace
+
+namespace {
+
+int mesh_args(const float* verts, int32_t nv, const int32_t* tris, int32_t nt, const int32_t* comp_first,
+              int32_t ncomp, BuildArgs* p) {
+    using namespace lsdf;
+    if (nv < 1 || nt < 1) return fail(LSDF_E_SHAPE, "mesh: empty (nv = %d, nt = %d)", (int)nv, (int)nt);
+    if (!verts || !tris) return fail(LSDF_E_INVALID_ARG, "mesh: NULL device pointer");
+    if (comp_first) {
+        if (ncomp < 1 || ncomp > LSDF_MAX_COMPONENTS)
+            return fail(LSDF_E_SHAPE, "mesh: ncomp = %d out of [1, %d]", (int)ncomp, LSDF_MAX_COMPONENTS);
+        if (comp_first[0] != 0 || comp_first[ncomp] != nt)
+            return fail(LSDF_E_SHAPE, "mesh: comp_first must run from 0 to nt");
+        for (int k = 0; k <= ncomp; ++k) {
+            if (k > 0 && comp_first[k] <= comp_first[k - 1])
+                return fail(LSDF_E_SHAPE, "mesh: comp_first must increase strictly");
+            p->comp_first[k] = comp_first[k];
+        }
+        p->ncomp = ncomp;
+    } else {
+        p->comp_first[0] = 0;
+        p->comp_first[1] = nt;
+        p->ncomp = 1;
+    }
+    p->nv = nv;
+    p->verts = verts;
+    p->tris = tris;
+    return LSDF_OK;
+}
+
+}  // namespace
+
+LSDF_API int lsdf_sdf_labels(const float* verts, int32_t nv, const int32_t* tris, int32_t nt,
+                             const int32_t* comp_first, int32_t ncomp, const lsdf_grid* desc, const void* grid_buf,
+                             const float* points, int64_t N, float* out, void* stream) {
+    using namespace lsdf;
+    clear_error();
+    if (!desc) return fail(LSDF_E_INVALID_ARG, "sdf_labels: desc is NULL");
+    if (N < 0) return fail(LSDF_E_SHAPE, "sdf_labels: N < 0");
+    LabelArgs a{};
+    int rc = mesh_args(verts, nv, tris, nt, comp_first, ncomp, &a.mesh);
+    if (rc != LSDF_OK) return rc;
+    if ((rc = prepare_link_grid(*desc, 0, &a.lg)) != LSDF_OK) return rc;
+    if (N == 0) return LSDF_OK;
+    if (!grid_buf || !points || !out) return fail(LSDF_E_INVALID_ARG, "sdf_labels: NULL device pointer");
+    a.grid = static_cast<const float*>(grid_buf);
+    a.points = points;
+    a.out = out;
+    a.N = N;
+    const dim3 grid((unsigned)((N + kBlock - 1) / kBlock));
+    if (a.lg.cubic)
+        hipLaunchKernelGGL(label_kernel<true>, grid, dim3(kBlock), 0, as_stream(stream), a);
+    else
+        hipLaunchKernelGGL(label_kernel<false>, grid, dim3(kBlock), 0, as_stream(stream), a);
+    return check_launch("sdf_labels");
+}
 
 LSDF_API int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* tris, int32_t nt,
                                  const int32_t* comp_first, int32_t ncomp, const lsdf_grid* desc,
@@ -137,25 +234,10 @@ LSDF_API int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* 
     using namespace lsdf;
     clear_error();
     if (!desc) return fail(LSDF_E_INVALID_ARG, "build_link_sdf: desc is NULL");
-    if (nv < 1 || nt < 1) return fail(LSDF_E_SHAPE, "build_link_sdf: empty mesh (nv = %d, nt = %d)", (int)nv, (int)nt);
-    if (!verts || !tris || !grid_buf) return fail(LSDF_E_INVALID_ARG, "build_link_sdf: NULL device pointer");
     BuildArgs p{};
-    if (comp_first) {
-        if (ncomp < 1 || ncomp > LSDF_MAX_COMPONENTS)
-            return fail(LSDF_E_SHAPE, "build_link_sdf: ncomp = %d out of [1, %d]", (int)ncomp, LSDF_MAX_COMPONENTS);
-        if (comp_first[0] != 0 || comp_first[ncomp] != nt)
-            return fail(LSDF_E_SHAPE, "build_link_sdf: comp_first must run from 0 to nt");
-        for (int k = 0; k <= ncomp; ++k) {
-            if (k > 0 && comp_first[k] <= comp_first[k - 1])
-                return fail(LSDF_E_SHAPE, "build_link_sdf: comp_first must increase strictly");
-            p.comp_first[k] = comp_first[k];
-        }
-        p.ncomp = ncomp;
-    } else {
-        p.comp_first[0] = 0;
-        p.comp_first[1] = nt;
-        p.ncomp = 1;
-    }
+    int rc0 = mesh_args(verts, nv, tris, nt, comp_first, ncomp, &p);
+    if (rc0 != LSDF_OK) return rc0;
+    if (!grid_buf) return fail(LSDF_E_INVALID_ARG, "build_link_sdf: grid_buf is NULL");
     LinkGrid g;
     int rc = prepare_link_grid(*desc, 0, &g);
     if (rc != LSDF_OK) return rc;
@@ -164,9 +246,6 @@ LSDF_API int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* 
         p.h[a] = (float)(((double)desc->hi[a] - (double)desc->lo[a]) / (double)(desc->n[a] - 1));
         p.n[a] = desc->n[a];
     }
-    p.nv = nv;
-    p.verts = verts;
-    p.tris = tris;
     p.out = static_cast<float*>(grid_buf) + desc->elem_offset;
     const int64_t nodes = (int64_t)p.n[0] * p.n[1] * p.n[2];
     hipLaunchKernelGGL(build_sdf_kernel, dim3((unsigned)((nodes + kBlock - 1) / kBlock)), dim3(kBlock), 0,

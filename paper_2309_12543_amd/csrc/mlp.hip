@@ -1,0 +1,697 @@
+// Learned per-link SDF surrogate: evaluation, clearance with exact-grid
+// fallback, training (forward, backward, weight gradients, Adam) and labels.
+#include <algorithm>
+#include <cmath>
+
+#include "grid_sample.hpp"
+#include "mlp_common.hpp"
+
+namespace {
+
+using namespace lsdf;
+using namespace lsdf::mlp;
+
+constexpr int kBlock = 512;                 // 8 waves
+constexpr int kWaves = kBlock / 64;
+constexpr int kSplit = 512;                 // samples per weight-gradient split
+constexpr int kBlocksPerCu = 2;             // 69 KB of LDS per block
+
+struct Domain {
+    float cen[3];
+    float inv[3];    // 1 / half
+};
+
+__device__ inline float wave_min(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// evaluation at given link-frame points
+// ---------------------------------------------------------------------------
+
+struct EvalArgs {
+    Domain d;
+    const float* params;
+    const float* points;
+    float* out;
+    int64_t N;
+    int64_t tiles;
+};
+
+__global__ __launch_bounds__(kBlock) void mlp_eval_kernel(EvalArgs p) {
+    __shared__ __bf16 sW2[WTILE_ELEMS];
+    __shared__ __bf16 sW3[WTILE_ELEMS];
+    __shared__ SmallParams sp;
+    stage_weights(sW2, p.params + OFF_W2, false);
+    stage_weights(sW3, p.params + OFF_W3, false);
+    stage_small(&sp, p.params);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t t = (int64_t)blockIdx.x * kWaves + wave; t < p.tiles; t += (int64_t)gridDim.x * kWaves) {
+        float xh[NT][3];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int64_t j = min(t * TILE + 16 * nt + (lane & 15), p.N - 1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xh[nt][a] = (p.points[3 * j + a] - p.d.cen[a]) * p.d.inv[a];
+        }
+        float m[NT];
+        forward_tile<false>(sW2, sW3, &sp, xh, m, ForwardTrace{});
+        if (lane < 16) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int64_t j = t * TILE + 16 * nt + lane;
+                if (j < p.N) p.out[j] = m[nt];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// clearance: network per pair, exact grid below the margin
+// ---------------------------------------------------------------------------
+
+struct QueryMlpArgs {
+    LinkGrid link[LSDF_MAX_LINKS];
+    Domain dom[LSDF_MAX_LINKS];
+    const float* link_T;
+    const float* params;
+    const float* grid;
+    const float* points;
+    uint32_t* keys;
+    int64_t M;
+    int64_t tiles_per_link;
+    int32_t tiles_per_c;
+    int32_t C;
+    int32_t L;
+    float margin;
+};
+
+template <bool CUBIC>
+__global__ __launch_bounds__(kBlock) void query_mlp_kernel(QueryMlpArgs p) {
+    __shared__ __bf16 sW2[WTILE_ELEMS];
+    __shared__ __bf16 sW3[WTILE_ELEMS];
+    __shared__ SmallParams sp;
+    const int i = blockIdx.y;
+    const float* P = p.params + (int64_t)i * NPARAM;
+    stage_weights(sW2, P + OFF_W2, false);
+    stage_weights(sW3, P + OFF_W3, false);
+    stage_small(&sp, P);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const LinkGrid& lg = p.link[i];
+    const Domain& dm = p.dom[i];
+    const float* G = p.grid + lg.offset;
+    const int64_t t0 = p.tiles_per_link * blockIdx.x / gridDim.x;
+    const int64_t t1 = p.tiles_per_link * (blockIdx.x + 1) / gridDim.x;
+
+    float best = INFINITY;
+    int cur = -1;
+    GridMap gm{};
+    float R[9] = {}, tr[3] = {};
+    auto flush = [&](int c) {
+        const float w = wave_min(best);
+        if (lane == 0 && w < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(w));
+        best = INFINITY;
+    };
+    for (int64_t t = t0 + wave; t < t1; t += kWaves) {
+        const int c = (int)(t / p.tiles_per_c);
+        const int64_t j0 = (t - (int64_t)c * p.tiles_per_c) * TILE;
+        if (c != cur) {
+            if (cur >= 0) flush(cur);
+            cur = c;
+            const float* T = p.link_T + ((int64_t)c * p.L + i) * 12;
+            gm = grid_map(lg, T);
+            for (int r = 0; r < 3; ++r) {
+                for (int s = 0; s < 3; ++s) R[3 * r + s] = T[4 * r + s];
+                tr[r] = T[4 * r + 3];
+            }
+        }
+        float xh[NT][3], px[NT][3];
+        bool indom[NT];
+        bool any = false;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int64_t j = j0 + 16 * nt + (lane & 15);
+            const int64_t jj = min(j, p.M - 1);
+            const float dx = p.points[3 * jj + 0] - tr[0];
+            const float dy = p.points[3 * jj + 1] - tr[1];
+            const float dz = p.points[3 * jj + 2] - tr[2];
+            px[nt][0] = p.points[3 * jj + 0];
+            px[nt][1] = p.points[3 * jj + 1];
+            px[nt][2] = p.points[3 * jj + 2];
+            float mx = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float l = fmaf(R[a], dx, fmaf(R[3 + a], dy, R[6 + a] * dz));   // (R^T d)_a
+                xh[nt][a] = (l - dm.cen[a]) * dm.inv[a];
+                mx = fmaxf(mx, fabsf(xh[nt][a]));
+            }
+            indom[nt] = (j < p.M) && (mx <= 1.0f);
+            any |= indom[nt];
+        }
+        if (!__ballot(any)) continue;
+        float m[NT];
+        forward_tile<false>(sW2, sW3, &sp, xh, m, ForwardTrace{});
+        if (lane < 16) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                if (!indom[nt]) continue;
+                const float v = m[nt] < p.margin ? sample_or_inf<CUBIC>(G, lg, gm, px[nt][0], px[nt][1], px[nt][2])
+                                                 : m[nt];
+                best = fminf(best, v);
+            }
+        }
+    }
+    if (cur >= 0) flush(cur);
+}
+
+// ---------------------------------------------------------------------------
+// training
+// ---------------------------------------------------------------------------
+
+// Per-link slices of the training workspace ([L][...] arrays).
+struct TrainBufs {
+    float* z1;      // [L][128][B]
+    float* z2;
+    float* z3;
+    float* dz1;
+    __bf16* h1;     // [L][128][B]
+    __bf16* h2;
+    __bf16* h3;
+    __bf16* dz2;
+    __bf16* dz3;
+    float* xh;      // [L][B][3]
+    float* dm;      // [L][B]
+    float* loss;    // [L][B / TILE]
+    float* gpart;   // [L][nsplit][NPARAM]
+};
+
+struct TrainArgs {
+    Domain dom[LSDF_MAX_LINKS];
+    TrainBufs w;
+    const float* params;
+    const float* samples;
+    const float* labels;
+    const int32_t* bidx;
+    int64_t N;
+    int32_t B;
+    int32_t nsplit;
+};
+
+__global__ __launch_bounds__(kBlock) void train_forward_kernel(TrainArgs p) {
+    __shared__ __bf16 sW2[WTILE_ELEMS];
+    __shared__ __bf16 sW3[WTILE_ELEMS];
+    __shared__ SmallParams sp;
+    const int l = blockIdx.y;
+    const float* P = p.params + (int64_t)l * NPARAM;
+    stage_weights(sW2, P + OFF_W2, false);
+    stage_weights(sW3, P + OFF_W3, false);
+    stage_small(&sp, P);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tt = blockIdx.x * kWaves + wave;          // tile of this wave
+    const int64_t B = p.B;
+    const int64_t lB = (int64_t)l * B;
+    float xh[NT][3];
+    int64_t idx[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int64_t s = (int64_t)tt * TILE + 16 * nt + (lane & 15);
+        int64_t k = p.bidx ? (int64_t)p.bidx[lB + s] : s;
+        k = min(max(k, (int64_t)0), p.N - 1);          // a bad index reads a valid sample
+        idx[nt] = (int64_t)l * p.N + k;
+        const Domain& d = p.dom[l];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xh[nt][a] = (p.samples[3 * idx[nt] + a] - d.cen[a]) * d.inv[a];
+        if (lane < 16) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) p.w.xh[(lB + s) * 3 + a] = xh[nt][a];
+        }
+    }
+    const int64_t plane = (int64_t)l * H * B;
+    ForwardTrace tr{p.w.z1 + plane, p.w.z2 + plane, p.w.z3 + plane, p.w.h1 + plane, p.w.h2 + plane, p.w.h3 + plane,
+                    B, (int64_t)tt * TILE};
+    float m[NT];
+    forward_tile<true>(sW2, sW3, &sp, xh, m, tr);
+    float absr = 0.0f;
+    if (lane < 16) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int64_t s = (int64_t)tt * TILE + 16 * nt + lane;
+            const float r = m[nt] - p.labels[idx[nt]];
+            p.w.dm[lB + s] = (r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f)) / (float)B;
+            absr += fabsf(r);
+        }
+    }
+    absr = wave_sum(absr);
+    if (lane == 0) p.w.loss[(int64_t)l * (B / TILE) + tt] = absr;
+}
+
+__global__ __launch_bounds__(kBlock) void train_backward_kernel(TrainArgs p) {
+    __shared__ __bf16 sW3t[WTILE_ELEMS];
+    __shared__ __bf16 sW2t[WTILE_ELEMS];
+    __shared__ float sw4[H];
+    const int l = blockIdx.y;
+    const float* P = p.params + (int64_t)l * NPARAM;
+    stage_weights(sW3t, P + OFF_W3, true);
+    stage_weights(sW2t, P + OFF_W2, true);
+    for (int u = threadIdx.x; u < H; u += blockDim.x) sw4[u] = bf16_round(P[OFF_W4 + u]);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4;
+    const int col = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tt = blockIdx.x * kWaves + wave;
+    const int64_t B = p.B;
+    const int64_t lB = (int64_t)l * B;
+    const int64_t plane = (int64_t)l * H * B;
+    const int64_t c0 = (int64_t)tt * TILE;
+
+    // dz3 = dm * w4 * SiLU'(z3), rounded: B operand of dh2 = W3^T dz3
+    bf16x8 b[4][NT];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int u = perm_unit(s, 8 * g + e);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int64_t c = c0 + 16 * nt + col;
+                const float d = p.w.dm[lB + c] * sw4[u] * silu_grad(p.w.z3[plane + u * B + c]);
+                const __bf16 db = (__bf16)d;
+                b[s][nt][e] = db;
+                p.w.dz3[plane + u * B + c] = db;
+            }
+        }
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+        const __bf16* sW = layer == 0 ? sW3t : sW2t;
+        f32x4 acc[8][NT];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const bf16x8 a = lds_a(sW, mt, s, lane);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s][nt], acc[mt][nt], 0, 0, 0);
+            }
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int u = 16 * mt + 4 * g + r;
+                    const int64_t c = c0 + 16 * nt + col;
+                    if (layer == 0) {
+                        // dz2 = (W3^T dz3) * SiLU'(z2), rounded: B operand of dh1 = W2^T dz2
+                        const __bf16 db = (__bf16)(acc[mt][nt][r] * silu_grad(p.w.z2[plane + u * B + c]));
+                        b[mt >> 1][nt][(mt & 1) * 4 + r] = db;
+                        p.w.dz2[plane + u * B + c] = db;
+                    } else {
+                        // dz1 = (W2^T dz2) * SiLU'(z1), kept in FP32
+                        p.w.dz1[plane + u * B + c] = acc[mt][nt][r] * silu_grad(p.w.z1[plane + u * B + c]);
+                    }
+                }
+    }
+}
+
+// Weight gradients over one split of the batch: dW3 = dz3^T h2 and
+// dW2 = dz2^T h1 on MFMA (K = samples), the rest on the VALU.
+__global__ __launch_bounds__(kBlock) void train_wgrad_kernel(TrainArgs p) {
+    const int l = blockIdx.y;
+    const int split = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4;
+    const int col = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t B = p.B;
+    const int64_t plane = (int64_t)l * H * B;
+    const int64_t k0 = (int64_t)split * kSplit;
+    float* gp = p.w.gpart + ((int64_t)l * p.nsplit + split) * NPARAM;
+
+    {
+        const bool third = wave < 4;
+        const int q = wave & 3;
+        const __bf16* A = (third ? p.w.dz3 : p.w.dz2) + plane;   // [out][B]
+        const __bf16* Bm = (third ? p.w.h2 : p.w.h1) + plane;    // [in][B]
+        const int r0 = 64 * (q >> 1), c0 = 64 * (q & 1);
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int64_t k = k0; k < k0 + kSplit; k += 32) {
+            bf16x8 a[4], bb[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                a[mt] = *reinterpret_cast<const bf16x8*>(A + (r0 + 16 * mt + col) * B + k + 8 * g);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                bb[nt] = *reinterpret_cast<const bf16x8*>(Bm + (c0 + 16 * nt + col) * B + k + 8 * g);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bb[nt], acc[mt][nt], 0, 0, 0);
+        }
+        const int off = third ? OFF_W3 : OFF_W2;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    gp[off + (r0 + 16 * mt + 4 * g + r) * H + (c0 + 16 * nt + col)] = acc[mt][nt][r];
+    }
+
+    // small gradients: one thread per (kind, unit)
+    const int t = threadIdx.x;
+    const int u = t & (H - 1);
+    const int kind = t >> 7;   // 0: W1 and b1, 1: b2, 2: b3, 3: w4
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    const int64_t lB = (int64_t)l * B;
+    for (int64_t k = k0; k < k0 + kSplit; ++k) {
+        if (kind == 0) {
+            const float d = p.w.dz1[plane + u * B + k];
+            const float* x = p.w.xh + (lB + k) * 3;
+            s0 = fmaf(d, x[0], s0);
+            s1 = fmaf(d, x[1], s1);
+            s2 = fmaf(d, x[2], s2);
+            s3 += d;
+        } else if (kind == 1) {
+            s0 += (float)p.w.dz2[plane + u * B + k];
+        } else if (kind == 2) {
+            s0 += (float)p.w.dz3[plane + u * B + k];
+        } else {
+            s0 = fmaf(p.w.dm[lB + k], (float)p.w.h3[plane + u * B + k], s0);
+        }
+    }
+    if (kind == 0) {
+        gp[OFF_W1 + 3 * u + 0] = s0;
+        gp[OFF_W1 + 3 * u + 1] = s1;
+        gp[OFF_W1 + 3 * u + 2] = s2;
+        gp[OFF_B1 + u] = s3;
+    } else if (kind == 1) {
+        gp[OFF_B2 + u] = s0;
+    } else if (kind == 2) {
+        gp[OFF_B3 + u] = s0;
+    } else {
+        gp[OFF_W4 + u] = s0;
+    }
+    if (t == 0) {
+        float sb = 0.f;
+        for (int64_t k = k0; k < k0 + kSplit; ++k) sb += p.w.dm[lB + k];
+        gp[OFF_B4] = sb;
+    }
+}
+
+struct ReduceArgs {
+    TrainBufs w;
+    float* params;
+    float* m;
+    float* v;
+    float* grad_out;
+    float* loss_out;
+    int32_t L;
+    int32_t B;
+    int32_t nsplit;
+    int32_t adam;
+    float lr;      // step size
+    float beta1;
+    float beta2;
+    float eps;
+    float c1;      // 1 - beta1^t
+    float c2;      // 1 - beta2^t
+};
+
+// Sums the split partials into the gradient; optionally applies Adam.
+__global__ __launch_bounds__(256) void train_reduce_kernel(ReduceArgs p) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < (int64_t)p.L * NPARAM) {
+        const int l = (int)(k / NPARAM);
+        const int pk = (int)(k - (int64_t)l * NPARAM);
+        float gsum = 0.f;
+        for (int s = 0; s < p.nsplit; ++s) gsum += p.w.gpart[((int64_t)l * p.nsplit + s) * NPARAM + pk];
+        if (p.grad_out) p.grad_out[k] = gsum;
+        if (p.adam) {
+            const float mk = p.beta1 * p.m[k] + (1.0f - p.beta1) * gsum;
+            const float vk = p.beta2 * p.v[k] + (1.0f - p.beta2) * gsum * gsum;
+            p.m[k] = mk;
+            p.v[k] = vk;
+            p.params[k] -= p.lr * (mk / p.c1) / (sqrtf(vk / p.c2) + p.eps);
+        }
+    }
+    if (p.loss_out && k < p.L) {
+        const int tiles = p.B / TILE;
+        float s = 0.f;
+        for (int t = 0; t < tiles; ++t) s += p.w.loss[k * tiles + t];
+        p.loss_out[k] = s / (float)p.B;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+
+int make_domain(const lsdf_mlp_domain& d, int index, Domain* out) {
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(d.centre[a]) || !std::isfinite(d.half[a]) || !(d.half[a] > 0.0f))
+            return fail(LSDF_E_INVALID_ARG, "mlp domain %d: centre must be finite and half > 0", index);
+        out->cen[a] = d.centre[a];
+        out->inv[a] = (float)(1.0 / (double)d.half[a]);
+    }
+    return LSDF_OK;
+}
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return cus;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Carves the training workspace; returns the bytes it needs.
+size_t train_layout(int32_t L, int32_t B, char* base, TrainBufs* w) {
+    const size_t f_plane = align256((size_t)L * H * B * sizeof(float));
+    const size_t h_plane = align256((size_t)L * H * B * sizeof(__bf16));
+    const int nsplit = B / kSplit;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    TrainBufs t{};
+    t.z1 = (float*)take(f_plane);
+    t.z2 = (float*)take(f_plane);
+    t.z3 = (float*)take(f_plane);
+    t.dz1 = (float*)take(f_plane);
+    t.h1 = (__bf16*)take(h_plane);
+    t.h2 = (__bf16*)take(h_plane);
+    t.h3 = (__bf16*)take(h_plane);
+    t.dz2 = (__bf16*)take(h_plane);
+    t.dz3 = (__bf16*)take(h_plane);
+    t.xh = (float*)take((size_t)L * B * 3 * sizeof(float));
+    t.dm = (float*)take((size_t)L * B * sizeof(float));
+    t.loss = (float*)take((size_t)L * (B / TILE) * sizeof(float));
+    t.gpart = (float*)take((size_t)L * nsplit * NPARAM * sizeof(float));
+    if (w) *w = t;
+    return off;
+}
+
+int check_train_sizes(int32_t L, int32_t B, int64_t N) {
+    if (L < 1 || L > LSDF_MAX_LINKS) return fail(LSDF_E_SHAPE, "mlp train: L = %d out of [1, %d]", (int)L, LSDF_MAX_LINKS);
+    if (B < kSplit || B % kSplit != 0) return fail(LSDF_E_SHAPE, "mlp train: B = %d must be a positive multiple of %d", (int)B, kSplit);
+    if (N < 1) return fail(LSDF_E_SHAPE, "mlp train: N = %lld < 1", (long long)N);
+    return LSDF_OK;
+}
+
+int train_common(const float* params, float* adam_m, float* adam_v, int64_t t, float lr, float beta1, float beta2,
+                 float eps, bool adam, const lsdf_mlp_domain* domains, int32_t L, const float* samples,
+                 const float* labels, int64_t N, const int32_t* batch_index, int32_t B, float* loss_out,
+                 float* grad_out, void* workspace, size_t ws_bytes, void* stream) {
+    int rc = check_train_sizes(L, B, N);
+    if (rc != LSDF_OK) return rc;
+    if (!params || !domains || !samples || !labels || !workspace)
+        return fail(LSDF_E_INVALID_ARG, "mlp train: NULL pointer");
+    if (adam && (!adam_m || !adam_v)) return fail(LSDF_E_INVALID_ARG, "mlp train: NULL Adam moments");
+    if (adam && t < 1) return fail(LSDF_E_INVALID_ARG, "mlp train: step t = %lld < 1", (long long)t);
+    if (adam && !(std::isfinite(lr) && std::isfinite(beta1) && std::isfinite(beta2) && std::isfinite(eps) &&
+                  beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps >= 0.f))
+        return fail(LSDF_E_INVALID_ARG, "mlp train: bad Adam hyper-parameters");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(LSDF_E_INVALID_ARG, "mlp train: workspace is not 256-byte aligned");
+    const size_t need = train_layout(L, B, nullptr, nullptr);
+    if (ws_bytes < need) return fail(LSDF_E_SHAPE, "mlp train: workspace has %zu bytes, needs %zu", ws_bytes, need);
+    TrainArgs a{};
+    for (int i = 0; i < L; ++i) {
+        rc = make_domain(domains[i], i, &a.dom[i]);
+        if (rc != LSDF_OK) return rc;
+    }
+    train_layout(L, B, static_cast<char*>(workspace), &a.w);
+    a.params = params;
+    a.samples = samples;
+    a.labels = labels;
+    a.bidx = batch_index;
+    a.N = N;
+    a.B = B;
+    a.nsplit = B / kSplit;
+    hipStream_t s = as_stream(stream);
+    const dim3 tiles_grid(B / (TILE * kWaves), L);
+    hipLaunchKernelGGL(train_forward_kernel, tiles_grid, dim3(kBlock), 0, s, a);
+    if ((rc = check_launch("mlp train forward")) != LSDF_OK) return rc;
+    hipLaunchKernelGGL(train_backward_kernel, tiles_grid, dim3(kBlock), 0, s, a);
+    if ((rc = check_launch("mlp train backward")) != LSDF_OK) return rc;
+    hipLaunchKernelGGL(train_wgrad_kernel, dim3(a.nsplit, L), dim3(kBlock), 0, s, a);
+    if ((rc = check_launch("mlp train weight gradients")) != LSDF_OK) return rc;
+    ReduceArgs r{};
+    r.w = a.w;
+    r.params = const_cast<float*>(params);
+    r.m = adam_m;
+    r.v = adam_v;
+    r.grad_out = grad_out;
+    r.loss_out = loss_out;
+    r.L = L;
+    r.B = B;
+    r.nsplit = a.nsplit;
+    r.adam = adam ? 1 : 0;
+    if (adam) {
+        r.lr = lr;
+        r.beta1 = beta1;
+        r.beta2 = beta2;
+        r.eps = eps;
+        r.c1 = (float)(1.0 - std::pow((double)beta1, (double)t));
+        r.c2 = (float)(1.0 - std::pow((double)beta2, (double)t));
+    }
+    const int64_t total = (int64_t)L * NPARAM;
+    hipLaunchKernelGGL(train_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, r);
+    return check_launch("mlp train reduce");
+}
+
+}  // namespace
+
+LSDF_API int lsdf_mlp_eval(const float* params, const lsdf_mlp_domain* domain, const float* points, int64_t N,
+                           float* out, void* stream) {
+    clear_error();
+    if (!domain) return fail(LSDF_E_INVALID_ARG, "mlp_eval: domain is NULL");
+    if (N < 0) return fail(LSDF_E_SHAPE, "mlp_eval: N < 0");
+    if (N == 0) return LSDF_OK;
+    if (!params || !points || !out) return fail(LSDF_E_INVALID_ARG, "mlp_eval: NULL device pointer");
+    EvalArgs a{};
+    int rc = make_domain(*domain, 0, &a.d);
+    if (rc != LSDF_OK) return rc;
+    const int cus = device_cus();
+    if (cus <= 0) return fail(LSDF_E_DEVICE, "mlp_eval: cannot read the device's compute-unit count");
+    a.params = params;
+    a.points = points;
+    a.out = out;
+    a.N = N;
+    a.tiles = (N + TILE - 1) / TILE;
+    const int64_t blocks = std::min<int64_t>((int64_t)cus * kBlocksPerCu, (a.tiles + kWaves - 1) / kWaves);
+    hipLaunchKernelGGL(mlp_eval_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, as_stream(stream), a);
+    return check_launch("mlp_eval");
+}
+
+LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t L, const lsdf_grid* grids,
+                                         const void* grid_buf, const float* mlp_params, const lsdf_mlp_domain* domains,
+                                         float margin, const float* points, int64_t M, float* out_dist,
+                                         int32_t* out_link, float* out_link_dist, uint32_t flags, void* workspace,
+                                         size_t ws_bytes, void* stream) {
+    clear_error();
+    if (flags != 0) return fail(LSDF_E_UNSUPPORTED, "query_mlp: unsupported flags 0x%x", flags);
+    if (C < 0 || M < 0) return fail(LSDF_E_SHAPE, "query_mlp: negative size");
+    if (L < 1 || L > LSDF_MAX_LINKS) return fail(LSDF_E_SHAPE, "query_mlp: L = %d out of [1, %d]", (int)L, LSDF_MAX_LINKS);
+    if (!grids || !domains) return fail(LSDF_E_INVALID_ARG, "query_mlp: grids or domains is NULL");
+    if (std::isnan(margin)) return fail(LSDF_E_INVALID_ARG, "query_mlp: margin is NaN");
+    if (C == 0) return LSDF_OK;
+    if (!link_T || !grid_buf || !mlp_params || !out_dist || !out_link || !workspace)
+        return fail(LSDF_E_INVALID_ARG, "query_mlp: NULL device pointer");
+    if (M > 0 && !points) return fail(LSDF_E_INVALID_ARG, "query_mlp: points is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(LSDF_E_INVALID_ARG, "query_mlp: workspace is not 256-byte aligned");
+    size_t need = 0;
+    int rc = lsdf_query_workspace_size(C, L, M, &need);
+    if (rc != LSDF_OK) return rc;
+    if (ws_bytes < need) return fail(LSDF_E_SHAPE, "query_mlp: workspace has %zu bytes, needs %zu", ws_bytes, need);
+    QueryMlpArgs a{};
+    bool cubic = true;
+    for (int i = 0; i < L; ++i) {
+        if ((rc = prepare_link_grid(grids[i], i, &a.link[i])) != LSDF_OK) return rc;
+        if ((rc = make_domain(domains[i], i, &a.dom[i])) != LSDF_OK) return rc;
+        cubic = cubic && a.link[i].cubic;
+    }
+    hipStream_t s = as_stream(stream);
+    a.link_T = link_T;
+    a.params = mlp_params;
+    a.grid = static_cast<const float*>(grid_buf);
+    a.points = points;
+    a.keys = static_cast<uint32_t*>(workspace);
+    a.M = M;
+    a.C = C;
+    a.L = L;
+    a.margin = margin;
+    a.tiles_per_c = (int32_t)((M + TILE - 1) / TILE);
+    a.tiles_per_link = (int64_t)C * a.tiles_per_c;
+    if (a.tiles_per_link > 0) {
+        const int cus = device_cus();
+        if (cus <= 0) return fail(LSDF_E_DEVICE, "query_mlp: cannot read the device's compute-unit count");
+        const int64_t per_link = std::max<int64_t>(
+            1, std::min<int64_t>(((int64_t)cus * kBlocksPerCu + L - 1) / L, (a.tiles_per_link + kWaves - 1) / kWaves));
+        const dim3 grid((unsigned)per_link, L);
+        if (cubic)
+            hipLaunchKernelGGL(query_mlp_kernel<true>, grid, dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL(query_mlp_kernel<false>, grid, dim3(kBlock), 0, s, a);
+        if ((rc = check_launch("query_min_distance_mlp")) != LSDF_OK) return rc;
+    }
+    return lsdf::launch_query_finalize(static_cast<uint32_t*>(workspace), out_dist, out_link, out_link_dist, C, L, s);
+}
+
+LSDF_API int lsdf_mlp_train_workspace_size(int32_t L, int32_t B, size_t* bytes) {
+    clear_error();
+    if (!bytes) return fail(LSDF_E_INVALID_ARG, "mlp_train_workspace_size: bytes is NULL");
+    int rc = check_train_sizes(L, B, 1);
+    if (rc != LSDF_OK) return rc;
+    *bytes = train_layout(L, B, nullptr, nullptr);
+    return LSDF_OK;
+}
+
+LSDF_API int lsdf_mlp_loss_grad(const float* params, const lsdf_mlp_domain* domains, int32_t L, const float* samples,
+                                const float* labels, int64_t N, const int32_t* batch_index, int32_t B, float* loss_out,
+                                float* grad_out, void* workspace, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (!grad_out) return fail(LSDF_E_INVALID_ARG, "mlp_loss_grad: grad_out is NULL");
+    return train_common(params, nullptr, nullptr, 0, 0.f, 0.f, 0.f, 0.f, false, domains, L, samples, labels, N,
+                        batch_index, B, loss_out, grad_out, workspace, ws_bytes, stream);
+}
+
+LSDF_API int lsdf_mlp_train_step(float* params, float* adam_m, float* adam_v, int64_t t, float lr, float beta1,
+                                 float beta2, float eps, const lsdf_mlp_domain* domains, int32_t L,
+                                 const float* samples, const float* labels, int64_t N, const int32_t* batch_index,
+                                 int32_t B, float* loss_out, float* grad_out, void* workspace, size_t ws_bytes,
+                                 void* stream) {
+    clear_error();
+    return train_common(params, adam_m, adam_v, t, lr, beta1, beta2, eps, true, domains, L, samples, labels, N,
+                        batch_index, B, loss_out, grad_out, workspace, ws_bytes, stream);
+}

@@ -23,11 +23,15 @@
 //     kernel boundary orders it after every atomic, with no device fence).
 #include <algorithm>
 
-#include "lsdf_internal.hpp"
+#include "grid_sample.hpp"
 
 namespace {
 
 using lsdf::LinkGrid;
+using lsdf::Cell;
+using lsdf::inside;
+using lsdf::interpolate;
+using lsdf::locate;
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
@@ -70,51 +74,6 @@ struct FinalizeArgs {
     int32_t C;
     int32_t L;
 };
-
-__device__ inline float lerp_exact_ends(float a, float b, float t) {
-    return fmaf(t, b, fmaf(-t, a, a));
-}
-
-template <bool CUBIC>
-__device__ inline bool inside(const LinkGrid& g, float v0, float v1, float v2) {
-    if (CUBIC) return fmaxf(fabsf(v0), fmaxf(fabsf(v1), fabsf(v2))) <= g.half[0];
-    return (fabsf(v0) <= g.half[0]) & (fabsf(v1) <= g.half[1]) & (fabsf(v2) <= g.half[2]);
-}
-
-// One cell gather: element index of the cell's lower corner and the three
-// fractions, from centred coordinates known to be inside the box.
-struct Cell {
-    int idx;
-    float fx, fy, fz;
-};
-
-__device__ inline Cell locate(const LinkGrid& g, float v0, float v1, float v2) {
-    const float u0 = v0 + g.half[0];
-    const float u1 = v1 + g.half[1];
-    const float u2 = v2 + g.half[2];
-    // u >= 0 here, so truncation is the floor
-    const int ix = min((int)u0, g.n[0] - 2);
-    const int iy = min((int)u1, g.n[1] - 2);
-    const int iz = min((int)u2, g.n[2] - 2);
-    Cell c;
-    c.fx = u0 - (float)ix;
-    c.fy = u1 - (float)iy;
-    c.fz = u2 - (float)iz;
-    c.idx = (iz * g.n[1] + iy) * g.n[0] + ix;
-    return c;
-}
-
-// Trilinear value of a cell from its corners (x first, then y, then z).
-__device__ inline float interpolate(float c000, float c100, float c010, float c110, float c001, float c101,
-                                    float c011, float c111, const Cell& cl) {
-    const float e00 = lerp_exact_ends(c000, c100, cl.fx);
-    const float e10 = lerp_exact_ends(c010, c110, cl.fx);
-    const float e01 = lerp_exact_ends(c001, c101, cl.fx);
-    const float e11 = lerp_exact_ends(c011, c111, cl.fx);
-    const float e0 = lerp_exact_ends(e00, e10, cl.fy);
-    const float e1 = lerp_exact_ends(e01, e11, cl.fy);
-    return lerp_exact_ends(e0, e1, cl.fz) + 0.0f;   // -0 -> +0
-}
 
 template <bool CUBIC>
 __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float* __restrict__ points,
@@ -243,6 +202,17 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs p) {
     p.out_link[c] = arg;
 }
 
+}  // namespace
+
+int lsdf::launch_query_finalize(uint32_t* keys, float* out_dist, int32_t* out_link, float* out_link_dist, int32_t C,
+                                int32_t L, hipStream_t s) {
+    FinalizeArgs f{keys, out_dist, out_link, out_link_dist, C, L};
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((C + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, f);
+    return check_launch("query finalize");
+}
+
+namespace {
+
 size_t keys_bytes(int64_t C, int64_t L) { return ((size_t)(C * L) * 4 + 255) / 256 * 256; }
 
 int device_cus() {
@@ -316,7 +286,5 @@ LSDF_API int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L, 
         int rc = check_launch("query_min_distance");
         if (rc != LSDF_OK) return rc;
     }
-    FinalizeArgs f{p.keys, out_dist, out_link, out_link_dist, C, L};
-    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((C + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, f);
-    return check_launch("query_min_distance (finalize)");
+    return launch_query_finalize(p.keys, out_dist, out_link, out_link_dist, C, L, s);
 }

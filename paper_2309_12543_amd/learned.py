@@ -1,0 +1,63 @@
+"""Host-side driver of the learned per-link SDF surrogate.
+
+The arithmetic (labels, forward, backward, Adam, evaluation) runs in
+liblsdf.so; this module only sequences the calls: it computes labels for
+given sample positions, shuffles sample indices per epoch and steps the
+optimiser.  The paper trains its own small network with an L1 loss and Adam
+at learning rate 1e-4 (Sec. IV-B); the same loss and optimiser are used here.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import lsdf
+
+
+def labels_for_samples(meshes, grids: lsdf.GridSet, samples: torch.Tensor) -> torch.Tensor:
+    """Labels [L][N]: grid value inside each link's box, exact mesh distance
+    outside (lsdf_sdf_labels), for link-frame samples [L][N][3]."""
+    L, N = int(samples.shape[0]), int(samples.shape[1])
+    out = torch.empty((L, N), dtype=torch.float32, device=samples.device)
+    for i, m in enumerate(meshes):
+        v = torch.as_tensor(np.asarray(m.verts, dtype=np.float32), device=samples.device)
+        t = torch.as_tensor(np.asarray(m.tris, dtype=np.int32), device=samples.device)
+        lsdf.sdf_labels(v, t, m.comp_first, grids, i, samples[i], out=out[i])
+    return out
+
+
+def train(params: torch.Tensor, domains, samples: torch.Tensor, labels: torch.Tensor, *, epochs: int,
+          batch: int = 4096, lr: float = 1e-4, lr_final: float | None = None, seed: int = 0,
+          log_every: int = 0, log=print):
+    """Adam on every link's network at once; params [L][33665] is updated in
+    place.  The learning rate follows a cosine from ``lr`` to ``lr_final``
+    (constant when lr_final is None).  Returns the per-epoch mean loss [L]."""
+    L, N = int(samples.shape[0]), int(samples.shape[1])
+    dev = params.device
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    ws = torch.empty(lsdf.mlp_train_workspace_size(L, batch), dtype=torch.uint8, device=dev)
+    loss = torch.empty(L, dtype=torch.float32, device=dev)
+    doms = domains if not isinstance(domains, tuple) else lsdf.make_domains(*domains)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    steps_per_epoch = N // batch
+    total = epochs * steps_per_epoch
+    history = []
+    t = 0
+    for ep in range(epochs):
+        perm = torch.stack([torch.randperm(N, generator=gen, device=dev) for _ in range(L)]).to(torch.int32)
+        acc = torch.zeros(L, dtype=torch.float32, device=dev)
+        for k in range(steps_per_epoch):
+            t += 1
+            rate = lr if lr_final is None else lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * t / total))
+            idx = perm[:, k * batch:(k + 1) * batch].contiguous()
+            lsdf.mlp_train_step(params, m, v, t, rate, doms, samples, labels, batch, idx, loss=loss, workspace=ws)
+            acc += loss
+        history.append((acc / max(1, steps_per_epoch)).cpu().numpy())
+        if log_every and (ep + 1) % log_every == 0:
+            log(f"[train] epoch {ep + 1}/{epochs}: mean L1 per link (mm) "
+                + " ".join(f"{1e3 * x:.2f}" for x in history[-1]))
+    return np.array(history)

@@ -23,6 +23,8 @@ LSDF_F32, LSDF_BF16, LSDF_F16 = 0, 1, 2
 LSDF_MAX_LINKS = 16
 LSDF_MAX_DOF = 15
 LSDF_MAX_COMPONENTS = 16
+LSDF_MLP_HIDDEN = 128
+LSDF_MLP_PARAMS = 33665
 
 DTYPE_CODES = {torch.float32: LSDF_F32}
 
@@ -36,6 +38,10 @@ class LsdfError(RuntimeError):
 class lsdf_grid(ct.Structure):
     _fields_ = [("lo", ct.c_float * 3), ("hi", ct.c_float * 3), ("n", ct.c_int32 * 3),
                 ("dtype", ct.c_int32), ("elem_offset", ct.c_int64)]
+
+
+class lsdf_mlp_domain(ct.Structure):
+    _fields_ = [("centre", ct.c_float * 3), ("half", ct.c_float * 3)]
 
 
 class lsdf_dh(ct.Structure):
@@ -70,6 +76,23 @@ def load_library():
     lib.lsdf_build_link_sdf.restype = ct.c_int
     lib.lsdf_build_link_sdf.argtypes = [vp, i32, vp, i32, ct.POINTER(ct.c_int32), i32, ct.POINTER(lsdf_grid),
                                         vp, vp]
+    fp = ct.POINTER(ct.c_float)
+    dom = ct.POINTER(lsdf_mlp_domain)
+    lib.lsdf_mlp_eval.restype = ct.c_int
+    lib.lsdf_mlp_eval.argtypes = [vp, dom, vp, i64, vp, vp]
+    lib.lsdf_query_min_distance_mlp.restype = ct.c_int
+    lib.lsdf_query_min_distance_mlp.argtypes = [vp, i32, i32, ct.POINTER(lsdf_grid), vp, vp, dom, ct.c_float, vp, i64,
+                                                vp, vp, vp, u32, vp, sz, vp]
+    lib.lsdf_mlp_train_workspace_size.restype = ct.c_int
+    lib.lsdf_mlp_train_workspace_size.argtypes = [i32, i32, ct.POINTER(sz)]
+    lib.lsdf_mlp_loss_grad.restype = ct.c_int
+    lib.lsdf_mlp_loss_grad.argtypes = [vp, dom, i32, vp, vp, i64, vp, i32, vp, vp, vp, sz, vp]
+    lib.lsdf_mlp_train_step.restype = ct.c_int
+    lib.lsdf_mlp_train_step.argtypes = [vp, vp, vp, i64, ct.c_float, ct.c_float, ct.c_float, ct.c_float, dom, i32,
+                                        vp, vp, i64, vp, i32, vp, vp, vp, sz, vp]
+    lib.lsdf_sdf_labels.restype = ct.c_int
+    lib.lsdf_sdf_labels.argtypes = [vp, i32, vp, i32, ct.POINTER(ct.c_int32), i32, ct.POINTER(lsdf_grid), vp, vp,
+                                    i64, vp, vp]
     _lib = lib
     return lib
 
@@ -265,3 +288,162 @@ def build_robot_grids(meshes, lo, hi, n, device="cuda", stream=None) -> GridSet:
         t = torch.as_tensor(np.asarray(m.tris, dtype=np.int32), device=device)
         build_link_sdf(v, t, m.comp_first, gs, i, stream=stream)
     return gs
+
+
+# ---------------------------------------------------------------------------
+# learned per-link SDF surrogate
+# ---------------------------------------------------------------------------
+
+def make_domains(centre, half):
+    """ctypes array of lsdf_mlp_domain from [L][3] centres and half extents."""
+    centre = np.asarray(centre, dtype=np.float32).reshape(-1, 3)
+    half = np.asarray(half, dtype=np.float32).reshape(-1, 3)
+    arr = (lsdf_mlp_domain * centre.shape[0])()
+    for i in range(centre.shape[0]):
+        for a in range(3):
+            arr[i].centre[a] = float(centre[i, a])
+            arr[i].half[a] = float(half[i, a])
+    return arr
+
+
+def mlp_eval(params: torch.Tensor, domain, points: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """Network outputs of one link at link-frame points [N][3] (lsdf_mlp_eval)."""
+    lib = load_library()
+    _require(params, "params", torch.float32, (LSDF_MLP_PARAMS,))
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be [N][3]")
+    _require(points, "points", torch.float32)
+    N = int(points.shape[0])
+    if out is None:
+        out = torch.empty(N, dtype=torch.float32, device=points.device)
+    _require(out, "out", torch.float32, (N,))
+    d = domain if isinstance(domain, ct.Array) else make_domains(*domain)
+    _check(lib.lsdf_mlp_eval(params.data_ptr(), d, points.data_ptr() if N else None, N, out.data_ptr(),
+                             _stream_handle(stream, points.device)))
+    return out
+
+
+def query_min_distance_mlp(link_T: torch.Tensor, grids: GridSet, mlp_params: torch.Tensor, domains,
+                           points: torch.Tensor, *, margin: float = 0.05, link_dist: bool = False,
+                           workspace: torch.Tensor | None = None, out=None, stream=None):
+    """Clearance with the learned surrogate and exact-grid fallback below
+    ``margin`` (lsdf_query_min_distance_mlp)."""
+    lib = load_library()
+    if link_T.dim() != 4 or tuple(link_T.shape[2:]) != (3, 4):
+        raise ValueError("link_T must be [C][L][3][4]")
+    _require(link_T, "link_T", torch.float32)
+    C, L = int(link_T.shape[0]), int(link_T.shape[1])
+    if L != grids.L:
+        raise ValueError(f"link_T has {L} links, grids has {grids.L}")
+    _require(mlp_params, "mlp_params", torch.float32, (L, LSDF_MLP_PARAMS))
+    d = domains if isinstance(domains, ct.Array) else make_domains(*domains)
+    if len(d) != L:
+        raise ValueError("one domain per link required")
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be [M][3]")
+    _require(points, "points", torch.float32)
+    M = int(points.shape[0])
+    dev = link_T.device
+    if out is None:
+        dist = torch.empty(C, dtype=torch.float32, device=dev)
+        link = torch.empty(C, dtype=torch.int32, device=dev)
+        ld = torch.empty((C, L), dtype=torch.float32, device=dev) if link_dist else None
+    else:
+        dist, link, ld = out
+    _require(dist, "out_dist", torch.float32, (C,))
+    _require(link, "out_link", torch.int32, (C,))
+    if ld is not None:
+        _require(ld, "out_link_dist", torch.float32, (C, L))
+    if workspace is None:
+        workspace = query_workspace(C, L, M, dev)
+    _require(workspace, "workspace", torch.uint8)
+    _check(lib.lsdf_query_min_distance_mlp(
+        link_T.data_ptr(), C, L, grids.desc, grids.buf.data_ptr(), mlp_params.data_ptr(), d, float(margin),
+        points.data_ptr() if M > 0 else None, M, dist.data_ptr(), link.data_ptr(),
+        ld.data_ptr() if ld is not None else None, 0, workspace.data_ptr(), workspace.numel(),
+        _stream_handle(stream, dev)))
+    return (dist, link, ld) if link_dist else (dist, link)
+
+
+def mlp_train_workspace_size(L: int, B: int) -> int:
+    n = ct.c_size_t(0)
+    _check(load_library().lsdf_mlp_train_workspace_size(L, B, ct.byref(n)))
+    return int(n.value)
+
+
+def _train_args(params, domains, samples, labels, batch_index, B):
+    if params.dim() != 2 or params.shape[1] != LSDF_MLP_PARAMS:
+        raise ValueError("params must be [L][33665]")
+    L = int(params.shape[0])
+    if samples.dim() != 3 or samples.shape[0] != L or samples.shape[2] != 3:
+        raise ValueError("samples must be [L][N][3]")
+    N = int(samples.shape[1])
+    _require(samples, "samples", torch.float32)
+    _require(labels, "labels", torch.float32, (L, N))
+    if batch_index is not None:
+        _require(batch_index, "batch_index", torch.int32, (L, B))
+    d = domains if isinstance(domains, ct.Array) else make_domains(*domains)
+    if len(d) != L:
+        raise ValueError("one domain per link required")
+    return L, N, d
+
+
+def mlp_loss_grad(params, domains, samples, labels, B, batch_index=None, workspace=None, stream=None):
+    """(loss [L], gradient [L][33665]) of the mean absolute error over B
+    samples per link (lsdf_mlp_loss_grad)."""
+    lib = load_library()
+    _require(params, "params", torch.float32)
+    L, N, d = _train_args(params, domains, samples, labels, batch_index, B)
+    dev = params.device
+    loss = torch.empty(L, dtype=torch.float32, device=dev)
+    grad = torch.empty_like(params)
+    if workspace is None:
+        workspace = torch.empty(mlp_train_workspace_size(L, B), dtype=torch.uint8, device=dev)
+    _check(lib.lsdf_mlp_loss_grad(params.data_ptr(), d, L, samples.data_ptr(), labels.data_ptr(), N,
+                                  batch_index.data_ptr() if batch_index is not None else None, B, loss.data_ptr(),
+                                  grad.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream_handle(stream, dev)))
+    return loss, grad
+
+
+def mlp_train_step(params, adam_m, adam_v, t, lr, domains, samples, labels, B, batch_index=None, *,
+                   beta1=0.9, beta2=0.999, eps=1e-8, loss=None, grad=None, workspace=None, stream=None):
+    """One Adam step on every link's network (lsdf_mlp_train_step); updates
+    params, adam_m and adam_v in place."""
+    lib = load_library()
+    for name, tns in (("params", params), ("adam_m", adam_m), ("adam_v", adam_v)):
+        _require(tns, name, torch.float32, tuple(params.shape))
+    L, N, d = _train_args(params, domains, samples, labels, batch_index, B)
+    dev = params.device
+    if workspace is None:
+        workspace = torch.empty(mlp_train_workspace_size(L, B), dtype=torch.uint8, device=dev)
+    _check(lib.lsdf_mlp_train_step(params.data_ptr(), adam_m.data_ptr(), adam_v.data_ptr(), int(t), float(lr),
+                                   float(beta1), float(beta2), float(eps), d, L, samples.data_ptr(), labels.data_ptr(),
+                                   N, batch_index.data_ptr() if batch_index is not None else None, B,
+                                   loss.data_ptr() if loss is not None else None,
+                                   grad.data_ptr() if grad is not None else None, workspace.data_ptr(),
+                                   workspace.numel(), _stream_handle(stream, dev)))
+
+
+def sdf_labels(verts: torch.Tensor, tris: torch.Tensor, comp_first, grids: GridSet, index: int,
+               points: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """Training labels of link ``index`` at link-frame points: grid value in
+    the box, exact mesh distance outside (lsdf_sdf_labels)."""
+    lib = load_library()
+    _require(verts, "verts", torch.float32)
+    _require(tris, "tris", torch.int32)
+    _require(points, "points", torch.float32)
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be [N][3]")
+    N = int(points.shape[0])
+    if out is None:
+        out = torch.empty(N, dtype=torch.float32, device=points.device)
+    _require(out, "out", torch.float32, (N,))
+    cf_p, ncomp = None, 0
+    if comp_first is not None:
+        cf = np.ascontiguousarray(np.asarray(comp_first, dtype=np.int32))
+        ncomp = cf.shape[0] - 1
+        cf_p = cf.ctypes.data_as(ct.POINTER(ct.c_int32))
+    _check(lib.lsdf_sdf_labels(verts.data_ptr(), int(verts.shape[0]), tris.data_ptr(), int(tris.shape[0]), cf_p, ncomp,
+                               ct.pointer(grids.desc[index]), grids.buf.data_ptr(),
+                               points.data_ptr() if N else None, N, out.data_ptr(), _stream_handle(stream, points.device)))
+    return out

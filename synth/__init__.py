@@ -4,7 +4,7 @@ parameters and meshes, waypoints, obstacle clouds, grid boxes); none of the
 distance method's arithmetic is here.
 
 Base seed 230912543; sub-streams: DH and meshes S+0, waypoints S+2+100*traj,
-scene S+3+100*traj.
+scene S+3+100*traj, network samples S+4+link, network initial weights S+5.
 """
 from __future__ import annotations
 
@@ -12,7 +12,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .robot import GRID_PAD, Mesh, Robot, box_mesh, capsule_mesh, grid_box, make_robot, sphere_mesh, union_mesh
+from .robot import (GRID_PAD, MLP_FAR, Mesh, Robot, box_mesh, capsule_mesh, grid_box, make_robot, mlp_domain, mlp_init,
+                    mlp_samples, sphere_mesh, surface_points, union_mesh)
 from .scene import human_table, uniform_cube
 from .traj import make_waypoints
 
@@ -85,4 +86,5 @@ def make_workload(name: str = "tiny", C: int | None = None, M: int | None = None
 
 __all__ = ["BASE_SEED", "GRID_PAD", "Mesh", "Robot", "Workload", "WORKLOADS", "box_mesh",
            "capsule_mesh", "grid_box", "human_table", "make_robot", "make_waypoints",
-           "make_workload", "sphere_mesh", "uniform_cube", "union_mesh"]
+           "make_workload", "sphere_mesh", "uniform_cube", "union_mesh", "MLP_FAR", "mlp_domain", "mlp_init",
+           "mlp_samples", "surface_points"]

@@ -233,3 +233,59 @@ def grid_box(mesh: Mesh, pad: float = GRID_PAD):
     lo = mesh.verts.min(axis=0) - pad
     hi = mesh.verts.max(axis=0) + pad
     return lo, hi
+
+
+# ----------------------------------------------------------------------------
+# Samples for the learned per-link SDF (input generation only: positions and
+# initial weights; labels are computed by the library or the oracle)
+# ----------------------------------------------------------------------------
+
+MLP_FAR = 1.0      # metres the network's domain extends beyond the grid box
+
+
+def mlp_domain(lo, hi, far: float = MLP_FAR):
+    """Centre and half extent of a link's network domain: its grid box grown
+    by `far` on every side."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    return (lo + hi) / 2, (hi - lo) / 2 + far
+
+
+def surface_points(mesh: Mesh, n: int, rng: np.random.Generator) -> np.ndarray:
+    """Uniform points on the mesh surface (area-weighted triangles, uniform
+    barycentric coordinates)."""
+    a, b, c = (mesh.verts[mesh.tris[:, k]] for k in range(3))
+    area = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+    t = rng.choice(len(area), size=n, p=area / area.sum())
+    r1, r2 = rng.uniform(size=n), rng.uniform(size=n)
+    s = np.sqrt(r1)
+    return ((1 - s)[:, None] * a[t] + (s * (1 - r2))[:, None] * b[t] + (s * r2)[:, None] * c[t])
+
+
+def mlp_samples(mesh: Mesh, lo, hi, n: int, seed: int, far: float = MLP_FAR, sigma: float = 0.02):
+    """n link-frame training positions: 40 % near the surface (surface point +
+    N(0, sigma)), 30 % uniform in the grid box, 30 % uniform in the domain."""
+    rng = np.random.default_rng(seed)
+    n_s, n_b = int(0.4 * n), int(0.3 * n)
+    n_d = n - n_s - n_b
+    cen, half = mlp_domain(lo, hi, far)
+    near = surface_points(mesh, n_s, rng) + rng.normal(0.0, sigma, size=(n_s, 3))
+    box = rng.uniform(lo, hi, size=(n_b, 3))
+    dom = rng.uniform(cen - half, cen + half, size=(n_d, 3))
+    pts = np.concatenate([near, box, dom])
+    return pts[rng.permutation(n)]
+
+
+def mlp_init(n_links: int, seed: int, hidden: int = 128) -> np.ndarray:
+    """Initial parameters [n_links][33665]: every weight and bias uniform in
+    +-1/sqrt(fan_in) (the common default for fully connected layers)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_links):
+        parts = []
+        for fan_in, fan_out in ((3, hidden), (hidden, hidden), (hidden, hidden), (hidden, 1)):
+            bound = 1.0 / np.sqrt(fan_in)
+            parts.append(rng.uniform(-bound, bound, size=fan_out * fan_in))
+            parts.append(rng.uniform(-bound, bound, size=fan_out))
+        out.append(np.concatenate(parts))
+    return np.stack(out)

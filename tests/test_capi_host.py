@@ -124,3 +124,38 @@ def test_build_argument_errors(lib):
     bad = (ct.c_int32 * 3)(0, 0, 12)                       # empty part
     assert lib.lsdf_build_link_sdf(FAKE, 8, FAKE, 12, bad, 2, g, FAKE, None) == B.LSDF_E_SHAPE
     assert lib.lsdf_build_link_sdf(FAKE, 8, FAKE, 12, cf, 17, g, FAKE, None) == B.LSDF_E_SHAPE
+
+
+def test_mlp_argument_errors(lib):
+    from paper_2309_12543_amd import lsdf as B
+    n = ct.c_size_t(0)
+    assert lib.lsdf_mlp_train_workspace_size(7, 4096, ct.byref(n)) == 0 and n.value > 7 * 4096 * 128 * 4
+    assert lib.lsdf_mlp_train_workspace_size(7, 1000, ct.byref(n)) == B.LSDF_E_SHAPE     # not a multiple of 512
+    assert lib.lsdf_mlp_train_workspace_size(0, 4096, ct.byref(n)) == B.LSDF_E_SHAPE
+    dom = B.make_domains([[0, 0, 0], [0, 0, 0]], [[1, 1, 1], [1, 1, 1]])
+    bad = B.make_domains([[0, 0, 0]], [[1, 0, 1]])
+    # lsdf_mlp_eval: domain NULL, half <= 0, N < 0, N = 0 no-op
+    assert lib.lsdf_mlp_eval(FAKE, None, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG
+    assert lib.lsdf_mlp_eval(FAKE, bad, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG
+    assert lib.lsdf_mlp_eval(FAKE, dom, FAKE, -1, FAKE, None) == B.LSDF_E_SHAPE
+    assert lib.lsdf_mlp_eval(FAKE, dom, FAKE, 0, FAKE, None) == B.LSDF_OK
+    # training: B not a multiple of 512, NULL moments, t = 0, workspace too small or misaligned
+    args = lambda Bt=512, t=1, m=FAKE, ws=FAKE, wsb=1 << 30: (
+        FAKE, m, FAKE, t, 1e-3, 0.9, 0.999, 1e-8, dom, 2, FAKE, FAKE, 1024, None, Bt, None, None, ws, wsb, None)
+    assert lib.lsdf_mlp_train_step(*args(Bt=500)) == B.LSDF_E_SHAPE
+    assert lib.lsdf_mlp_train_step(*args(m=None)) == B.LSDF_E_INVALID_ARG
+    assert lib.lsdf_mlp_train_step(*args(t=0)) == B.LSDF_E_INVALID_ARG
+    assert lib.lsdf_mlp_train_step(*args(wsb=16)) == B.LSDF_E_SHAPE
+    assert lib.lsdf_mlp_train_step(*args(ws=ct.c_void_p(0x100010))) == B.LSDF_E_INVALID_ARG
+    assert lib.lsdf_mlp_loss_grad(FAKE, dom, 2, FAKE, FAKE, 1024, None, 512, None, None, FAKE, 1 << 30, None) \
+        == B.LSDF_E_INVALID_ARG                                                      # grad_out NULL
+    # learned query: margin NaN, NULL domains, flags
+    g = grid_array(2)
+    q = lambda margin=0.05, doms=dom, flags=0: lib.lsdf_query_min_distance_mlp(
+        FAKE, 4, 2, g, FAKE, FAKE, doms, margin, FAKE, 10, FAKE, FAKE, None, flags, FAKE, 1 << 20, None)
+    assert q(margin=float("nan")) == B.LSDF_E_INVALID_ARG
+    assert q(doms=None) == B.LSDF_E_INVALID_ARG
+    assert q(flags=2) == B.LSDF_E_UNSUPPORTED
+    # labels: empty mesh, NULL descriptor
+    assert lib.lsdf_sdf_labels(FAKE, 0, FAKE, 12, None, 0, g, FAKE, FAKE, 10, FAKE, None) == B.LSDF_E_SHAPE
+    assert lib.lsdf_sdf_labels(FAKE, 8, FAKE, 12, None, 0, None, FAKE, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG

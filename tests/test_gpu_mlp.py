@@ -1,0 +1,191 @@
+"""GPU parity of the learned per-link SDF path against the oracle, through
+the C ABI: network evaluation and L1-loss gradients against the oracle's
+bfloat16 twin (same rounding points, double accumulation) and its pure
+double network, the Adam step against the oracle's, labels against the
+oracle's grid and mesh distances, and the learned clearance query against
+the plain query (every pair falling back) and against the twin network."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+# bfloat16 activations: a flip of one rounding between the GPU and the twin
+# (their FP32 / double sums differ in the last bits) moves an activation by
+# one bfloat16 ulp (2^-8 relative); over two hidden layers of 128 units that
+# stays well below 2e-3 of the output scale for these weights.
+TOL_EVAL = 2e-3
+
+
+def say(*a):
+    print("[gpu-mlp]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_12543_amd import lsdf
+    lsdf.load_library()
+    return lsdf
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def params_f32(L, seed, scale=2.0):
+    return (synth.mlp_init(L, synth.BASE_SEED + 5 + seed) * scale).astype(np.float32)
+
+
+def domains_of(w):
+    cen, half = synth.mlp_domain(w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64))
+    return cen.astype(np.float32), half.astype(np.float32)
+
+
+def normalise(points, cen, half):
+    """The kernel's normalisation, (x - centre) * (1 / half), in float32."""
+    inv = (1.0 / half.astype(np.float64)).astype(np.float32)
+    return ((points.astype(np.float32) - cen.astype(np.float32)) * inv).astype(np.float64)
+
+
+def test_mlp_eval_matches_twin(B, orc, tiny):
+    cen, half = domains_of(tiny)
+    P = params_f32(1, 0)[0]
+    rng = np.random.default_rng(40)
+    pts = rng.uniform(cen[2] - half[2], cen[2] + half[2], size=(3001, 3)).astype(np.float32)
+    say("mlp_eval N=3001")
+    got = B.mlp_eval(dev(P), (cen[2:3], half[2:3]), dev(pts)).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    X = normalise(pts, cen[2], half[2])
+    twin = orc.mlp_forward(P.astype(np.float64), X, bf16=True)
+    full = orc.mlp_forward(P.astype(np.float64), X, bf16=False)
+    scale = max(1.0, np.abs(twin).max())
+    e_twin, e_full = np.abs(got - twin).max(), np.abs(got - full).max()
+    say(f"max |gpu - bf16 twin| = {e_twin:.3g}, max |gpu - double net| = {e_full:.3g}, output scale {scale:.3g}")
+    assert e_twin <= TOL_EVAL * scale
+    assert e_full <= 5e-2 * scale
+
+
+def test_mlp_loss_grad_matches_twin(B, orc, tiny):
+    cen, half = domains_of(tiny)
+    L, N, Bt = 2, 1536, 1024
+    P = params_f32(L, 1)
+    rng = np.random.default_rng(41)
+    samples = np.stack([rng.uniform(cen[i] - half[i], cen[i] + half[i], size=(N, 3)) for i in range(L)]).astype(np.float32)
+    X = [normalise(samples[i], cen[i], half[i]) for i in range(L)]
+    # labels 0.3 away from the outputs, so that sign(m - y) is the same everywhere
+    labels = np.stack([orc.mlp_forward(P[i].astype(np.float64), X[i], bf16=True) + rng.choice([-0.3, 0.3], size=N)
+                       for i in range(L)]).astype(np.float32)
+    bidx = np.stack([rng.permutation(N)[:Bt] for _ in range(L)]).astype(np.int32)
+    say(f"mlp_loss_grad L={L} N={N} B={Bt}")
+    loss, grad = B.mlp_loss_grad(dev(P), (cen[:L], half[:L]), dev(samples), dev(labels), Bt, dev(bidx, torch.int32))
+    loss, grad = loss.cpu().numpy().astype(np.float64), grad.cpu().numpy().astype(np.float64)
+    for i in range(L):
+        Xi, Yi = X[i][bidx[i]], labels[i][bidx[i]].astype(np.float64)
+        l_twin, g_twin = orc.mlp_loss_grad(P[i].astype(np.float64), Xi, Yi, bf16=True)
+        l_full, g_full = orc.mlp_loss_grad(P[i].astype(np.float64), Xi, Yi, bf16=False)
+        cos_t = g_twin @ grad[i] / np.linalg.norm(g_twin) / np.linalg.norm(grad[i])
+        cos_f = g_full @ grad[i] / np.linalg.norm(g_full) / np.linalg.norm(grad[i])
+        rel_t = np.abs(grad[i] - g_twin).max() / np.abs(g_twin).max()
+        say(f"link {i}: loss {loss[i]:.6f} vs twin {l_twin:.6f}; grad cosine twin {cos_t:.6f} full {cos_f:.6f}; "
+            f"max-norm rel vs twin {rel_t:.3g}")
+        assert loss[i] == pytest.approx(l_twin, rel=1e-4)
+        assert cos_t >= 0.9999 and rel_t <= 1e-2
+        assert cos_f >= 0.999
+
+
+def test_mlp_train_step_is_adam(B, orc, tiny):
+    cen, half = domains_of(tiny)
+    L, N, Bt = 2, 1024, 512
+    P = params_f32(L, 2)
+    rng = np.random.default_rng(42)
+    samples = np.stack([rng.uniform(cen[i] - half[i], cen[i] + half[i], size=(N, 3)) for i in range(L)]).astype(np.float32)
+    labels = rng.normal(size=(L, N)).astype(np.float32)
+    p = dev(P)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    grad = torch.empty_like(p)
+    lr = 1e-3
+    say("mlp_train_step t=1, 2")
+    for t in (1, 2):
+        before = p.cpu().numpy().astype(np.float64)
+        m64, v64 = m.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64)
+        B.mlp_train_step(p, m, v, t, lr, (cen[:L], half[:L]), dev(samples), dev(labels), Bt, grad=grad)
+        torch.cuda.synchronize()
+        g = grad.cpu().numpy().astype(np.float64)
+        want = before.copy()
+        for i in range(L):
+            orc.adam_step(want[i], m64[i], v64[i], g[i], t, lr)
+        got = p.cpu().numpy().astype(np.float64)
+        assert np.abs(got - want).max() <= 1e-6 * max(1.0, np.abs(want).max()) + 1e-7
+        assert np.abs(m.cpu().numpy() - m64).max() <= 1e-6 * max(1e-30, np.abs(m64).max())
+
+
+def test_sdf_labels_match_oracle(B, orc, tiny, tiny_grids):
+    i = 3
+    mesh = tiny.robot.links[i]
+    pts = synth.mlp_samples(mesh, tiny.grid_lo[i], tiny.grid_hi[i], 4000, 43).astype(np.float32)
+    gs = B.GridSet(tiny.grid_lo, tiny.grid_hi, tiny.grid_n, device="cuda")
+    for k, g in enumerate(tiny_grids):
+        gs.set_grid(k, g.astype(np.float32))
+    say("sdf_labels N=4000")
+    lab = B.sdf_labels(dev(mesh.verts), dev(mesh.tris, torch.int32), mesh.comp_first, gs, i, dev(pts)).cpu().numpy()
+    # inside the box: the query arithmetic with an identity pose, bit for bit
+    ident = np.concatenate([np.eye(3), np.zeros((3, 1))], 1)[None, None].astype(np.float32)
+    inbox = np.zeros(len(pts), bool)
+    ref = np.empty(len(pts))
+    for j in range(len(pts)):
+        cl = orc.query_f32(ident, tiny.grid_lo[i:i + 1], tiny.grid_hi[i:i + 1], tiny.grid_n[i:i + 1],
+                           [tiny_grids[i].astype(np.float32)], pts[j:j + 1])
+        inbox[j] = np.isfinite(cl[0, 0])
+        ref[j] = cl[0, 0]
+    out = ~inbox
+    ref[out] = orc.mesh_sdf(pts[out].astype(np.float64), mesh.verts, mesh.tris, mesh.comp_first)
+    assert inbox.sum() > 500 and out.sum() > 500
+    assert np.array_equal(lab[inbox].view(np.uint32), ref[inbox].astype(np.float32).view(np.uint32))
+    assert np.abs(lab[out] - ref[out]).max() < 2e-6
+
+
+def test_query_mlp_all_fallback_equals_plain(B, orc, tiny, tiny_grids):
+    """With an infinite margin every pair takes the grid value: the learned
+    query must give the plain query's bits."""
+    cen, half = domains_of(tiny)
+    gs = B.GridSet(tiny.grid_lo, tiny.grid_hi, tiny.grid_n, device="cuda")
+    for k, g in enumerate(tiny_grids):
+        gs.set_grid(k, g.astype(np.float32))
+    T = dev(orc.fk(tiny.robot.dh, tiny.q, tiny.robot.base_T).astype(np.float32))
+    pts = dev(tiny.points.astype(np.float32))
+    P = dev(params_f32(7, 3))
+    say("query_mlp margin=+inf vs plain")
+    d0, l0, ld0 = B.query_min_distance(T, gs, pts, link_dist=True)
+    d1, l1, ld1 = B.query_min_distance_mlp(T, gs, P, (cen, half), pts, margin=float("inf"), link_dist=True)
+    torch.cuda.synchronize()
+    assert torch.equal(ld0.view(torch.int32), ld1.view(torch.int32))
+    assert torch.equal(d0.view(torch.int32), d1.view(torch.int32)) and torch.equal(l0, l1)
+
+
+def test_query_mlp_no_fallback_matches_twin(B, orc, tiny, tiny_grids):
+    """With margin -inf every in-domain pair takes the network value: the
+    per-link minima must match the twin network's over the same pairs."""
+    cen, half = domains_of(tiny)
+    gs = B.GridSet(tiny.grid_lo, tiny.grid_hi, tiny.grid_n, device="cuda")
+    for k, g in enumerate(tiny_grids):
+        gs.set_grid(k, g.astype(np.float32))
+    C, M = 3, 301
+    T32 = orc.fk(tiny.robot.dh, tiny.q[:C], tiny.robot.base_T).astype(np.float32)
+    pts = tiny.points[:M].astype(np.float32)
+    P = params_f32(7, 4)
+    say(f"query_mlp margin=-inf C={C} M={M}")
+    d, l, ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half), dev(pts), margin=float("-inf"),
+                                        link_dist=True)
+    ld = ld.cpu().numpy().astype(np.float64)
+    for c in range(C):
+        for i in range(7):
+            R, t = T32[c, i, :, :3].astype(np.float64), T32[c, i, :, 3].astype(np.float64)
+            loc = (pts.astype(np.float64) - t) @ R
+            X = (loc - cen[i]) / half[i]
+            ind = np.all(np.abs(X) <= 1.0, axis=1)
+            want = orc.mlp_forward(P[i].astype(np.float64), X[ind], bf16=True).min() if ind.any() else np.inf
+            assert abs(ld[c, i] - want) <= TOL_EVAL * max(1.0, abs(want)), (c, i, ld[c, i], want)
