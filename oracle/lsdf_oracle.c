@@ -564,3 +564,79 @@ ORC_EXPORT void orc_adam_step(double* P, double* Mo, double* Vo, const double* G
         P[k] -= lr * mh / (sqrt(vh) + eps);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Judge of the learned surrogate: per (c, i), the minimum over the points   */
+/* inside link i's network domain (|(l - dom_c) / dom_h|_a <= 1 on every     */
+/* axis) of F_i(l) = the double-precision grid interpolant inside the grid   */
+/* box, the exact mesh signed distance outside it.  Exact: points outside    */
+/* the box are visited in increasing order of their distance to the mesh's   */
+/* bounding box, a lower bound of their mesh distance, and the scan stops    */
+/* when that bound reaches the running minimum.  +inf when no point is in    */
+/* the domain.                                                               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double lb;
+    int64_t j;
+} orc_lb_t;
+
+static int cmp_lb(const void* a, const void* b) {
+    double x = ((const orc_lb_t*)a)->lb, y = ((const orc_lb_t*)b)->lb;
+    return (x > y) - (x < y);
+}
+
+ORC_EXPORT void orc_judge_min(const double* T, int32_t C, int32_t L, const double* lo, const double* hi,
+                              const int32_t* n, const double* grids, const int64_t* offs,
+                              const double* const* Vs, const int32_t* const* Ts, const int32_t* const* comps,
+                              const int32_t* ncomps, const double* aabb_lo, const double* aabb_hi,
+                              const double* dom_c, const double* dom_h, const double* P, int64_t M, double* out) {
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+    for (int32_t c = 0; c < C; ++c) {
+        for (int32_t i = 0; i < L; ++i) {
+            const double* Ti = T + ((int64_t)c * L + i) * 12;
+            double h[3];
+            for (int a = 0; a < 3; ++a) h[a] = (hi[3 * i + a] - lo[3 * i + a]) / (double)(n[3 * i + a] - 1);
+            orc_lb_t* outside = (orc_lb_t*)malloc(sizeof(orc_lb_t) * (size_t)(M > 0 ? M : 1));
+            int64_t nout = 0;
+            double best = INFINITY;
+            for (int64_t j = 0; j < M; ++j) {
+                double d[3] = {P[3 * j] - Ti[3], P[3 * j + 1] - Ti[7], P[3 * j + 2] - Ti[11]};
+                double l[3], u[3];
+                int indom = 1, inbox = 1;
+                for (int a = 0; a < 3; ++a) {
+                    l[a] = Ti[0 + a] * d[0] + Ti[4 + a] * d[1] + Ti[8 + a] * d[2];
+                    if (fabs((l[a] - dom_c[3 * i + a]) / dom_h[3 * i + a]) > 1.0) indom = 0;
+                    u[a] = (l[a] - lo[3 * i + a]) / h[a];
+                    if (!(u[a] >= 0.0 && u[a] <= (double)(n[3 * i + a] - 1))) inbox = 0;
+                }
+                if (!indom) continue;
+                if (inbox) {
+                    double v = orc_trilinear_f64(grids + offs[i], n + 3 * i, u);
+                    if (v < best) best = v;
+                } else {
+                    double q2 = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        double e = 0.0;
+                        if (l[a] < aabb_lo[3 * i + a]) e = aabb_lo[3 * i + a] - l[a];
+                        if (l[a] > aabb_hi[3 * i + a]) e = l[a] - aabb_hi[3 * i + a];
+                        q2 += e * e;
+                    }
+                    outside[nout].lb = sqrt(q2);
+                    outside[nout].j = j;
+                    ++nout;
+                }
+            }
+            qsort(outside, (size_t)nout, sizeof(orc_lb_t), cmp_lb);
+            for (int64_t k = 0; k < nout && outside[k].lb < best; ++k) {
+                int64_t j = outside[k].j;
+                double d[3] = {P[3 * j] - Ti[3], P[3 * j + 1] - Ti[7], P[3 * j + 2] - Ti[11]};
+                double l[3];
+                for (int a = 0; a < 3; ++a) l[a] = Ti[0 + a] * d[0] + Ti[4 + a] * d[1] + Ti[8 + a] * d[2];
+                double s = orc_mesh_sdf(l, Vs[i], Ts[i], comps[i], ncomps[i]);
+                if (s < best) best = s;
+            }
+            free(outside);
+            out[(int64_t)c * L + i] = best;
+        }
+    }
+}

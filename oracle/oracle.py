@@ -76,6 +76,9 @@ def load():
     lib.orc_adam_step.restype = None
     lib.orc_adam_step.argtypes = [_dp, _dp, _dp, _dp, ct.c_int64, ct.c_int64, ct.c_double, ct.c_double,
                                   ct.c_double, ct.c_double]
+    lib.orc_judge_min.restype = None
+    lib.orc_judge_min.argtypes = [_dp, ct.c_int32, ct.c_int32, _dp, _dp, _ip, _dp, _lp, ct.POINTER(_dp),
+                                  ct.POINTER(_ip), ct.POINTER(_ip), _ip, _dp, _dp, _dp, _dp, _dp, ct.c_int64, _dp]
     _lib = lib
     return lib
 
@@ -211,6 +214,33 @@ def exact_min(T, meshes, points) -> np.ndarray:
     return out
 
 
+def judge_min(T, lo, hi, n, grids, meshes, dom_c, dom_h, points) -> np.ndarray:
+    """Per-link minima [C][L] of the judge field of the learned surrogate:
+    grid value inside each link's box, exact mesh distance outside it, over
+    the points inside each link's network domain."""
+    lib = load()
+    T = _c(T, np.float64)
+    C, L = T.shape[0], T.shape[1]
+    lo, hi, n = _c(lo, np.float64), _c(hi, np.float64), _c(n, np.int32)
+    buf, offs = _pack(grids, np.float64)
+    Vs = [_c(m.verts, np.float64) for m in meshes]
+    Ts = [_c(m.tris, np.int32) for m in meshes]
+    Cs = [_c(m.comp_first, np.int32) for m in meshes]
+    nc = _c([m.comp_first.shape[0] - 1 for m in meshes], np.int32)
+    alo = _c([m.verts.min(axis=0) for m in meshes], np.float64)
+    ahi = _c([m.verts.max(axis=0) for m in meshes], np.float64)
+    dc, dh = _c(dom_c, np.float64), _c(dom_h, np.float64)
+    Vp = (_dp * L)(*[_ptr(v, _dp) for v in Vs])
+    Tp = (_ip * L)(*[_ptr(t, _ip) for t in Ts])
+    Cp = (_ip * L)(*[_ptr(c, _ip) for c in Cs])
+    P = _c(points, np.float64).reshape(-1, 3)
+    out = np.empty((C, L), dtype=np.float64)
+    lib.orc_judge_min(_ptr(T, _dp), C, L, _ptr(lo, _dp), _ptr(hi, _dp), _ptr(n, _ip), _ptr(buf, _dp),
+                      _ptr(offs, _lp), Vp, Tp, Cp, _ptr(nc, _ip), _ptr(alo, _dp), _ptr(ahi, _dp), _ptr(dc, _dp),
+                      _ptr(dh, _dp), _ptr(P, _dp), P.shape[0], _ptr(out, _dp))
+    return out
+
+
 def reduce(cl):
     """Per configuration: (min over links, lowest argmin link or -1)."""
     lib = load()
@@ -300,4 +330,4 @@ def mlp_unpack(params):
 
 __all__ = ["build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
            "query_f32", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids",
-           "MLP_HIDDEN", "adam_step", "mlp_forward", "mlp_loss_grad", "mlp_nparam", "mlp_unpack"]
+           "MLP_HIDDEN", "adam_step", "judge_min", "mlp_forward", "mlp_loss_grad", "mlp_nparam", "mlp_unpack"]

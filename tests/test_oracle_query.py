@@ -214,3 +214,36 @@ def test_f32_twin_close_to_f64(orc, tiny, tiny_grids):
     both = np.isfinite(cl64) & np.isfinite(cl32)
     assert both.mean() > 0.99
     assert np.max(np.abs(cl64[both] - cl32[both])) < 1e-6
+
+
+def test_judge_min_against_brute_force(orc, tiny, tiny_grids):
+    """The pruned judge equals the unpruned definition: grid values for the
+    points in each box, exact mesh distances for the others (inside the
+    network domain)."""
+    import synth
+    q = tiny.q[:3]
+    T = orc.fk(tiny.robot.dh, q, tiny.robot.base_T)
+    rng = np.random.default_rng(18)
+    origins = T[:, :, :, 3].reshape(-1, 3)
+    pts = np.concatenate([origins[rng.integers(0, origins.shape[0], 60)] + rng.normal(0, 0.15, size=(60, 3)),
+                          rng.uniform(-1.5, 1.5, size=(60, 3))])
+    dc, dh = synth.mlp_domain(tiny.grid_lo.astype(np.float64), tiny.grid_hi.astype(np.float64), far=0.4)
+    got = orc.judge_min(T, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, tiny_grids, tiny.robot.links, dc, dh, pts)
+    grid_cl = orc.query_f64(T, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, tiny_grids, pts)
+    want = np.full_like(got, np.inf)
+    for c in range(T.shape[0]):
+        for i in range(tiny.L):
+            R, t = T[c, i, :, :3], T[c, i, :, 3]
+            loc = (pts - t) @ R
+            indom = np.all(np.abs((loc - dc[i]) / dh[i]) <= 1.0, axis=1)
+            for j in np.flatnonzero(indom):
+                v = orc.query_f64(T[c:c + 1, i:i + 1], tiny.grid_lo[i:i + 1], tiny.grid_hi[i:i + 1],
+                                  tiny.grid_n[i:i + 1], [tiny_grids[i]], pts[j:j + 1])[0, 0]
+                if not np.isfinite(v):
+                    m = tiny.robot.links[i]
+                    v = orc.mesh_sdf(loc[j:j + 1], m.verts, m.tris, m.comp_first)[0]
+                want[c, i] = min(want[c, i], v)
+    assert np.array_equal(np.isfinite(got), np.isfinite(want))
+    fin = np.isfinite(got)
+    assert np.max(np.abs(got[fin] - want[fin])) < 1e-12
+    assert (got[fin] < grid_cl[fin]).any() or np.isinf(grid_cl).any()   # some minima come from outside a box
