@@ -83,6 +83,87 @@ def cpu_baseline(w, budget_s: float = 12.0):
                       "double-precision kinematics + query, OpenMP over waypoints"}
 
 
+def time_calls(fn, steps, warmup):
+    """Mean duration (ms) of fn() measured with HIP events on the current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 8):
+    """The learned form on the 500 x 100,000 x 7 workload (64^3 grids): per-link
+    networks trained on the GPU (untimed), then the grid-only query and the
+    network-plus-fallback query timed on the same inputs, and the learned
+    clearances judged against the oracle's exact minimum on sampled waypoints."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_2309_12543_amd import learned, lsdf
+
+    w = synth.make_workload("learned")
+    log(f"learned variant: C={w.C} M={w.M} L={w.L}, training {epochs} epochs")
+    gs = lsdf.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device=dev)
+    cen, half = synth.mlp_domain(w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64))
+    n = 1 << 20
+    S = torch.as_tensor(np.stack([synth.mlp_samples(m, w.grid_lo[i], w.grid_hi[i], n, synth.BASE_SEED + 4 + i)
+                                  for i, m in enumerate(w.robot.links)]).astype(np.float32), device=dev)
+    t0 = time.perf_counter()
+    labels = learned.labels_for_samples(w.robot.links, gs, S)
+    params = torch.as_tensor(synth.mlp_init(w.L, synth.BASE_SEED + 5).astype(np.float32), device=dev)
+    hist = learned.train(params, (cen, half), S, labels, epochs=epochs, batch=4096, lr=3e-3, lr_final=3e-5,
+                         log_every=max(1, epochs // 4), log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    doms = lsdf.make_domains(cen, half)
+    q = torch.as_tensor(w.q, dtype=torch.float32, device=dev)
+    pts = torch.as_tensor(w.points, dtype=torch.float32, device=dev)
+    T = lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T)
+    ws = torch.zeros(lsdf.query_workspace_size(w.C, w.L, w.M), dtype=torch.uint8, device=dev)
+    outg = (torch.empty(w.C, device=dev), torch.empty(w.C, dtype=torch.int32, device=dev), None)
+    outm = (torch.empty(w.C, device=dev), torch.empty(w.C, dtype=torch.int32, device=dev), None)
+    grid_ms = time_calls(lambda: lsdf.query_min_distance(T, gs, pts, workspace=ws, out=outg), steps * 10, 5)
+    mlp_ms = time_calls(lambda: lsdf.query_min_distance_mlp(T, gs, params, doms, pts, margin=0.05, workspace=ws,
+                                                            out=outm), steps, 1)
+    d_grid = outg[0].cpu().numpy().astype(np.float64)
+    d_mlp = outm[0].cpu().numpy().astype(np.float64)
+    # judge: exact minimum of grid-in-box / mesh-outside over each link's domain
+    sel = np.linspace(0, w.C - 1, judge_waypoints).round().astype(int)
+    log(f"learned variant: judging {len(sel)} waypoints with the oracle")
+    grids = oracle.workload_grids(w)
+    T64 = oracle.fk(w.robot.dh, w.q[sel], w.robot.base_T)
+    jcl = oracle.judge_min(T64, w.grid_lo, w.grid_hi, w.grid_n, grids, w.robot.links, cen, half, w.points)
+    judge, _ = oracle.reduce(jcl)
+    both = np.isfinite(judge) & np.isfinite(d_mlp[sel])
+    err = np.abs(d_mlp[sel][both] - judge[both]) * 1e3
+    pairs = w.C * w.M * w.L
+    return {
+        "workload": f"{w.name}: {w.C} waypoints x {w.M} points x {w.L} links, 64^3 FP32 grids, "
+                    f"3-128-128-128-1 SiLU network per link (bf16 MFMA, FP32 accumulate), fallback below 5 cm",
+        "grid_ms_per_batch": round(grid_ms, 4),
+        "mlp_ms_per_batch": round(mlp_ms, 3),
+        "grid_gq_s": round(pairs / (grid_ms / 1e3) / 1e9, 2),
+        "mlp_gq_s": round(pairs / (mlp_ms / 1e3) / 1e9, 2),
+        "judged_waypoints": int(len(sel)),
+        "max_err_mm": round(float(err.max()), 3) if err.size else None,
+        "mean_err_mm": round(float(err.mean()), 3) if err.size else None,
+        "grid_inf_waypoints": int(np.sum(~np.isfinite(d_grid))),
+        "mlp_inf_waypoints": int(np.sum(~np.isfinite(d_mlp))),
+        "train_s": round(train_s, 1),
+        "train_epochs": epochs,
+        "train_samples_per_link": n,
+        "final_train_l1_mm": [round(1e3 * float(x), 2) for x in hist[-1]],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +171,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="paper")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned-epochs", type=int, default=400,
+                    help="training epochs of the learned variant (0 skips the learned variant)")
+    ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB mebibytes (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -181,6 +265,8 @@ def main():
                      "kernel": "query_kernel (timed with its finalize kernel: one lsdf_query_min_distance call)",
                      "algorithmic_flop": flop},
     }
+    if args.learned_epochs > 0:
+        rec["learned"] = learned_variant(dev, args.learned_epochs, args.learned_steps)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)

@@ -63,12 +63,14 @@ extern "C" {
  * h_a = (hi_a - lo_a) / (n_a - 1); the box [lo, hi] is the capture range.
  * Storage: element (kz * n_y + ky) * n_x + kx (x fastest), `dtype` elements,
  * starting `elem_offset` elements into the shared grid buffer.  Negative
- * inside the link, positive outside. */
+ * inside the link, positive outside.  16-bit storage (bfloat16 or IEEE
+ * binary16) is widened exactly to FP32 before interpolation; interpolation
+ * and every reduction stay FP32.  The grids of one query share a dtype. */
 typedef struct lsdf_grid {
     float   lo[3];
     float   hi[3];
     int32_t n[3];          /* nodes per axis, each >= 2 */
-    int32_t dtype;         /* LSDF_F32 (LSDF_BF16 / LSDF_F16 reserved) */
+    int32_t dtype;         /* storage: LSDF_F32, LSDF_BF16 or LSDF_F16 */
     int64_t elem_offset;   /* >= 0, in elements of `dtype` */
 } lsdf_grid;
 
@@ -141,7 +143,8 @@ int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L,
  *   comp_first  host int32 [ncomp+1]: triangles [comp_first[k],
  *               comp_first[k+1]) form closed part k; NULL = one part of all
  *               nt triangles.  The link's distance is the minimum over parts.
- *   desc        host descriptor of the grid to fill (dtype LSDF_F32)
+ *   desc        host descriptor of the grid to fill; 16-bit storage holds the
+ *               FP32 distance rounded once to nearest even
  *   grid_buf    device buffer; nodes are written at desc->elem_offset
  * Inside/outside is decided by the generalised winding number of each part
  * (negative inside). */

@@ -22,9 +22,10 @@ struct BuildArgs {
     int32_t n[3];
     int32_t ncomp;
     int32_t nv;
+    int32_t dtype;       // storage type of the output grid
     const float* verts;
     const int32_t* tris;
-    float* out;
+    void* out;
 };
 
 struct V3 {
@@ -138,20 +139,28 @@ __global__ __launch_bounds__(kBlock) void build_sdf_kernel(BuildArgs p) {
     const V3 pt = {fmaf((float)kx, p.h[0], p.lo[0]), fmaf((float)ky, p.h[1], p.lo[1]),
                    fmaf((float)kz, p.h[2], p.lo[2])};
     const float sdf = mesh_sdf(p, s_tri, pt, true);
-    if (active) p.out[idx] = sdf;
+    if (active) {
+        // one rounding, to nearest even, into the storage type
+        if (p.dtype == LSDF_BF16)
+            static_cast<uint16_t*>(p.out)[idx] = __builtin_bit_cast(uint16_t, (__bf16)sdf);
+        else if (p.dtype == LSDF_F16)
+            static_cast<_Float16*>(p.out)[idx] = (_Float16)sdf;
+        else
+            static_cast<float*>(p.out)[idx] = sdf;
+    }
 }
 
 struct LabelArgs {
     BuildArgs mesh;
     LinkGrid lg;
-    const float* grid;
+    const void* grid;
     const float* points;
     float* out;
     int64_t N;
 };
 
 // Labels: the grid value inside the grid box, the exact distance outside.
-template <bool CUBIC>
+template <bool CUBIC, int DT>
 __global__ __launch_bounds__(kBlock) void label_kernel(LabelArgs p) {
     __shared__ float s_tri[kBlock][9];
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -160,7 +169,8 @@ __global__ __launch_bounds__(kBlock) void label_kernel(LabelArgs p) {
     const V3 pt = {p.points[3 * jj + 0], p.points[3 * jj + 1], p.points[3 * jj + 2]};
     const float ident[12] = {1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f};
     const GridMap gm = grid_map(p.lg, ident);
-    const float g = sample_or_inf<CUBIC>(p.grid + p.lg.offset, p.lg, gm, pt.x, pt.y, pt.z);
+    const float g = sample_or_inf<CUBIC, DT>(static_cast<const typename GridT<DT>::T*>(p.grid) + p.lg.offset, p.lg,
+                                             gm, pt.x, pt.y, pt.z);
     const bool exact = active && !(g < INFINITY);
     float v = g;
     if (__syncthreads_or(exact)) {
@@ -216,15 +226,20 @@ LSDF_API int lsdf_sdf_labels(const float* verts, int32_t nv, const int32_t* tris
     if ((rc = prepare_link_grid(*desc, 0, &a.lg)) != LSDF_OK) return rc;
     if (N == 0) return LSDF_OK;
     if (!grid_buf || !points || !out) return fail(LSDF_E_INVALID_ARG, "sdf_labels: NULL device pointer");
-    a.grid = static_cast<const float*>(grid_buf);
+    a.grid = grid_buf;
     a.points = points;
     a.out = out;
     a.N = N;
     const dim3 grid((unsigned)((N + kBlock - 1) / kBlock));
-    if (a.lg.cubic)
-        hipLaunchKernelGGL(label_kernel<true>, grid, dim3(kBlock), 0, as_stream(stream), a);
-    else
-        hipLaunchKernelGGL(label_kernel<false>, grid, dim3(kBlock), 0, as_stream(stream), a);
+    hipStream_t st = as_stream(stream);
+    switch (a.lg.dtype * 2 + (a.lg.cubic ? 1 : 0)) {
+        case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((label_kernel<true, LSDF_F32>), grid, dim3(kBlock), 0, st, a); break;
+        case LSDF_F32 * 2: hipLaunchKernelGGL((label_kernel<false, LSDF_F32>), grid, dim3(kBlock), 0, st, a); break;
+        case LSDF_BF16 * 2 + 1: hipLaunchKernelGGL((label_kernel<true, LSDF_BF16>), grid, dim3(kBlock), 0, st, a); break;
+        case LSDF_BF16 * 2: hipLaunchKernelGGL((label_kernel<false, LSDF_BF16>), grid, dim3(kBlock), 0, st, a); break;
+        case LSDF_F16 * 2 + 1: hipLaunchKernelGGL((label_kernel<true, LSDF_F16>), grid, dim3(kBlock), 0, st, a); break;
+        default: hipLaunchKernelGGL((label_kernel<false, LSDF_F16>), grid, dim3(kBlock), 0, st, a); break;
+    }
     return check_launch("sdf_labels");
 }
 
@@ -246,7 +261,8 @@ LSDF_API int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* 
         p.h[a] = (float)(((double)desc->hi[a] - (double)desc->lo[a]) / (double)(desc->n[a] - 1));
         p.n[a] = desc->n[a];
     }
-    p.out = static_cast<float*>(grid_buf) + desc->elem_offset;
+    p.dtype = desc->dtype;
+    p.out = static_cast<char*>(grid_buf) + desc->elem_offset * (desc->dtype == LSDF_F32 ? 4 : 2);
     const int64_t nodes = (int64_t)p.n[0] * p.n[1] * p.n[2];
     hipLaunchKernelGGL(build_sdf_kernel, dim3((unsigned)((nodes + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        as_stream(stream), p);

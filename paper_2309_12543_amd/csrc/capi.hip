@@ -22,7 +22,7 @@ int fail(int code, const char* fmt, ...) {
 int prepare_link_grid(const lsdf_grid& g, int index, LinkGrid* out) {
     if (!finite3(g.lo) || !finite3(g.hi))
         return fail(LSDF_E_INVALID_ARG, "grid %d: non-finite box", index);
-    if (g.dtype != LSDF_F32)
+    if (g.dtype != LSDF_F32 && g.dtype != LSDF_BF16 && g.dtype != LSDF_F16)
         return fail(LSDF_E_UNSUPPORTED, "grid %d: unsupported dtype %d", index, (int)g.dtype);
     if (g.elem_offset < 0) return fail(LSDF_E_INVALID_ARG, "grid %d: negative elem_offset", index);
     for (int a = 0; a < 3; ++a) {

@@ -7,6 +7,26 @@
 
 namespace lsdf {
 
+// Storage type of a grid and its exact widening to FP32 (bfloat16: the top
+// half of a binary32; binary16: v_cvt_f32_f16).
+template <int DT>
+struct GridT;
+template <>
+struct GridT<LSDF_F32> {
+    using T = float;
+    static __device__ inline float get(const T* p, int i) { return p[i]; }
+};
+template <>
+struct GridT<LSDF_BF16> {
+    using T = uint16_t;
+    static __device__ inline float get(const T* p, int i) { return __uint_as_float((uint32_t)p[i] << 16); }
+};
+template <>
+struct GridT<LSDF_F16> {
+    using T = _Float16;
+    static __device__ inline float get(const T* p, int i) { return (float)p[i]; }
+};
+
 __device__ inline float lerp_exact_ends(float a, float b, float t) {
     return fmaf(t, b, fmaf(-t, a, a));
 }
@@ -76,17 +96,20 @@ __device__ inline GridMap grid_map(const LinkGrid& lg, const float* T) {
 }
 
 // Grid value of link-frame or world point x through map gm, +inf outside.
-template <bool CUBIC>
-__device__ inline float sample_or_inf(const float* __restrict__ G, const LinkGrid& lg, const GridMap& gm, float x,
-                                      float y, float z) {
+// G points at the link's first element (storage type DT).
+template <bool CUBIC, int DT = LSDF_F32>
+__device__ inline float sample_or_inf(const typename GridT<DT>::T* __restrict__ G, const LinkGrid& lg,
+                                      const GridMap& gm, float x, float y, float z) {
     const float v0 = fmaf(gm.m00, x, fmaf(gm.m01, y, fmaf(gm.m02, z, gm.w0)));
     const float v1 = fmaf(gm.m10, x, fmaf(gm.m11, y, fmaf(gm.m12, z, gm.w1)));
     const float v2 = fmaf(gm.m20, x, fmaf(gm.m21, y, fmaf(gm.m22, z, gm.w2)));
     if (!inside<CUBIC>(lg, v0, v1, v2)) return INFINITY;
     const Cell cl = locate(lg, v0, v1, v2);
-    const float* cp = G + cl.idx;
+    const typename GridT<DT>::T* cp = G + cl.idx;
     const int nx = lg.n[0], nxy = lg.n[0] * lg.n[1];
-    return interpolate(cp[0], cp[1], cp[nx], cp[nx + 1], cp[nxy], cp[nxy + 1], cp[nxy + nx], cp[nxy + nx + 1], cl);
+    using E = GridT<DT>;
+    return interpolate(E::get(cp, 0), E::get(cp, 1), E::get(cp, nx), E::get(cp, nx + 1), E::get(cp, nxy),
+                       E::get(cp, nxy + 1), E::get(cp, nxy + nx), E::get(cp, nxy + nx + 1), cl);
 }
 
 }  // namespace lsdf

@@ -63,6 +63,6 @@ int prepare_link_grid(const lsdf_grid& g, int index, LinkGrid* out);
 // Turns the query workspace keys into out_dist / out_link / out_link_dist
 // and clears them (shared by the plain and the learned query).
 int launch_query_finalize(uint32_t* keys, float* out_dist, int32_t* out_link, float* out_link_dist, int32_t C,
-                          int32_t L, hipStream_t s);
+                          int32_t L, hipStream_t s, uint32_t* scratch = nullptr, int64_t scratch_words = 0);
 
 }  // namespace lsdf

@@ -85,7 +85,7 @@ struct QueryMlpArgs {
     Domain dom[LSDF_MAX_LINKS];
     const float* link_T;
     const float* params;
-    const float* grid;
+    const void* grid;
     const float* points;
     uint32_t* keys;
     int64_t M;
@@ -96,7 +96,7 @@ struct QueryMlpArgs {
     float margin;
 };
 
-template <bool CUBIC>
+template <bool CUBIC, int DT>
 __global__ __launch_bounds__(kBlock) void query_mlp_kernel(QueryMlpArgs p) {
     __shared__ __bf16 sW2[WTILE_ELEMS];
     __shared__ __bf16 sW3[WTILE_ELEMS];
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void query_mlp_kernel(QueryMlpArgs p) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const LinkGrid& lg = p.link[i];
     const Domain& dm = p.dom[i];
-    const float* G = p.grid + lg.offset;
+    const typename GridT<DT>::T* G = static_cast<const typename GridT<DT>::T*>(p.grid) + lg.offset;
     const int64_t t0 = p.tiles_per_link * blockIdx.x / gridDim.x;
     const int64_t t1 = p.tiles_per_link * (blockIdx.x + 1) / gridDim.x;
 
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void query_mlp_kernel(QueryMlpArgs p) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 if (!indom[nt]) continue;
-                const float v = m[nt] < p.margin ? sample_or_inf<CUBIC>(G, lg, gm, px[nt][0], px[nt][1], px[nt][2])
+                const float v = m[nt] < p.margin ? sample_or_inf<CUBIC, DT>(G, lg, gm, px[nt][0], px[nt][1], px[nt][2])
                                                  : m[nt];
                 best = fminf(best, v);
             }
@@ -636,15 +636,17 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
     if (ws_bytes < need) return fail(LSDF_E_SHAPE, "query_mlp: workspace has %zu bytes, needs %zu", ws_bytes, need);
     QueryMlpArgs a{};
     bool cubic = true;
+    const int dtype = grids[0].dtype;
     for (int i = 0; i < L; ++i) {
         if ((rc = prepare_link_grid(grids[i], i, &a.link[i])) != LSDF_OK) return rc;
         if ((rc = make_domain(domains[i], i, &a.dom[i])) != LSDF_OK) return rc;
+        if (grids[i].dtype != dtype) return fail(LSDF_E_UNSUPPORTED, "query_mlp: grids of one query must share a dtype");
         cubic = cubic && a.link[i].cubic;
     }
     hipStream_t s = as_stream(stream);
     a.link_T = link_T;
     a.params = mlp_params;
-    a.grid = static_cast<const float*>(grid_buf);
+    a.grid = grid_buf;
     a.points = points;
     a.keys = static_cast<uint32_t*>(workspace);
     a.M = M;
@@ -659,10 +661,14 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
         const int64_t per_link = std::max<int64_t>(
             1, std::min<int64_t>(((int64_t)cus * kBlocksPerCu + L - 1) / L, (a.tiles_per_link + kWaves - 1) / kWaves));
         const dim3 grid((unsigned)per_link, L);
-        if (cubic)
-            hipLaunchKernelGGL(query_mlp_kernel<true>, grid, dim3(kBlock), 0, s, a);
-        else
-            hipLaunchKernelGGL(query_mlp_kernel<false>, grid, dim3(kBlock), 0, s, a);
+        switch (dtype * 2 + (cubic ? 1 : 0)) {
+            case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((query_mlp_kernel<true, LSDF_F32>), grid, dim3(kBlock), 0, s, a); break;
+            case LSDF_F32 * 2: hipLaunchKernelGGL((query_mlp_kernel<false, LSDF_F32>), grid, dim3(kBlock), 0, s, a); break;
+            case LSDF_BF16 * 2 + 1: hipLaunchKernelGGL((query_mlp_kernel<true, LSDF_BF16>), grid, dim3(kBlock), 0, s, a); break;
+            case LSDF_BF16 * 2: hipLaunchKernelGGL((query_mlp_kernel<false, LSDF_BF16>), grid, dim3(kBlock), 0, s, a); break;
+            case LSDF_F16 * 2 + 1: hipLaunchKernelGGL((query_mlp_kernel<true, LSDF_F16>), grid, dim3(kBlock), 0, s, a); break;
+            default: hipLaunchKernelGGL((query_mlp_kernel<false, LSDF_F16>), grid, dim3(kBlock), 0, s, a); break;
+        }
         if ((rc = check_launch("query_min_distance_mlp")) != LSDF_OK) return rc;
     }
     return lsdf::launch_query_finalize(static_cast<uint32_t*>(workspace), out_dist, out_link, out_link_dist, C, L, s);

@@ -26,7 +26,7 @@ LSDF_MAX_COMPONENTS = 16
 LSDF_MLP_HIDDEN = 128
 LSDF_MLP_PARAMS = 33665
 
-DTYPE_CODES = {torch.float32: LSDF_F32}
+DTYPE_CODES = {torch.float32: LSDF_F32, torch.bfloat16: LSDF_BF16, torch.float16: LSDF_F16}
 
 
 class LsdfError(RuntimeError):
@@ -136,7 +136,7 @@ def _require(t: torch.Tensor, name: str, dtype, shape=None):
 class GridSet:
     """Descriptors of L link grids packed into one device buffer."""
 
-    def __init__(self, lo, hi, n, buf: torch.Tensor | None = None, device=None):
+    def __init__(self, lo, hi, n, buf: torch.Tensor | None = None, device=None, dtype=torch.float32):
         lo = np.asarray(lo, dtype=np.float32).reshape(-1, 3)
         hi = np.asarray(hi, dtype=np.float32).reshape(-1, 3)
         n = np.asarray(n, dtype=np.int64).reshape(-1, 3)
@@ -156,11 +156,12 @@ class GridSet:
                 d.lo[a] = float(lo[i, a])
                 d.hi[a] = float(hi[i, a])
                 d.n[a] = int(n[i, a])
-            d.dtype = LSDF_F32
+            d.dtype = DTYPE_CODES[dtype]
             d.elem_offset = int(self.offsets[i])
+        self.dtype = dtype
         if buf is None:
-            buf = torch.empty(self.total, dtype=torch.float32, device=device or "cuda")
-        _require(buf, "grid buffer", torch.float32)
+            buf = torch.empty(self.total, dtype=dtype, device=device or "cuda")
+        _require(buf, "grid buffer", dtype)
         if buf.numel() < self.total:
             raise ValueError(f"grid buffer holds {buf.numel()} elements, descriptors need {self.total}")
         self.buf = buf
@@ -171,7 +172,9 @@ class GridSet:
         return self.buf[o:o + int(nx) * int(ny) * int(nz)].view(int(nz), int(ny), int(nx))
 
     def set_grid(self, i: int, values):
-        self.grid(i).copy_(torch.as_tensor(np.ascontiguousarray(values), dtype=torch.float32))
+        """Stores float values, rounded to the grid's storage type (nearest even)."""
+        v = torch.as_tensor(np.ascontiguousarray(values, dtype=np.float32), dtype=torch.float32)
+        self.grid(i).copy_(v.to(self.dtype))
 
 
 # ---------------------------------------------------------------------------
@@ -280,9 +283,9 @@ def build_link_sdf(verts: torch.Tensor, tris: torch.Tensor, comp_first, grids: G
                                    grids.buf.data_ptr(), _stream_handle(stream, verts.device)))
 
 
-def build_robot_grids(meshes, lo, hi, n, device="cuda", stream=None) -> GridSet:
+def build_robot_grids(meshes, lo, hi, n, device="cuda", stream=None, dtype=torch.float32) -> GridSet:
     """GridSet with every link's SDF built on the GPU from its mesh."""
-    gs = GridSet(lo, hi, n, device=device)
+    gs = GridSet(lo, hi, n, device=device, dtype=dtype)
     for i, m in enumerate(meshes):
         v = torch.as_tensor(np.asarray(m.verts, dtype=np.float32), device=device)
         t = torch.as_tensor(np.asarray(m.tris, dtype=np.int32), device=device)

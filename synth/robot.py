@@ -262,17 +262,19 @@ def surface_points(mesh: Mesh, n: int, rng: np.random.Generator) -> np.ndarray:
     return ((1 - s)[:, None] * a[t] + (s * (1 - r2))[:, None] * b[t] + (s * r2)[:, None] * c[t])
 
 
-def mlp_samples(mesh: Mesh, lo, hi, n: int, seed: int, far: float = MLP_FAR, sigma: float = 0.02):
-    """n link-frame training positions: 40 % near the surface (surface point +
-    N(0, sigma)), 30 % uniform in the grid box, 30 % uniform in the domain."""
+def mlp_samples(mesh: Mesh, lo, hi, n: int, seed: int, far: float = MLP_FAR):
+    """n link-frame training positions: 35 % near the surface (surface point +
+    N(0, 2 cm)), 25 % in the band around it (surface point + N(0, 15 cm)),
+    20 % uniform in the grid box and 20 % uniform in the network's domain."""
     rng = np.random.default_rng(seed)
-    n_s, n_b = int(0.4 * n), int(0.3 * n)
-    n_d = n - n_s - n_b
+    n_near, n_band, n_box = int(0.35 * n), int(0.25 * n), int(0.2 * n)
+    n_dom = n - n_near - n_band - n_box
     cen, half = mlp_domain(lo, hi, far)
-    near = surface_points(mesh, n_s, rng) + rng.normal(0.0, sigma, size=(n_s, 3))
-    box = rng.uniform(lo, hi, size=(n_b, 3))
-    dom = rng.uniform(cen - half, cen + half, size=(n_d, 3))
-    pts = np.concatenate([near, box, dom])
+    near = surface_points(mesh, n_near, rng) + rng.normal(0.0, 0.02, size=(n_near, 3))
+    band = surface_points(mesh, n_band, rng) + rng.normal(0.0, 0.15, size=(n_band, 3))
+    box = rng.uniform(lo, hi, size=(n_box, 3))
+    dom = rng.uniform(cen - half, cen + half, size=(n_dom, 3))
+    pts = np.concatenate([near, band, box, dom])
     return pts[rng.permutation(n)]
 
 

@@ -184,6 +184,87 @@ def test_query_bit_exact_non_cubic_grids(B, orc, tiny):
     assert_bit_exact(run_query(B, T32, gs, pts), twin(orc, w, T32, grids, pts))
 
 
+def test_query_culling_is_exact_on_faces_and_nonrigid_poses(B, orc, tiny, tiny_grids):
+    """The block culling must never drop a pair the box test keeps: points
+    placed on box faces and corners (then jittered by a few ulps), and poses
+    whose rotation part is scaled and sheared, still give the twin's bits."""
+    rng = np.random.default_rng(33)
+    C = 40
+    T = orc.fk(tiny.robot.dh, tiny.q[:C], tiny.robot.base_T)
+    A = np.array([[1.3, 0.2, 0.0], [0.0, 0.7, 0.1], [0.05, 0.0, 1.1]])   # not a rotation
+    T[: C // 2, :, :, :3] = T[: C // 2, :, :, :3] @ A
+    T32 = T.astype(np.float32)
+    pts = []
+    for c in range(0, C, 3):
+        for i in range(tiny.L):
+            lo, hi = tiny.grid_lo[i].astype(np.float64), tiny.grid_hi[i].astype(np.float64)
+            for _ in range(6):
+                l = rng.uniform(lo, hi)
+                a = rng.integers(0, 3)
+                l[a] = lo[a] if rng.uniform() < 0.5 else hi[a]           # on a face
+                if rng.uniform() < 0.3:
+                    l = np.where(rng.uniform(size=3) < 0.5, lo, hi)     # a corner
+                R, t = T32[c, i, :, :3].astype(np.float64), T32[c, i, :, 3].astype(np.float64)
+                x = R @ l + t
+                pts.append(x * (1 + rng.integers(-4, 5, size=3) * 2.0 ** -23))
+    pts = np.array(pts, dtype=np.float32)
+    pts = np.concatenate([pts, tiny.points[:500].astype(np.float32)])
+    gs = upload_grids(B, tiny, tiny_grids)
+    gpu = run_query(B, T32, gs, pts)
+    ref = twin(orc, tiny, T32, tiny_grids, pts)
+    assert_bit_exact(gpu, ref)
+    assert np.isfinite(gpu[2]).mean() > 0.5
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_query_bit_exact_half_storage(B, orc, tiny, tiny_grids, paper, paper_grids, dt):
+    """16-bit grids: the kernel widens each corner exactly to FP32, so the
+    result equals the twin run on the rounded values, bit for bit."""
+    tdt = torch.bfloat16 if dt == "bf16" else torch.float16
+    for w, grids in ((tiny, tiny_grids), (paper, paper_grids)):
+        T32 = orc.fk(w.robot.dh, w.q, w.robot.base_T).astype(np.float32)
+        gs = B.GridSet(w.grid_lo, w.grid_hi, w.grid_n, device="cuda", dtype=tdt)
+        for i, g in enumerate(grids):
+            gs.set_grid(i, g.astype(np.float32))
+        rounded = [gs.grid(i).float().cpu().numpy().astype(np.float64) for i in range(w.L)]
+        pts = w.points.astype(np.float32)
+        say(f"query {dt} grids, {w.name}")
+        assert_bit_exact(run_query(B, T32, gs, pts), twin(orc, w, T32, rounded, pts))
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_build_link_sdf_half_storage(B, orc, tiny, tiny_grids, dt):
+    """build_link_sdf rounds its FP32 distance once into the storage type:
+    within one ulp of the storage format of the oracle's rounded value."""
+    tdt = torch.bfloat16 if dt == "bf16" else torch.float16
+    u = 2.0 ** -8 if dt == "bf16" else 2.0 ** -11
+    gs = B.build_robot_grids(tiny.robot.links, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, dtype=tdt)
+    torch.cuda.synchronize()
+    for i in range(tiny.L):
+        got = gs.grid(i).float().cpu().numpy().astype(np.float64)
+        want = torch.tensor(tiny_grids[i].astype(np.float32)).to(tdt).double().numpy()
+        assert np.all(np.abs(got - want) <= 2 * u * np.abs(want) + 1e-7), i
+
+
+def test_query_workspace_reuse_across_shapes(B, orc, tiny, tiny_grids):
+    """One workspace serving calls of different sizes: every call must leave
+    it all-zero (keys and culling scratch), so that a later call with more
+    configurations reads no stale bytes as keys."""
+    gs = upload_grids(B, tiny, tiny_grids)
+    rng = np.random.default_rng(34)
+    ws = torch.zeros(B.query_workspace_size(200, 7, 20000), dtype=torch.uint8, device="cuda")
+    for C, M in ((3, 2049), (129, 16385), (7, 300), (200, 20000)):
+        q = synth.make_waypoints(tiny.robot.qmin, tiny.robot.qmax, C, 199 + C)
+        T32 = orc.fk(tiny.robot.dh, q, tiny.robot.base_T).astype(np.float32)
+        origins = T32[:, :, :, 3].reshape(-1, 3).astype(np.float64)
+        pts = (origins[rng.integers(0, origins.shape[0], M)] + rng.normal(0, 0.15, size=(M, 3))).astype(np.float32)
+        say(f"shared workspace C={C} M={M}")
+        d, l, ld = B.query_min_distance(to_dev(T32), gs, to_dev(pts), link_dist=True, workspace=ws)
+        torch.cuda.synchronize()
+        assert int(ws.count_nonzero()) == 0
+        assert_bit_exact((d.cpu().numpy(), l.cpu().numpy(), ld.cpu().numpy()), twin(orc, tiny, T32, tiny_grids, pts))
+
+
 def test_query_workspace_cleared_and_repeatable(B, orc, tiny, tiny_grids):
     T32 = to_dev(orc.fk(tiny.robot.dh, tiny.q, tiny.robot.base_T).astype(np.float32))
     gs = upload_grids(B, tiny, tiny_grids)

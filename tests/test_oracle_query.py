@@ -247,3 +247,24 @@ def test_judge_min_against_brute_force(orc, tiny, tiny_grids):
     fin = np.isfinite(got)
     assert np.max(np.abs(got[fin] - want[fin])) < 1e-12
     assert (got[fin] < grid_cl[fin]).any() or np.isinf(grid_cl).any()   # some minima come from outside a box
+
+
+@pytest.mark.parametrize("dt,u", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -11)])
+def test_half_storage_error_bound(orc, tiny, tiny_grids, dt, u):
+    """Rounding the stored node values to a 16-bit format moves each node by
+    at most u |v| (u = 2^-8 for bfloat16, 2^-11 for binary16); trilinear
+    interpolation is a convex combination of 8 nodes, so every per-link
+    minimum moves by at most u times the largest |node| of its link (plus
+    the FP32 rounding of the interpolation itself)."""
+    import torch
+    tdt = torch.bfloat16 if dt == "bf16" else torch.float16
+    g32 = [g.astype(np.float32) for g in tiny_grids]
+    gq = [torch.tensor(g).to(tdt).float().numpy() for g in g32]
+    T32 = orc.fk(tiny.robot.dh, tiny.q, tiny.robot.base_T).astype(np.float32)
+    a = orc.query_f32(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, tiny.points)
+    b = orc.query_f32(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, gq, tiny.points)
+    assert np.array_equal(np.isfinite(a), np.isfinite(b))
+    fin = np.isfinite(a)
+    bound = np.array([u * np.abs(g).max() for g in g32])[None, :].repeat(a.shape[0], 0)
+    assert np.all(np.abs(a - b)[fin] <= bound[fin] * (1 + 1e-3) + 4e-7)
+    assert np.abs(a - b)[fin].max() > 0       # the rounding is visible
