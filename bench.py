@@ -21,7 +21,7 @@ if ROOT not in sys.path:
 
 METRIC = "ms per 500-waypoint batch; G point-link queries/s; grid vs MLP-SDF at ≤1 mm"
 PEAK_FP32_VECTOR_TFLOPS = 157.3       # MI355X published FP32 vector peak
-FLOP_PER_PAIR = 24                    # map to grid coordinates (9 FMA) + 6 box compares
+FLOP_PER_TEST = 24                    # map a point or a sphere centre to grid coordinates (9 FMA) + 6 compares
 FLOP_PER_INBOX_PAIR = 28              # cell + fraction (6), 7 lerps (21), min (1)
 BYTES_PER_INBOX_PAIR = 32             # 8 gathered FP32 corners
 
@@ -45,20 +45,52 @@ def profiled_traffic(kernel_source: str, summary: str):
         return None
 
 
-def count_inbox_pairs(T: np.ndarray, lo, hi, points: np.ndarray) -> int:
-    """Pairs (c, i, j) whose point lies in link i's box at waypoint c (double
-    precision; used only to price the in-box work for the roofline)."""
-    total = 0
+def culled_work(T: np.ndarray, lo, hi, points: np.ndarray, block: int = 8):
+    """Work of the culled method at waypoint-link granularity, in double
+    precision: (sphere tests, pairs in blocks whose sphere reaches the link's
+    box, pairs inside the box).  Every (waypoint, link, 8-point block) needs
+    one sphere test; a surviving block needs the point test of its points;
+    an in-box pair needs the interpolation.  Used only to price the kernel's
+    compulsory work for the roofline."""
     P = points.astype(np.float64)
+    M = P.shape[0]
+    nb = (M + block - 1) // block
+    pad = np.concatenate([P, np.repeat(P[-1:], nb * block - M, axis=0)]).reshape(nb, block, 3)
+    cnt = np.full(nb, block)
+    cnt[-1] = M - (nb - 1) * block
+    bmin, bmax = pad.min(axis=1), pad.max(axis=1)
+    cen = 0.5 * (bmin + bmax)
+    rad = np.sqrt(((pad - cen[:, None, :]) ** 2).sum(-1)).max(axis=1)
     C, L = T.shape[:2]
+    tests = C * L * nb
+    surv_pairs, inbox = 0, 0
     for i in range(L):
-        R = T[:, i, :, :3].astype(np.float64)     # [C][3][3]
-        t = T[:, i, :, 3].astype(np.float64)      # [C][3]
-        for c0 in range(0, C, 50):
-            l = np.einsum("cba,cjb->cja", R[c0:c0 + 50], P[None] - t[c0:c0 + 50, None, :])
-            inside = np.all((l >= lo[i]) & (l <= hi[i]), axis=-1)
-            total += int(inside.sum())
-    return total
+        mid = 0.5 * (lo[i] + hi[i])
+        hw = 0.5 * (hi[i] - lo[i])
+        R = T[:, i, :, :3].astype(np.float64)
+        t = T[:, i, :, 3].astype(np.float64)
+        for c0 in range(0, C, 25):
+            Rc, tc = R[c0:c0 + 25], t[c0:c0 + 25]
+            lc = np.einsum("cba,cjb->cja", Rc, cen[None] - tc[:, None, :])              # [c][block][3]
+            surv = np.all(np.abs(lc - mid) <= hw + rad[None, :, None], axis=-1)          # [c][block]
+            surv_pairs += int((surv * cnt[None, :]).sum())
+            lp = np.einsum("cba,cjb->cja", Rc, P[None] - tc[:, None, :])
+            inbox += int(np.all((lp >= lo[i]) & (lp <= hi[i]), axis=-1).sum())
+    return tests, surv_pairs, inbox
+
+
+_ORACLE_GRIDS = {}
+
+
+def oracle_grids(w):
+    """The oracle's double-precision grids of a workload's robot (cached by
+    node count: every workload uses the same robot and boxes)."""
+    import oracle
+    key = int(w.grid_n[0, 0])
+    if key not in _ORACLE_GRIDS:
+        log(f"oracle grids {key}^3 (double, brute force)")
+        _ORACLE_GRIDS[key] = oracle.workload_grids(w)
+    return _ORACLE_GRIDS[key]
 
 
 def cpu_baseline(w, budget_s: float = 12.0):
@@ -66,8 +98,8 @@ def cpu_baseline(w, budget_s: float = 12.0):
     workload, repeated for about budget_s seconds."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    log(f"cpu baseline: building oracle grids ({threads} threads)")
-    grids = oracle.workload_grids(w)
+    log(f"cpu baseline ({threads} threads)")
+    grids = oracle_grids(w)
     reps, t_total = 0, 0.0
     while t_total < budget_s and reps < 200:
         t0 = time.perf_counter()
@@ -138,7 +170,7 @@ def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 8):
     # judge: exact minimum of grid-in-box / mesh-outside over each link's domain
     sel = np.linspace(0, w.C - 1, judge_waypoints).round().astype(int)
     log(f"learned variant: judging {len(sel)} waypoints with the oracle")
-    grids = oracle.workload_grids(w)
+    grids = oracle_grids(w)
     T64 = oracle.fk(w.robot.dh, w.q[sel], w.robot.base_T)
     jcl = oracle.judge_min(T64, w.grid_lo, w.grid_hi, w.grid_n, grids, w.robot.links, cen, half, w.points)
     judge, _ = oracle.reduce(jcl)
@@ -164,6 +196,118 @@ def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 8):
     }
 
 
+def precision_variant(dev, steps: int, judge_waypoints: int = 16):
+    """128^3 grids stored as FP32, bfloat16 and binary16 on the 500 x 100,000
+    x 7 workload: time per batch and the per-waypoint clearance error against
+    the double-precision oracle (its own grids, kinematics and query) on
+    sampled waypoints."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_2309_12543_amd import lsdf
+
+    w = synth.make_workload("precision")
+    log(f"precision variant: C={w.C} M={w.M} L={w.L} n={int(w.grid_n[0, 0])}")
+    q = torch.as_tensor(w.q, dtype=torch.float32, device=dev)
+    pts = torch.as_tensor(w.points, dtype=torch.float32, device=dev)
+    T = lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T)
+    ws = torch.zeros(lsdf.query_workspace_size(w.C, w.L, w.M), dtype=torch.uint8, device=dev)
+    sel = np.linspace(0, w.C - 1, judge_waypoints).round().astype(int)
+    grids = oracle_grids(w)
+    T64 = oracle.fk(w.robot.dh, w.q[sel], w.robot.base_T)
+    ref, _ = oracle.reduce(oracle.query_f64(T64, w.grid_lo, w.grid_hi, w.grid_n, grids, w.points))
+    out = {"workload": f"{w.name}: {w.C} waypoints x {w.M} points x {w.L} links, {int(w.grid_n[0, 0])}^3 grids",
+           "judged_waypoints": int(len(sel))}
+    for name, tdt in (("f32", torch.float32), ("bf16", torch.bfloat16), ("f16", torch.float16)):
+        gs = lsdf.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device=dev, dtype=tdt)
+        res = (torch.empty(w.C, device=dev), torch.empty(w.C, dtype=torch.int32, device=dev), None)
+        ms = time_calls(lambda: lsdf.query_min_distance(T, gs, pts, workspace=ws, out=res), steps, 5)
+        d = res[0].cpu().numpy().astype(np.float64)[sel]
+        both = np.isfinite(d) & np.isfinite(ref)
+        err = np.abs(d[both] - ref[both]) * 1e3
+        out[name] = {"query_ms": round(ms, 4), "grid_mb": round(gs.buf.numel() * gs.buf.element_size() / 1e6, 2),
+                     "max_err_mm": round(float(err.max()), 4) if err.size else None,
+                     "mean_err_mm": round(float(err.mean()), 4) if err.size else None,
+                     "finite_pattern_equal": bool(np.array_equal(np.isfinite(d), np.isfinite(ref)))}
+        del gs
+    return out
+
+
+def batched_variant(dev, steps: int, warmup: int):
+    """64 re-planned trajectories, each against its own cloud (50-1,000
+    waypoints and 5,000-200,000 points per trajectory, 64^3 FP32 grids), in
+    one batched call: the tiling picked by the autotuner, then the step
+    (kinematics of every waypoint + the batched query) timed eagerly and as a
+    graph replay, and the query kernel alone."""
+    import torch
+
+    import synth
+    from paper_2309_12543_amd import lsdf
+    from paper_2309_12543_amd.step_graph import StepGraph
+
+    t0 = time.perf_counter()
+    w = synth.make_batched()
+    log(f"batched variant: K={w.K} sum C={w.C} sum M={w.M} ({time.perf_counter() - t0:.1f} s to generate)")
+    gs = lsdf.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device=dev)
+    q = torch.as_tensor(w.q, dtype=torch.float32, device=dev)
+    pts = torch.as_tensor(w.points, dtype=torch.float32, device=dev)
+    co = torch.as_tensor(w.c_off, dtype=torch.int32, device=dev)
+    mo = torch.as_tensor(w.m_off, dtype=torch.int64, device=dev)
+    T = lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T)
+    ws = torch.zeros(lsdf.query_batched_workspace_size(w.K, w.C, w.L, w.M), dtype=torch.uint8, device=dev)
+    best, best_ms, _ = lsdf.query_autotune(T, gs, pts, co, mo, reps=3, workspace=ws)
+    log(f"batched variant: autotuner picked {best} ({best_ms:.3f} ms per call)")
+    res = {}
+    for name, tun in (("default", None), ("tuned", best)):
+        out = (torch.empty(w.C, device=dev), torch.empty(w.C, dtype=torch.int32, device=dev), None)
+        kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in kev:
+            a.record()
+            b.record()
+        it = iter(range(10 ** 9))
+
+        def one(timed):
+            lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T, out=T)
+            if timed:
+                lsdf.set_kernel_events(*kev[next(it)])
+            lsdf.query_min_distance_batched(T, gs, pts, co, mo, tuning=tun, workspace=ws, out=out)
+
+        for _ in range(warmup):
+            one(False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            one(True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / steps
+        kms = float(np.mean([a.elapsed_time(b) for a, b in kev]))
+        res[name] = {"ms_per_step": round(ms, 4), "query_kernel_ms": round(kms, 4), "out": out}
+    sg = StepGraph(w.robot.dh, w.robot.base_T, gs, w.C, w.M, w.K, tuning=best)
+    sg.load(q, pts, co, mo)
+    graph_ms = time_calls(sg.replay, steps, warmup)
+    d_t, l_t, _ = res["tuned"]["out"]
+    d_d, l_d, _ = res["default"]["out"]
+    same = bool(torch.equal(sg.dist.view(torch.int32), d_t.view(torch.int32)) and torch.equal(sg.link, l_t)
+                and torch.equal(d_d.view(torch.int32), d_t.view(torch.int32)) and torch.equal(l_d, l_t))
+    pairs = w.pairs()
+    for r in res.values():
+        r.pop("out")
+    return {
+        "workload": f"batched: {w.K} trajectories, waypoints U{{50..1000}} (sum {w.C}), points U{{5000..200000}} "
+                    f"(sum {w.M}), {w.L} links, 64^3 FP32 grids, own scene per trajectory",
+        "pairs": pairs,
+        "autotuned": {"chunk_points": best.chunk_points, "blocks_per_cu": best.blocks_per_cu,
+                      "autotune_ms_per_call": round(best_ms, 4)},
+        "default": res["default"],
+        "tuned": res["tuned"],
+        "graph_replay_ms_per_step": round(graph_ms, 4),
+        "gq_s_tuned_eager": round(pairs / (res["tuned"]["ms_per_step"] / 1e3) / 1e9, 1),
+        "gq_s_graph": round(pairs / (graph_ms / 1e3) / 1e9, 1),
+        "results_identical_across_tilings_and_graph": same,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +318,8 @@ def main():
     ap.add_argument("--learned-epochs", type=int, default=400,
                     help="training epochs of the learned variant (0 skips the learned variant)")
     ap.add_argument("--learned-steps", type=int, default=5)
+    ap.add_argument("--no-precision", action="store_true", help="skip the 128^3 bf16/fp16 storage variant")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-trajectory batched variant")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB mebibytes (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -210,34 +356,52 @@ def main():
     ws = torch.zeros(lsdf.query_workspace_size(w.C, w.L, w.M), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
-    def step(ev=None):
+    # per step: events around the query call, and events the library records
+    # around the query kernel alone (lsdf_set_kernel_events)
+    call_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+    kern_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+    for a, b in call_ev + kern_ev:      # create the events before handing them to the library
+        a.record()
+        b.record()
+
+    def step(k=None):
         lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T, out=T)
-        if ev is not None:
-            ev[0].record()
+        if k is not None:
+            call_ev[k][0].record()
+            lsdf.set_kernel_events(*kern_ev[k])
         lsdf.query_min_distance(T, gs, pts, workspace=ws, out=(dist, link, None))
-        if ev is not None:
-            ev[1].record()
+        if k is not None:
+            call_ev[k][1].record()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
     log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(events[k])
+        step(k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    call_ms = float(np.mean([a.elapsed_time(b) for a, b in call_ev]))
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in kern_ev]))
     pairs = w.C * w.M * w.L
     value = pairs / (ms_per_step / 1e3) / 1e9
 
+    # the same step captured once in a graph and replayed
+    from paper_2309_12543_amd.step_graph import StepGraph
+    sg = StepGraph(w.robot.dh, w.robot.base_T, gs, w.C, w.M, 1)
+    sg.load(q, pts, torch.tensor([0, w.C], dtype=torch.int32, device=dev),
+            torch.tensor([0, w.M], dtype=torch.int64, device=dev))
+    graph_ms = time_calls(sg.replay, args.steps, args.warmup)
+    same = bool(torch.equal(sg.dist.view(torch.int32), dist.view(torch.int32)) and torch.equal(sg.link, link))
+    del sg
+
     Tn = T.cpu().numpy()
-    inbox = count_inbox_pairs(Tn, w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64), w.points)
-    flop = FLOP_PER_PAIR * pairs + FLOP_PER_INBOX_PAIR * inbox
+    tests, surv_pairs, inbox = culled_work(Tn, w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64), w.points)
+    flop = FLOP_PER_TEST * (tests + surv_pairs) + FLOP_PER_INBOX_PAIR * inbox
     achieved = flop / (kernel_ms / 1e3) / 1e12
     rec = {
         "metric": METRIC,
@@ -256,17 +420,28 @@ def main():
                                f"{int(w.grid_n[0, 0])}^3 FP32 link grids",
                    "waypoints": w.C, "points": w.M, "links": w.L, "grid_nodes": int(w.grid_n[0, 0]),
                    "parallelism": "single GPU"},
+        "query_call_ms": round(call_ms, 5),
         "query_kernel_ms": round(kernel_ms, 5),
+        "graph_replay_ms_per_step": round(graph_ms, 5),
+        "graph_equals_eager": same,
         "inbox_pair_fraction": round(inbox / pairs, 5),
+        "sphere_survivor_pair_fraction": round(surv_pairs / pairs, 5),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
                      "traffic": profiled_traffic(os.path.join(ROOT, "paper_2309_12543_amd", "csrc", "query.hip"),
                                                  os.path.join(ROOT, "profiles", "query_kernel_paper.txt")),
-                     "kernel": "query_kernel (timed with its finalize kernel: one lsdf_query_min_distance call)",
-                     "algorithmic_flop": flop},
+                     "kernel": "query_kernel (its own launch, timed by events the library records around it)",
+                     "algorithmic_flop": flop,
+                     "work": {"sphere_tests": tests, "point_tests_in_surviving_blocks": surv_pairs,
+                              "inbox_pairs": inbox, "flop_per_test": FLOP_PER_TEST,
+                              "flop_per_inbox_pair": FLOP_PER_INBOX_PAIR}},
     }
     if args.learned_epochs > 0:
         rec["learned"] = learned_variant(dev, args.learned_epochs, args.learned_steps)
+    if not args.no_precision:
+        rec["precision"] = precision_variant(dev, 50)
+    if not args.no_batched:
+        rec["batched"] = batched_variant(dev, 20, 3)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)

@@ -56,6 +56,8 @@ extern "C" {
 #define LSDF_MAX_LINKS      16    /* links per query (dof + 1 for a serial arm) */
 #define LSDF_MAX_DOF        15
 #define LSDF_MAX_COMPONENTS 16    /* closed parts per link mesh */
+#define LSDF_MAX_TRAJECTORIES 65536          /* trajectories per batched query */
+#define LSDF_MAX_POINTS (((int64_t)1) << 34) /* obstacle points per query */
 
 /* One link's SDF grid (the "Link SDF" of Sec. III-A: extent e_r, resolution
  * r_r, in the link's own frame).  Node-centred: node k = (kx, ky, kz),
@@ -90,6 +92,16 @@ int lsdf_version(void);
  * pointer stays valid until the next library call on the same thread. */
 const char* lsdf_last_error(void);
 
+/* Measurement aid: the calling thread's next clearance query (plain,
+ * batched or learned) records `before` on its stream just before launching
+ * its main kernel and `after` just after it, so that the elapsed time
+ * between the two events is that kernel's alone (without the small set-up
+ * and finalising kernels around it).  before and after are hipEvent_t
+ * created by the caller, passed as void*; both or neither (NULL, NULL
+ * clears the setting).  The setting is used by one query and then cleared;
+ * a query whose point count is 0 launches no main kernel and leaves it. */
+int lsdf_set_kernel_events(void* before, void* after);
+
 /* ---- forward kinematics ----------------------------------------------------
  * Sec. III-A: the transformations T_{i,c} of every link i at every
  * configuration c, by forward kinematics run in parallel over c.
@@ -121,7 +133,7 @@ int lsdf_fk_batch(const lsdf_dh* dh, int32_t dof, const float* base_T,
  *                 and not written by the caller afterwards: every call
  *                 returns it to all-zero when it completes.  Calls that share
  *                 a workspace must not overlap in time (same stream is fine).
- * -0 is returned as +0.  M = 0 gives (+inf, -1) everywhere; C = 0 enqueues
+ * M <= LSDF_MAX_POINTS.  -0 is returned as +0.  M = 0 gives (+inf, -1) everywhere; C = 0 enqueues
  * nothing.  The arithmetic is FP32 in a fixed operation order (per link and
  * configuration the world-to-grid map is formed once as one affine matrix,
  * the form of Eq. 4; the lerp is fma(f, b, fma(-f, a, a))), so results are
@@ -133,6 +145,60 @@ int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L,
                             const float* points, int64_t M,
                             float* out_dist, int32_t* out_link, float* out_link_dist,
                             uint32_t flags, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- batched clearance query ----------------------------------------------
+ * The same quantity for K trajectories in one call.  The paper re-plans a
+ * path of a few hundred configurations against each new cloud, over and
+ * over (Sec. IV); this call takes many such (path, cloud) pairs at once.
+ * Trajectory k pairs configurations [c_off[k], c_off[k+1]) of link_T with
+ * points [m_off[k], m_off[k+1]) of points; each configuration's result
+ * is the plain query's over its own trajectory's points, bit for bit.
+ *   K             number of trajectories, 1 <= K <= LSDF_MAX_TRAJECTORIES
+ *   traj_c_offset DEVICE int32 [K+1], non-decreasing, in [0, C]
+ *   traj_m_offset DEVICE int64 [K+1], non-decreasing, in [0, M]
+ *   C, M          sizes of link_T / out_* and points (capacities: rows not
+ *                 covered by any trajectory get (+inf, -1))
+ *   tuning        work tiling, or NULL for the defaults (see below); it
+ *                 changes the speed only, never a result bit
+ *   other arguments as lsdf_query_min_distance; the workspace is sized by
+ *   lsdf_query_batched_workspace_size(K, C, L, M) under the same rules.
+ * The offsets are read on the device only, so the call copies nothing to or
+ * from the host and can be captured in a HIP graph and replayed with new
+ * offset, pose and point contents (same C, M, K capacities).  Offsets out
+ * of order or out of range are clamped into [0, C] and [0, M] on the device:
+ * the results are then meaningless, but no access leaves the buffers. */
+typedef struct {
+    int32_t chunk_points;   /* points per work chunk: a multiple of 8 in
+                               [8, 8192]; 0 = default (32) */
+    int32_t blocks_per_cu;  /* workgroups of the persistent grid per compute
+                               unit, in [1, 16]; 0 = default (8) */
+} lsdf_query_tuning;
+
+int lsdf_query_batched_workspace_size(int32_t K, int32_t C, int32_t L, int64_t M, size_t* bytes);
+
+int lsdf_query_min_distance_batched(int32_t K, const int32_t* traj_c_offset, const int64_t* traj_m_offset,
+                                    const float* link_T, int32_t C, int32_t L,
+                                    const lsdf_grid* grids, const void* grid_buf,
+                                    const float* points, int64_t M,
+                                    float* out_dist, int32_t* out_link, float* out_link_dist,
+                                    const lsdf_query_tuning* tuning, uint32_t flags,
+                                    void* workspace, size_t ws_bytes, void* stream);
+
+/* Picks the fastest tiling for one batched problem by timing it.
+ * Runs lsdf_query_min_distance_batched once untimed and `reps` times timed
+ * (HIP events on `stream`) per candidate, and returns the candidate with
+ * the lowest mean time in *best (and that time in ms in *best_ms, which may
+ * be NULL).  candidates = NULL uses a built-in list (chunk_points 8 to 1024
+ * at 8 workgroups per CU, fewer at 2 and 4).  1 <= reps <= 1000.
+ * It SYNCHRONISES the stream (not capturable); out_dist / out_link hold the
+ * problem's results when it returns LSDF_OK. */
+int lsdf_query_autotune(int32_t K, const int32_t* traj_c_offset, const int64_t* traj_m_offset,
+                        const float* link_T, int32_t C, int32_t L,
+                        const lsdf_grid* grids, const void* grid_buf,
+                        const float* points, int64_t M, float* out_dist, int32_t* out_link,
+                        const lsdf_query_tuning* candidates, int32_t n_candidates, int32_t reps,
+                        void* workspace, size_t ws_bytes, void* stream,
+                        lsdf_query_tuning* best, float* best_ms);
 
 /* ---- link SDF construction -------------------------------------------------
  * Sec. III-A: each link's signed distance field is computed once, offline,

@@ -195,6 +195,29 @@ def query_f32(T, lo, hi, n, grids, points) -> np.ndarray:
     return out
 
 
+def query_batched(query, T, lo, hi, n, grids, points, c_off, m_off) -> np.ndarray:
+    """Per-link minima [C][L] of a batch of trajectories: trajectory k's
+    configurations [c_off[k], c_off[k+1]) against its points [m_off[k],
+    m_off[k+1]), one plain query per trajectory (query = query_f32 or
+    query_f64).  Offsets are clamped as the library does: c into [0, C] and
+    non-decreasing from c_off[k], m likewise into [0, M]; a configuration
+    covered by several trajectories takes the minimum over them, and one
+    covered by none stays +inf."""
+    T = np.asarray(T)
+    P = np.asarray(points).reshape(-1, 3)
+    C, L, M = T.shape[0], T.shape[1], P.shape[0]
+    out = np.full((C, L), np.inf)
+    for k in range(len(c_off) - 1):
+        c0 = min(max(int(c_off[k]), 0), C)
+        c1 = min(max(int(c_off[k + 1]), c0), C)
+        m0 = min(max(int(m_off[k]), 0), M)
+        m1 = min(max(int(m_off[k + 1]), m0), M)
+        if c1 > c0 and m1 > m0:
+            part = query(T[c0:c1], lo, hi, n, grids, P[m0:m1])
+            out[c0:c1] = np.minimum(out[c0:c1], part)
+    return out
+
+
 def exact_min(T, meshes, points) -> np.ndarray:
     """Grid-free per-link minima [C][L]: exact mesh SDF at every point."""
     lib = load()
@@ -329,5 +352,5 @@ def mlp_unpack(params):
 
 
 __all__ = ["build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
-           "query_f32", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids",
+           "query_batched", "query_f32", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids",
            "MLP_HIDDEN", "adam_step", "judge_min", "mlp_forward", "mlp_loss_grad", "mlp_nparam", "mlp_unpack"]

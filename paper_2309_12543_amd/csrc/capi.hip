@@ -7,9 +7,17 @@ namespace lsdf {
 
 namespace {
 thread_local char g_err[512] = "";
+thread_local hipEvent_t g_ev_before = nullptr;
+thread_local hipEvent_t g_ev_after = nullptr;
 }
 
 void clear_error() { g_err[0] = '\0'; }
+
+void take_kernel_events(hipEvent_t* before, hipEvent_t* after) {
+    *before = g_ev_before;
+    *after = g_ev_after;
+    g_ev_before = g_ev_after = nullptr;
+}
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -51,3 +59,12 @@ int prepare_link_grid(const lsdf_grid& g, int index, LinkGrid* out) {
 LSDF_API int lsdf_version(void) { return (0 << 16) | (1 << 8) | 0; }
 
 LSDF_API const char* lsdf_last_error(void) { return lsdf::g_err; }
+
+LSDF_API int lsdf_set_kernel_events(void* before, void* after) {
+    lsdf::clear_error();
+    if ((before == nullptr) != (after == nullptr))
+        return lsdf::fail(LSDF_E_INVALID_ARG, "set_kernel_events: give both events or neither");
+    lsdf::g_ev_before = static_cast<hipEvent_t>(before);
+    lsdf::g_ev_after = static_cast<hipEvent_t>(after);
+    return LSDF_OK;
+}

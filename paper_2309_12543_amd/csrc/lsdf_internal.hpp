@@ -60,6 +60,10 @@ struct LinkGrid {
 
 int prepare_link_grid(const lsdf_grid& g, int index, LinkGrid* out);
 
+// Events set by lsdf_set_kernel_events for the calling thread's next query
+// (both NULL when none); taking them clears the setting.
+void take_kernel_events(hipEvent_t* before, hipEvent_t* after);
+
 // Turns the query workspace keys into out_dist / out_link / out_link_dist
 // and clears them (shared by the plain and the learned query).
 int launch_query_finalize(uint32_t* keys, float* out_dist, int32_t* out_link, float* out_link_dist, int32_t C,

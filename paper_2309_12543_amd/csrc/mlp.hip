@@ -661,6 +661,9 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
         const int64_t per_link = std::max<int64_t>(
             1, std::min<int64_t>(((int64_t)cus * kBlocksPerCu + L - 1) / L, (a.tiles_per_link + kWaves - 1) / kWaves));
         const dim3 grid((unsigned)per_link, L);
+        hipEvent_t ev0, ev1;
+        take_kernel_events(&ev0, &ev1);
+        if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return fail(LSDF_E_DEVICE, "query_mlp: event record failed");
         switch (dtype * 2 + (cubic ? 1 : 0)) {
             case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((query_mlp_kernel<true, LSDF_F32>), grid, dim3(kBlock), 0, s, a); break;
             case LSDF_F32 * 2: hipLaunchKernelGGL((query_mlp_kernel<false, LSDF_F32>), grid, dim3(kBlock), 0, s, a); break;
@@ -670,6 +673,7 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
             default: hipLaunchKernelGGL((query_mlp_kernel<false, LSDF_F16>), grid, dim3(kBlock), 0, s, a); break;
         }
         if ((rc = check_launch("query_min_distance_mlp")) != LSDF_OK) return rc;
+        if (ev1 && hipEventRecord(ev1, s) != hipSuccess) return fail(LSDF_E_DEVICE, "query_mlp: event record failed");
     }
     return lsdf::launch_query_finalize(static_cast<uint32_t*>(workspace), out_dist, out_link, out_link_dist, C, L, s);
 }

@@ -44,6 +44,13 @@ class lsdf_mlp_domain(ct.Structure):
     _fields_ = [("centre", ct.c_float * 3), ("half", ct.c_float * 3)]
 
 
+class lsdf_query_tuning(ct.Structure):
+    _fields_ = [("chunk_points", ct.c_int32), ("blocks_per_cu", ct.c_int32)]
+
+    def __repr__(self):
+        return f"lsdf_query_tuning(chunk_points={self.chunk_points}, blocks_per_cu={self.blocks_per_cu})"
+
+
 class lsdf_dh(ct.Structure):
     _fields_ = [("a", ct.c_float), ("alpha", ct.c_float), ("d", ct.c_float), ("theta_offset", ct.c_float)]
 
@@ -73,6 +80,17 @@ def load_library():
     lib.lsdf_query_min_distance.restype = ct.c_int
     lib.lsdf_query_min_distance.argtypes = [vp, i32, i32, ct.POINTER(lsdf_grid), vp, vp, i64, vp, vp, vp,
                                             u32, vp, sz, vp]
+    lib.lsdf_set_kernel_events.restype = ct.c_int
+    lib.lsdf_set_kernel_events.argtypes = [vp, vp]
+    tun = ct.POINTER(lsdf_query_tuning)
+    lib.lsdf_query_batched_workspace_size.restype = ct.c_int
+    lib.lsdf_query_batched_workspace_size.argtypes = [i32, i32, i32, i64, ct.POINTER(sz)]
+    lib.lsdf_query_min_distance_batched.restype = ct.c_int
+    lib.lsdf_query_min_distance_batched.argtypes = [i32, vp, vp, vp, i32, i32, ct.POINTER(lsdf_grid), vp, vp, i64,
+                                                    vp, vp, vp, tun, u32, vp, sz, vp]
+    lib.lsdf_query_autotune.restype = ct.c_int
+    lib.lsdf_query_autotune.argtypes = [i32, vp, vp, vp, i32, i32, ct.POINTER(lsdf_grid), vp, vp, i64, vp, vp,
+                                        tun, i32, i32, vp, sz, vp, tun, ct.POINTER(ct.c_float)]
     lib.lsdf_build_link_sdf.restype = ct.c_int
     lib.lsdf_build_link_sdf.argtypes = [vp, i32, vp, i32, ct.POINTER(ct.c_int32), i32, ct.POINTER(lsdf_grid),
                                         vp, vp]
@@ -202,19 +220,30 @@ def fk_batch(dh, q: torch.Tensor, base_T=None, out: torch.Tensor | None = None, 
     return out
 
 
+def set_kernel_events(before=None, after=None):
+    """The next query on this thread records torch.cuda.Event ``before`` /
+    ``after`` around its main kernel (lsdf_set_kernel_events).  The events
+    must already exist (record them once first)."""
+    h = lambda e: None if e is None else ct.c_void_p(e.cuda_event)
+    _check(load_library().lsdf_set_kernel_events(h(before), h(after)))
+
+
 def query_workspace_size(C: int, L: int, M: int) -> int:
     n = ct.c_size_t(0)
     _check(load_library().lsdf_query_workspace_size(C, L, M, ct.byref(n)))
     return int(n.value)
 
 
+def query_batched_workspace_size(K: int, C: int, L: int, M: int) -> int:
+    n = ct.c_size_t(0)
+    _check(load_library().lsdf_query_batched_workspace_size(K, C, L, M, ct.byref(n)))
+    return int(n.value)
+
+
 _workspaces: dict = {}
 
 
-def query_workspace(C: int, L: int, M: int, device) -> torch.Tensor:
-    """A zero-filled workspace, cached per device and kept for reuse (every
-    call leaves it zero-filled again)."""
-    need = query_workspace_size(C, L, M)
+def _cached_workspace(need: int, device) -> torch.Tensor:
     dev = torch.device(device)
     key = (dev.type, dev.index if dev.index is not None else torch.cuda.current_device())
     ws = _workspaces.get(key)
@@ -224,12 +253,13 @@ def query_workspace(C: int, L: int, M: int, device) -> torch.Tensor:
     return ws
 
 
-def query_min_distance(link_T: torch.Tensor, grids: GridSet, points: torch.Tensor, *,
-                       link_dist: bool = False, workspace: torch.Tensor | None = None,
-                       out=None, stream=None):
-    """Per configuration: (clearance [C] float32, argmin link [C] int32, and
-    per-link minima [C][L] when ``link_dist``) (lsdf_query_min_distance)."""
-    lib = load_library()
+def query_workspace(C: int, L: int, M: int, device, K: int = 1) -> torch.Tensor:
+    """A zero-filled workspace, cached per device and kept for reuse (every
+    call leaves it zero-filled again)."""
+    return _cached_workspace(query_batched_workspace_size(K, C, L, M), device)
+
+
+def _query_shapes(link_T, grids, points):
     if link_T.dim() != 4 or tuple(link_T.shape[2:]) != (3, 4):
         raise ValueError("link_T must be [C][L][3][4]")
     _require(link_T, "link_T", torch.float32)
@@ -243,6 +273,10 @@ def query_min_distance(link_T: torch.Tensor, grids: GridSet, points: torch.Tenso
     dev = link_T.device
     if grids.buf.device != dev or points.device != dev:
         raise ValueError("link_T, grids and points must be on one device")
+    return C, L, M, dev
+
+
+def _query_outputs(out, C, L, dev, link_dist):
     if out is None:
         dist = torch.empty(C, dtype=torch.float32, device=dev)
         link = torch.empty(C, dtype=torch.int32, device=dev)
@@ -253,6 +287,21 @@ def query_min_distance(link_T: torch.Tensor, grids: GridSet, points: torch.Tenso
     _require(link, "out_link", torch.int32, (C,))
     if ld is not None:
         _require(ld, "out_link_dist", torch.float32, (C, L))
+    return dist, link, ld
+
+
+def make_tuning(chunk_points: int = 0, blocks_per_cu: int = 0) -> lsdf_query_tuning:
+    return lsdf_query_tuning(int(chunk_points), int(blocks_per_cu))
+
+
+def query_min_distance(link_T: torch.Tensor, grids: GridSet, points: torch.Tensor, *,
+                       link_dist: bool = False, workspace: torch.Tensor | None = None,
+                       out=None, stream=None):
+    """Per configuration: (clearance [C] float32, argmin link [C] int32, and
+    per-link minima [C][L] when ``link_dist``) (lsdf_query_min_distance)."""
+    lib = load_library()
+    C, L, M, dev = _query_shapes(link_T, grids, points)
+    dist, link, ld = _query_outputs(out, C, L, dev, link_dist)
     if workspace is None:
         workspace = query_workspace(C, L, M, dev)
     _require(workspace, "workspace", torch.uint8)
@@ -262,6 +311,64 @@ def query_min_distance(link_T: torch.Tensor, grids: GridSet, points: torch.Tenso
         ld.data_ptr() if ld is not None else None, 0, workspace.data_ptr(), workspace.numel(),
         _stream_handle(stream, dev)))
     return (dist, link, ld) if link_dist else (dist, link)
+
+
+def _offsets(c_off: torch.Tensor, m_off: torch.Tensor, dev):
+    _require(c_off, "c_offsets", torch.int32)
+    _require(m_off, "m_offsets", torch.int64)
+    if c_off.dim() != 1 or m_off.dim() != 1 or c_off.numel() != m_off.numel() or c_off.numel() < 2:
+        raise ValueError("c_offsets and m_offsets must be [K+1] with K >= 1")
+    if c_off.device != dev or m_off.device != dev:
+        raise ValueError("offsets must be on the query's device")
+    return int(c_off.numel()) - 1
+
+
+def query_min_distance_batched(link_T: torch.Tensor, grids: GridSet, points: torch.Tensor, c_offsets: torch.Tensor,
+                               m_offsets: torch.Tensor, *, link_dist: bool = False, tuning=None,
+                               workspace: torch.Tensor | None = None, out=None, stream=None):
+    """K trajectories in one call (lsdf_query_min_distance_batched):
+    trajectory k pairs poses link_T[c_offsets[k]:c_offsets[k+1]] with
+    points[m_offsets[k]:m_offsets[k+1]].  The offsets are device tensors
+    (int32 and int64, [K+1]) and are never read on the host."""
+    lib = load_library()
+    C, L, M, dev = _query_shapes(link_T, grids, points)
+    K = _offsets(c_offsets, m_offsets, dev)
+    dist, link, ld = _query_outputs(out, C, L, dev, link_dist)
+    if workspace is None:
+        workspace = query_workspace(C, L, M, dev, K=K)
+    _require(workspace, "workspace", torch.uint8)
+    tun = ct.byref(tuning) if tuning is not None else None
+    _check(lib.lsdf_query_min_distance_batched(
+        K, c_offsets.data_ptr(), m_offsets.data_ptr(), link_T.data_ptr(), C, L, grids.desc, grids.buf.data_ptr(),
+        points.data_ptr() if M > 0 else None, M, dist.data_ptr(), link.data_ptr(),
+        ld.data_ptr() if ld is not None else None, tun, 0, workspace.data_ptr(), workspace.numel(),
+        _stream_handle(stream, dev)))
+    return (dist, link, ld) if link_dist else (dist, link)
+
+
+def query_autotune(link_T: torch.Tensor, grids: GridSet, points: torch.Tensor, c_offsets: torch.Tensor,
+                   m_offsets: torch.Tensor, *, candidates=None, reps: int = 5, workspace=None, stream=None):
+    """Times the batched query under each candidate tiling
+    (lsdf_query_autotune) and returns (best lsdf_query_tuning, its ms,
+    (dist, link) of the problem)."""
+    lib = load_library()
+    C, L, M, dev = _query_shapes(link_T, grids, points)
+    K = _offsets(c_offsets, m_offsets, dev)
+    dist, link, _ = _query_outputs(None, C, L, dev, False)
+    if workspace is None:
+        workspace = query_workspace(C, L, M, dev, K=K)
+    arr, n = None, 0
+    if candidates is not None:
+        cands = [c if isinstance(c, lsdf_query_tuning) else make_tuning(*c) for c in candidates]
+        n = len(cands)
+        arr = (lsdf_query_tuning * n)(*cands)
+    best = lsdf_query_tuning()
+    ms = ct.c_float(0.0)
+    _check(lib.lsdf_query_autotune(
+        K, c_offsets.data_ptr(), m_offsets.data_ptr(), link_T.data_ptr(), C, L, grids.desc, grids.buf.data_ptr(),
+        points.data_ptr() if M > 0 else None, M, dist.data_ptr(), link.data_ptr(), arr, n, reps,
+        workspace.data_ptr(), workspace.numel(), _stream_handle(stream, dev), ct.byref(best), ct.byref(ms)))
+    return best, float(ms.value), (dist, link)
 
 
 def build_link_sdf(verts: torch.Tensor, tris: torch.Tensor, comp_first, grids: GridSet, index: int, stream=None):

@@ -4,7 +4,8 @@ parameters and meshes, waypoints, obstacle clouds, grid boxes); none of the
 distance method's arithmetic is here.
 
 Base seed 230912543; sub-streams: DH and meshes S+0, waypoints S+2+100*traj,
-scene S+3+100*traj, network samples S+4+link, network initial weights S+5.
+scene S+3+100*traj, network samples S+4+link, network initial weights S+5,
+trajectory sizes of a batched workload S+6.
 """
 from __future__ import annotations
 
@@ -84,7 +85,84 @@ def make_workload(name: str = "tiny", C: int | None = None, M: int | None = None
     return Workload(name, robot, q, pts, grid_lo, grid_hi, grid_n, info)
 
 
-__all__ = ["BASE_SEED", "GRID_PAD", "Mesh", "Robot", "Workload", "WORKLOADS", "box_mesh",
+@dataclass
+class BatchedWorkload:
+    """K trajectories of one robot, each a path and its own obstacle cloud,
+    concatenated: trajectory k owns q[c_off[k]:c_off[k+1]] and
+    points[m_off[k]:m_off[k+1]]."""
+    name: str
+    robot: Robot
+    q: np.ndarray            # float64 [sum C_k][dof]
+    points: np.ndarray       # float64 [sum M_k][3] (values exactly representable in float32)
+    c_off: np.ndarray        # int64 [K+1]
+    m_off: np.ndarray        # int64 [K+1]
+    grid_lo: np.ndarray
+    grid_hi: np.ndarray
+    grid_n: np.ndarray
+    info: dict
+
+    @property
+    def K(self) -> int:
+        return int(self.c_off.size - 1)
+
+    @property
+    def C(self) -> int:
+        return int(self.q.shape[0])
+
+    @property
+    def M(self) -> int:
+        return int(self.points.shape[0])
+
+    @property
+    def L(self) -> int:
+        return self.robot.n_links
+
+    def pairs(self) -> int:
+        """Point-link queries of the whole batch: sum_k C_k M_k L."""
+        return int((np.diff(self.c_off) * np.diff(self.m_off)).sum()) * self.L
+
+
+def make_batched(K: int = 64, C_range=(50, 1000), M_range=(5000, 200000), n: int = 64, voxel: float = 0.02,
+                 kind: str = "scene", seed: int = BASE_SEED) -> BatchedWorkload:
+    """K re-planned trajectories with their own clouds: C_k and M_k drawn
+    uniformly from the inclusive ranges (stream S+6), waypoints of trajectory
+    k from stream S+2+100k and its scene from S+3+100k.  kind "cube" uses
+    uniform points in the 2 m cube instead of the voxelised person and
+    table.  Ranges may include 0 (empty trajectories)."""
+    robot = make_robot(seed + 0)
+    rng = np.random.default_rng(seed + 6)
+    Cs = rng.integers(C_range[0], C_range[1] + 1, size=K)
+    Ms = rng.integers(M_range[0], M_range[1] + 1, size=K)
+    qs, ps = [], []
+    occupied = []
+    for k in range(K):
+        C, M = int(Cs[k]), int(Ms[k])
+        qs.append(make_waypoints(robot.qmin, robot.qmax, C, seed + 2 + 100 * k) if C > 0
+                  else np.zeros((0, robot.dof)))
+        if M == 0:
+            ps.append(np.zeros((0, 3)))
+        elif kind == "cube":
+            ps.append(uniform_cube(M, seed + 3 + 100 * k))
+        else:
+            pts, sinfo = human_table(M, voxel, seed + 3 + 100 * k, return_info=True)
+            occupied.append(sinfo["occupied_voxels"])
+            ps.append(pts)
+    q = np.concatenate(qs).reshape(-1, robot.dof)
+    pts = np.concatenate(ps).reshape(-1, 3).astype(np.float32).astype(np.float64)
+    c_off = np.concatenate([[0], np.cumsum(Cs)]).astype(np.int64)
+    m_off = np.concatenate([[0], np.cumsum(Ms)]).astype(np.int64)
+    los, his = zip(*(grid_box(mesh) for mesh in robot.links))
+    grid_lo = np.array(los, dtype=np.float32)
+    grid_hi = np.array(his, dtype=np.float32)
+    grid_n = np.full((robot.n_links, 3), n, dtype=np.int32)
+    info = {"workload": "batched", "K": K, "C_range": list(C_range), "M_range": list(M_range), "n": n,
+            "voxel_m": voxel if kind == "scene" else None, "sum_C": int(Cs.sum()), "sum_M": int(Ms.sum())}
+    if occupied:
+        info["occupied_voxels_mean"] = float(np.mean(occupied))
+    return BatchedWorkload("batched", robot, q, pts, c_off, m_off, grid_lo, grid_hi, grid_n, info)
+
+
+__all__ = ["BatchedWorkload", "make_batched", "BASE_SEED", "GRID_PAD", "Mesh", "Robot", "Workload", "WORKLOADS", "box_mesh",
            "capsule_mesh", "grid_box", "human_table", "make_robot", "make_waypoints",
            "make_workload", "sphere_mesh", "uniform_cube", "union_mesh", "MLP_FAR", "mlp_domain", "mlp_init",
            "mlp_samples", "surface_points"]

@@ -159,3 +159,61 @@ def test_mlp_argument_errors(lib):
     # labels: empty mesh, NULL descriptor
     assert lib.lsdf_sdf_labels(FAKE, 0, FAKE, 12, None, 0, g, FAKE, FAKE, 10, FAKE, None) == B.LSDF_E_SHAPE
     assert lib.lsdf_sdf_labels(FAKE, 8, FAKE, 12, None, 0, None, FAKE, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG
+
+
+def test_batched_query_argument_errors(lib):
+    from paper_2309_12543_amd import lsdf as B
+    g = grid_array(2)
+
+    def q(K=3, c_off=FAKE, m_off=FAKE, C=4, M=10, tuning=None, ws=0x100000, ws_bytes=1 << 20, flags=0):
+        return lib.lsdf_query_min_distance_batched(K, c_off, m_off, FAKE, C, 2, g, FAKE, FAKE, M, FAKE, FAKE, None,
+                                                   tuning, flags, ct.c_void_p(ws) if ws else None, ws_bytes, None)
+    assert q(K=0) == B.LSDF_E_SHAPE
+    assert q(K=65537) == B.LSDF_E_SHAPE
+    assert q(c_off=None) == B.LSDF_E_INVALID_ARG
+    assert q(m_off=None) == B.LSDF_E_INVALID_ARG
+    assert q(flags=4) == B.LSDF_E_UNSUPPORTED
+    assert q(M=(1 << 34) + 1) == B.LSDF_E_SHAPE
+    for bad in [(12, 0), (4, 0), (8200, 0), (0, 17), (0, -1)]:
+        assert q(tuning=ct.byref(B.make_tuning(*bad))) == B.LSDF_E_INVALID_ARG, bad
+    assert b"chunk_points" in lib.lsdf_last_error() or b"blocks_per_cu" in lib.lsdf_last_error()
+    # the plan of K trajectories lives in the workspace: K = 3 fits where K = 60000 does not
+    n = ct.c_size_t(0)
+    assert lib.lsdf_query_batched_workspace_size(3, 4, 2, 10, ct.byref(n)) == 0
+    assert q(K=60000, ws_bytes=n.value) == B.LSDF_E_SHAPE
+    assert q(ws=0x100008) == B.LSDF_E_INVALID_ARG
+    # C = 0 is a successful no-op
+    assert q(C=0) == B.LSDF_OK
+
+
+def test_batched_workspace_size(lib):
+    n1, nk = ct.c_size_t(0), ct.c_size_t(0)
+    assert lib.lsdf_query_workspace_size(500, 7, 20000, ct.byref(n1)) == 0
+    assert lib.lsdf_query_batched_workspace_size(1, 500, 7, 20000, ct.byref(nk)) == 0
+    assert n1.value == nk.value
+    assert lib.lsdf_query_batched_workspace_size(64, 500, 7, 20000, ct.byref(nk)) == 0
+    assert nk.value > n1.value and nk.value % 256 == 0
+    assert lib.lsdf_query_batched_workspace_size(0, 500, 7, 20000, ct.byref(nk)) != 0
+
+
+def test_autotune_argument_errors(lib):
+    from paper_2309_12543_amd import lsdf as B
+    g = grid_array(2)
+    best = B.lsdf_query_tuning()
+
+    def a(cands=None, n=0, reps=3, best_p=True, c_off=FAKE):
+        return lib.lsdf_query_autotune(2, c_off, FAKE, FAKE, 4, 2, g, FAKE, FAKE, 10, FAKE, FAKE, cands, n, reps,
+                                       FAKE, 1 << 20, None, ct.byref(best) if best_p else None, None)
+    assert a(best_p=False) == B.LSDF_E_INVALID_ARG
+    assert a(reps=0) == B.LSDF_E_INVALID_ARG
+    assert a(c_off=None) == B.LSDF_E_INVALID_ARG
+    arr = (B.lsdf_query_tuning * 2)(B.make_tuning(32, 8), B.make_tuning(9, 8))
+    assert a(cands=arr, n=2) == B.LSDF_E_INVALID_ARG          # 9 is not a multiple of 8
+    assert a(cands=arr, n=0) == B.LSDF_E_INVALID_ARG
+
+
+def test_set_kernel_events_arguments(lib):
+    from paper_2309_12543_amd import lsdf as B
+    assert lib.lsdf_set_kernel_events(FAKE, None) == B.LSDF_E_INVALID_ARG
+    assert lib.lsdf_set_kernel_events(None, FAKE) == B.LSDF_E_INVALID_ARG
+    assert lib.lsdf_set_kernel_events(None, None) == B.LSDF_OK

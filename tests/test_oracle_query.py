@@ -268,3 +268,37 @@ def test_half_storage_error_bound(orc, tiny, tiny_grids, dt, u):
     bound = np.array([u * np.abs(g).max() for g in g32])[None, :].repeat(a.shape[0], 0)
     assert np.all(np.abs(a - b)[fin] <= bound[fin] * (1 + 1e-3) + 4e-7)
     assert np.abs(a - b)[fin].max() > 0       # the rounding is visible
+
+
+def test_batched_is_per_configuration_min_over_covering_trajectories(orc, tiny, tiny_grids):
+    """The batched oracle against the definition taken configuration by
+    configuration: each configuration's per-link minima are one plain query
+    over the union of the points of every trajectory whose clamped range
+    covers it (+inf when none does).  Offsets include an unsorted pair, a
+    negative entry, entries past C and M, and overlapping ranges."""
+    g32 = [g.astype(np.float32) for g in tiny_grids]
+    T = orc.fk(tiny.robot.dh, tiny.q[:30], tiny.robot.base_T).astype(np.float32)
+    pts = tiny.points[:900].astype(np.float32)
+    C, M = T.shape[0], pts.shape[0]
+    c_off = [-3, 8, 5, 14, 40, 22, 27]
+    m_off = [0, 300, 1200, 100, 650, -1, 899]
+    got = orc.query_batched(orc.query_f32, T, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, c_off, m_off)
+    ranges = []
+    for k in range(len(c_off) - 1):
+        c0 = min(max(c_off[k], 0), C)
+        c1 = min(max(c_off[k + 1], c0), C)
+        m0 = min(max(m_off[k], 0), M)
+        m1 = min(max(m_off[k + 1], m0), M)
+        ranges.append((c0, c1, m0, m1))
+    assert ranges[1] == (8, 8, 300, 900) and ranges[4] == (30, 30, 650, 650)
+    covered = 0
+    for c in range(C):
+        idx = [np.arange(m0, m1) for (c0, c1, m0, m1) in ranges if c0 <= c < c1]
+        idx = np.unique(np.concatenate(idx)) if idx else np.zeros(0, int)
+        if idx.size == 0:
+            assert np.all(np.isinf(got[c]))
+            continue
+        covered += 1
+        want = orc.query_f32(T[c:c + 1], tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts[idx])[0]
+        assert np.array_equal(got[c].astype(np.float32).view(np.uint32), want.view(np.uint32)), c
+    assert covered >= 20 and np.isfinite(got).any()
