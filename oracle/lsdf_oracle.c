@@ -640,3 +640,106 @@ ORC_EXPORT void orc_judge_min(const double* T, int32_t C, int32_t L, const doubl
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* The paper's own pipeline (Sec. III-A, Eq. 1-4): Robot SDFs.               */
+/*                                                                           */
+/* The environment is a voxel grid: voxel v (per axis 0 <= v_a < N_a) spans  */
+/* [lo_a + v_a r, lo_a + (v_a + 1) r) and has its centre at                  */
+/* lo_a + (v_a + 1/2) r (r = voxel edge; lo = -e_e, the paper's environment  */
+/* extent).  Link i's transformed SDF is a block of (2 m_i)^3 voxels         */
+/* (m_i r = e_r, the paper's Link SDF extent) aligned to the environment.    */
+/* Alignment of link i at configuration c (Eq. 1-3, read as                 */
+/*   T_O = t - lo,  k = round(T_O / r) - m,  dt = T_O - (k r + m r)):        */
+/* the block covers environment voxels k .. k + 2m - 1 on each axis, its     */
+/* centre sits at the grid line nearest to the link origin and dt, the      */
+/* origin's offset from that centre, lies in [-r/2, r/2].                    */
+/* Euclidean transformation (Eq. 4): block voxel j has centre               */
+/* P_j = (j + 1/2 - m) r relative to the block centre, and its link-local    */
+/* coordinate is G = R^T (P_j - dt); the transformed SDF value there is the  */
+/* link grid's interpolant g_i(G) (+inf outside the grid box).              */
+/* Robot SDF of configuration c: per environment voxel, the minimum over    */
+/* links of the aligned transformed values (+inf where no block reaches).   */
+/* Runtime: obstacle points are voxelised, v_a = floor((x_a - lo_a) / r)    */
+/* (in double), points outside the environment are dropped, and the         */
+/* distance of c is the minimum of its Robot SDF over the occupied voxels.  */
+/* ------------------------------------------------------------------------ */
+
+/* Eq. 1-3 for one link position t: block corner k and residual shift dt. */
+ORC_EXPORT void orc_align(const double* t, const double* env_lo, double r, int32_t m, int64_t* k, double* dt) {
+    for (int a = 0; a < 3; ++a) {
+        const double t_o = t[a] - env_lo[a];                 /* Eq. 1: T_O = T - (-e_e) */
+        k[a] = (int64_t)nearbyint(t_o / r) - m;               /* Eq. 2 */
+        dt[a] = t_o - ((double)k[a] * r + (double)m * r);     /* Eq. 3 */
+    }
+}
+
+/* Robot SDFs in double, [C][N_z][N_y][N_x] (x fastest). */
+ORC_EXPORT void orc_robot_sdf_f64(const double* T, int32_t C, int32_t L, const double* lo, const double* hi,
+                                  const int32_t* n, const double* grids, const int64_t* offs, const int32_t* m,
+                                  const double* env_lo, double r, const int32_t* env_n, double* out) {
+    const int64_t V = (int64_t)env_n[0] * env_n[1] * env_n[2];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t c = 0; c < C; ++c) {
+        double* rs = out + (int64_t)c * V;
+        for (int64_t v = 0; v < V; ++v) rs[v] = INFINITY;
+        for (int32_t i = 0; i < L; ++i) {
+            const double* Ti = T + ((int64_t)c * L + i) * 12;
+            const double t[3] = {Ti[3], Ti[7], Ti[11]};
+            int64_t k[3];
+            double dt[3];
+            orc_align(t, env_lo, r, m[i], k, dt);
+            double h[3];
+            for (int a = 0; a < 3; ++a) h[a] = (hi[3 * i + a] - lo[3 * i + a]) / (double)(n[3 * i + a] - 1);
+            const int32_t w = 2 * m[i];
+            for (int32_t jz = 0; jz < w; ++jz)
+                for (int32_t jy = 0; jy < w; ++jy)
+                    for (int32_t jx = 0; jx < w; ++jx) {
+                        const int64_t e[3] = {k[0] + jx, k[1] + jy, k[2] + jz};
+                        if (e[0] < 0 || e[1] < 0 || e[2] < 0 || e[0] >= env_n[0] || e[1] >= env_n[1] ||
+                            e[2] >= env_n[2])
+                            continue;                         /* outside the environment */
+                        const int32_t j[3] = {jx, jy, jz};
+                        double d[3], u[3];
+                        for (int a = 0; a < 3; ++a) d[a] = ((double)j[a] + 0.5 - (double)m[i]) * r - dt[a];
+                        int inside = 1;
+                        for (int a = 0; a < 3; ++a) {
+                            const double G = Ti[0 + a] * d[0] + Ti[4 + a] * d[1] + Ti[8 + a] * d[2];   /* Eq. 4 */
+                            u[a] = (G - lo[3 * i + a]) / h[a];
+                            if (!(u[a] >= 0.0 && u[a] <= (double)(n[3 * i + a] - 1))) inside = 0;
+                        }
+                        if (!inside) continue;
+                        const double val = orc_trilinear_f64(grids + offs[i], n + 3 * i, u);
+                        const int64_t idx = (e[2] * env_n[1] + e[1]) * (int64_t)env_n[0] + e[0];
+                        if (val < rs[idx]) rs[idx] = val;
+                    }
+        }
+    }
+}
+
+/* Environment voxel of a point (double arithmetic), or -1 outside. */
+ORC_EXPORT int64_t orc_voxel_index(const double* x, const double* env_lo, double r, const int32_t* env_n) {
+    int64_t v[3];
+    for (int a = 0; a < 3; ++a) {
+        const double q = floor((x[a] - env_lo[a]) / r);
+        if (!(q >= 0.0 && q < (double)env_n[a])) return -1;
+        v[a] = (int64_t)q;
+    }
+    return (v[2] * env_n[1] + v[1]) * (int64_t)env_n[0] + v[0];
+}
+
+/* Runtime of the Robot-SDF pipeline: per configuration, the minimum of its
+ * Robot SDF over the voxels occupied by the points (+inf if none). */
+ORC_EXPORT void orc_robot_sdf_query(const double* rs, int32_t C, const double* env_lo, double r,
+                                    const int32_t* env_n, const double* P, int64_t M, double* out) {
+    const int64_t V = (int64_t)env_n[0] * env_n[1] * env_n[2];
+    for (int32_t c = 0; c < C; ++c) out[c] = INFINITY;
+    for (int64_t j = 0; j < M; ++j) {
+        const int64_t v = orc_voxel_index(P + 3 * j, env_lo, r, env_n);
+        if (v < 0) continue;
+        for (int32_t c = 0; c < C; ++c) {
+            const double x = rs[(int64_t)c * V + v];
+            if (x < out[c]) out[c] = x;
+        }
+    }
+}

@@ -79,6 +79,15 @@ def load():
     lib.orc_judge_min.restype = None
     lib.orc_judge_min.argtypes = [_dp, ct.c_int32, ct.c_int32, _dp, _dp, _ip, _dp, _lp, ct.POINTER(_dp),
                                   ct.POINTER(_ip), ct.POINTER(_ip), _ip, _dp, _dp, _dp, _dp, _dp, ct.c_int64, _dp]
+    lib.orc_align.restype = None
+    lib.orc_align.argtypes = [_dp, _dp, ct.c_double, ct.c_int32, _lp, _dp]
+    lib.orc_robot_sdf_f64.restype = None
+    lib.orc_robot_sdf_f64.argtypes = [_dp, ct.c_int32, ct.c_int32, _dp, _dp, _ip, _dp, _lp, _ip, _dp, ct.c_double,
+                                      _ip, _dp]
+    lib.orc_voxel_index.restype = ct.c_int64
+    lib.orc_voxel_index.argtypes = [_dp, _dp, ct.c_double, _ip]
+    lib.orc_robot_sdf_query.restype = None
+    lib.orc_robot_sdf_query.argtypes = [_dp, ct.c_int32, _dp, ct.c_double, _ip, _dp, ct.c_int64, _dp]
     _lib = lib
     return lib
 
@@ -218,6 +227,65 @@ def query_batched(query, T, lo, hi, n, grids, points, c_off, m_off) -> np.ndarra
     return out
 
 
+# ---------------------------------------------------------------------------
+# the paper's Robot-SDF pipeline (Sec. III-A, Eq. 1-4)
+# ---------------------------------------------------------------------------
+
+def align(t, env_lo, r, m):
+    """Eq. 1-3: block corner k (int64 [3]) and residual shift dt ([3])."""
+    lib = load()
+    t, lo = _c(t, np.float64), _c(env_lo, np.float64)
+    k = np.zeros(3, np.int64)
+    dt = np.zeros(3, np.float64)
+    lib.orc_align(_ptr(t, _dp), _ptr(lo, _dp), float(r), int(m), _ptr(k, _lp), _ptr(dt, _dp))
+    return k, dt
+
+
+def robot_sdf_f64(T, lo, hi, n, grids, m, env_lo, r, env_n) -> np.ndarray:
+    """Robot SDFs [C][N_z][N_y][N_x] in double (Eq. 1-4, per-voxel minimum
+    over links); m [L] = block half-widths in voxels."""
+    lib = load()
+    T = _c(T, np.float64)
+    C, L = T.shape[0], T.shape[1]
+    lo, hi, n = _c(lo, np.float64), _c(hi, np.float64), _c(n, np.int32)
+    buf, offs = _pack(grids, np.float64)
+    m = _c(m, np.int32)
+    elo, en = _c(env_lo, np.float64), _c(env_n, np.int32)
+    out = np.empty((C, int(en[2]), int(en[1]), int(en[0])), dtype=np.float64)
+    lib.orc_robot_sdf_f64(_ptr(T, _dp), C, L, _ptr(lo, _dp), _ptr(hi, _dp), _ptr(n, _ip), _ptr(buf, _dp),
+                          _ptr(offs, _lp), _ptr(m, _ip), _ptr(elo, _dp), float(r), _ptr(en, _ip), _ptr(out, _dp))
+    return out
+
+
+def voxel_index(x, env_lo, r, env_n) -> int:
+    lib = load()
+    x, lo, en = _c(x, np.float64), _c(env_lo, np.float64), _c(env_n, np.int32)
+    return int(lib.orc_voxel_index(_ptr(x, _dp), _ptr(lo, _dp), float(r), _ptr(en, _ip)))
+
+
+def robot_sdf_query(rs, env_lo, r, env_n, points) -> np.ndarray:
+    """Runtime of the pipeline: per configuration, the minimum of its Robot
+    SDF over the voxels the points occupy."""
+    lib = load()
+    rs = _c(rs, np.float64)
+    C = rs.shape[0]
+    lo, en = _c(env_lo, np.float64), _c(env_n, np.int32)
+    P = _c(points, np.float64).reshape(-1, 3)
+    out = np.empty(C, dtype=np.float64)
+    lib.orc_robot_sdf_query(_ptr(rs, _dp), C, _ptr(lo, _dp), float(r), _ptr(en, _ip), _ptr(P, _dp), P.shape[0],
+                            _ptr(out, _dp))
+    return out
+
+
+def voxel_centres(env_lo, r, env_n, flat_index) -> np.ndarray:
+    """float32 centres lo + (v + 1/2) r of the given flat voxel indices
+    (computed in double, rounded once)."""
+    en = np.asarray(env_n, dtype=np.int64)
+    idx = np.asarray(flat_index, dtype=np.int64)
+    v = np.stack([idx % en[0], (idx // en[0]) % en[1], idx // (en[0] * en[1])], axis=-1).astype(np.float64)
+    return (np.asarray(env_lo, np.float64) + (v + 0.5) * float(r)).astype(np.float32)
+
+
 def exact_min(T, meshes, points) -> np.ndarray:
     """Grid-free per-link minima [C][L]: exact mesh SDF at every point."""
     lib = load()
@@ -351,6 +419,6 @@ def mlp_unpack(params):
     return out
 
 
-__all__ = ["build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
+__all__ = ["align", "robot_sdf_f64", "robot_sdf_query", "voxel_centres", "voxel_index", "build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
            "query_batched", "query_f32", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids",
            "MLP_HIDDEN", "adam_step", "judge_min", "mlp_forward", "mlp_loss_grad", "mlp_nparam", "mlp_unpack"]
