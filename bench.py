@@ -1,9 +1,11 @@
 """Benchmark: ms per 500-waypoint batch and G point-link queries/s.
 
-One step = forward kinematics of every waypoint (lsdf_fk_batch) plus the
-clearance query (lsdf_query_min_distance) over 500 waypoints x 20,000
-obstacle points x 7 links with 64^3 FP32 link grids, inputs resident in HBM.
-Prints one JSON line.  One GPU only.
+One step = forward kinematics of every waypoint plus the clearance query
+over 500 waypoints x 20,000 obstacle points x 7 links with 64^3 FP32 link
+grids, inputs resident in HBM, as one lsdf_query_from_joints call (the
+kinematics run in the query's first kernel); the same step as two calls
+(lsdf_fk_batch, lsdf_query_min_distance) and as a graph replay is reported
+beside it.  Prints one JSON line.  One GPU only.
 """
 from __future__ import annotations
 
@@ -268,10 +270,10 @@ def batched_variant(dev, steps: int, warmup: int):
         it = iter(range(10 ** 9))
 
         def one(timed):
-            lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T, out=T)
             if timed:
                 lsdf.set_kernel_events(*kev[next(it)])
-            lsdf.query_min_distance_batched(T, gs, pts, co, mo, tuning=tun, workspace=ws, out=out)
+            lsdf.query_from_joints(w.robot.dh, q, gs, pts, base_T=w.robot.base_T, c_offsets=co, m_offsets=mo,
+                                   link_T=T, tuning=tun, workspace=ws, out=out)
 
         for _ in range(warmup):
             one(False)
@@ -361,12 +363,13 @@ def main():
     call_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.steps)]
     kern_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
+               for _ in range(2 * args.steps)]
     for a, b in call_ev + kern_ev:      # create the events before handing them to the library
         a.record()
         b.record()
 
-    def step(k=None):
+    def step_separate(k=None):
+        # lsdf_fk_batch, then lsdf_query_min_distance
         lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T, out=T)
         if k is not None:
             call_ev[k][0].record()
@@ -375,18 +378,31 @@ def main():
         if k is not None:
             call_ev[k][1].record()
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(k)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
+    def step_fused(k=None):
+        # lsdf_query_from_joints: the kinematics inside the query's first kernel
+        if k is not None:
+            lsdf.set_kernel_events(*kern_ev[args.steps + k])
+        lsdf.query_from_joints(w.robot.dh, q, gs, pts, base_T=w.robot.base_T, link_T=T, workspace=ws,
+                               out=(dist, link, None))
+
+    def run(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(k)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    log(f"timing {args.steps} steps (separate calls, then the fused call)")
+    sep_ms = run(step_separate)
+    d_sep, l_sep = dist.clone(), link.clone()
+    ms_per_step = run(step_fused)
+    fused_same = bool(torch.equal(dist.view(torch.int32), d_sep.view(torch.int32)) and torch.equal(link, l_sep))
     call_ms = float(np.mean([a.elapsed_time(b) for a, b in call_ev]))
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in kern_ev]))
+    kernel_ms_sep = float(np.mean([a.elapsed_time(b) for a, b in kern_ev[:args.steps]]))
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in kern_ev[args.steps:]]))
     pairs = w.C * w.M * w.L
     value = pairs / (ms_per_step / 1e3) / 1e9
 
@@ -396,7 +412,7 @@ def main():
     sg.load(q, pts, torch.tensor([0, w.C], dtype=torch.int32, device=dev),
             torch.tensor([0, w.M], dtype=torch.int64, device=dev))
     graph_ms = time_calls(sg.replay, args.steps, args.warmup)
-    same = bool(torch.equal(sg.dist.view(torch.int32), dist.view(torch.int32)) and torch.equal(sg.link, link))
+    same = bool(torch.equal(sg.dist.view(torch.int32), d_sep.view(torch.int32)) and torch.equal(sg.link, l_sep))
     del sg
 
     Tn = T.cpu().numpy()
@@ -420,8 +436,12 @@ def main():
                                f"{int(w.grid_n[0, 0])}^3 FP32 link grids",
                    "waypoints": w.C, "points": w.M, "links": w.L, "grid_nodes": int(w.grid_n[0, 0]),
                    "parallelism": "single GPU"},
+        "step": "lsdf_query_from_joints: kinematics in the query's first kernel, then the query and finalize kernels",
+        "separate_calls_ms_per_step": round(sep_ms, 5),
+        "separate_calls_equal_fused": fused_same,
         "query_call_ms": round(call_ms, 5),
         "query_kernel_ms": round(kernel_ms, 5),
+        "query_kernel_ms_separate_calls": round(kernel_ms_sep, 5),
         "graph_replay_ms_per_step": round(graph_ms, 5),
         "graph_equals_eager": same,
         "inbox_pair_fraction": round(inbox / pairs, 5),

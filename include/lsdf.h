@@ -129,10 +129,10 @@ int lsdf_fk_batch(const lsdf_dh* dh, int32_t dof, const float* base_T,
  *   out_link_dist device float [C][L] per-link minima, or NULL
  *   flags         must be 0
  *   workspace     device scratch of at least lsdf_query_workspace_size()
- *                 bytes, 256-byte aligned, ZERO-FILLED before its first use
- *                 and not written by the caller afterwards: every call
- *                 returns it to all-zero when it completes.  Calls that share
- *                 a workspace must not overlap in time (same stream is fine).
+ *                 bytes, 256-byte aligned.  Its contents on entry are
+ *                 ignored (the call's first kernel initialises what it
+ *                 uses) and are unspecified afterwards.  Calls that share a
+ *                 workspace must not overlap in time (same stream is fine).
  * M <= LSDF_MAX_POINTS.  -0 is returned as +0.  M = 0 gives (+inf, -1) everywhere; C = 0 enqueues
  * nothing.  The arithmetic is FP32 in a fixed operation order (per link and
  * configuration the world-to-grid map is formed once as one affine matrix,
@@ -167,11 +167,18 @@ int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L,
  * offset, pose and point contents (same C, M, K capacities).  Offsets out
  * of order or out of range are clamped into [0, C] and [0, M] on the device:
  * the results are then meaningless, but no access leaves the buffers. */
+#define LSDF_SCHED_DEFAULT     0   /* the library's choice (XCD slices) */
+#define LSDF_SCHED_XCD_SLICES  1   /* each XCD takes a contiguous slice of
+                                      the work (its L2 sees few link grids) */
+#define LSDF_SCHED_INTERLEAVED 2   /* every wave of the grid takes every W-th
+                                      chunk (balances uneven work) */
 typedef struct {
     int32_t chunk_points;   /* points per work chunk: a multiple of 8 in
                                [8, 8192]; 0 = default (32) */
     int32_t blocks_per_cu;  /* workgroups of the persistent grid per compute
                                unit, in [1, 16]; 0 = default (8) */
+    int32_t schedule;       /* LSDF_SCHED_* */
+    int32_t reserved;       /* must be 0 */
 } lsdf_query_tuning;
 
 int lsdf_query_batched_workspace_size(int32_t K, int32_t C, int32_t L, int64_t M, size_t* bytes);
@@ -184,12 +191,34 @@ int lsdf_query_min_distance_batched(int32_t K, const int32_t* traj_c_offset, con
                                     const lsdf_query_tuning* tuning, uint32_t flags,
                                     void* workspace, size_t ws_bytes, void* stream);
 
+/* Kinematics and clearance in one call (Sec. III-A: forward kinematics of
+ * every configuration, then the distance of each to the obstacles).  The
+ * poses are computed in the query's first kernel, with the arithmetic of
+ * lsdf_fk_batch (the same bits), which saves a launch per step.
+ *   dh, dof, base_T   as lsdf_fk_batch; the grids are the dof + 1 frames'
+ *   q                 device float [C][dof] joint angles
+ *   K, traj_c_offset, traj_m_offset
+ *                     as lsdf_query_min_distance_batched, or K = 1 with both
+ *                     offset arrays NULL (one trajectory of all C and M)
+ *   link_T            device float [C][dof+1][3][4] receiving the poses, or
+ *                     NULL when only the clearances are wanted
+ *   other arguments as lsdf_query_min_distance_batched (workspace sized by
+ *   lsdf_query_batched_workspace_size(K, C, dof + 1, M)).
+ * Results are bit-identical to lsdf_fk_batch followed by the query. */
+int lsdf_query_from_joints(const lsdf_dh* dh, int32_t dof, const float* base_T, const float* q,
+                           int32_t K, const int32_t* traj_c_offset, const int64_t* traj_m_offset,
+                           int32_t C, const lsdf_grid* grids, const void* grid_buf,
+                           const float* points, int64_t M, float* link_T,
+                           float* out_dist, int32_t* out_link, float* out_link_dist,
+                           const lsdf_query_tuning* tuning, uint32_t flags,
+                           void* workspace, size_t ws_bytes, void* stream);
+
 /* Picks the fastest tiling for one batched problem by timing it.
  * Runs lsdf_query_min_distance_batched once untimed and `reps` times timed
  * (HIP events on `stream`) per candidate, and returns the candidate with
  * the lowest mean time in *best (and that time in ms in *best_ms, which may
- * be NULL).  candidates = NULL uses a built-in list (chunk_points 8 to 1024
- * at 8 workgroups per CU, fewer at 2 and 4).  1 <= reps <= 1000.
+ * be NULL).  candidates = NULL uses a built-in list (chunk_points 32 to
+ * 4096, 4 and 8 workgroups per CU, both schedules).  1 <= reps <= 1000.
  * It SYNCHRONISES the stream (not capturable); out_dist / out_link hold the
  * problem's results when it returns LSDF_OK. */
 int lsdf_query_autotune(int32_t K, const int32_t* traj_c_offset, const int64_t* traj_m_offset,
@@ -199,6 +228,54 @@ int lsdf_query_autotune(int32_t K, const int32_t* traj_c_offset, const int64_t* 
                         const lsdf_query_tuning* candidates, int32_t n_candidates, int32_t reps,
                         void* workspace, size_t ws_bytes, void* stream,
                         lsdf_query_tuning* best, float* best_ms);
+
+/* ---- the paper's Robot-SDF pipeline (comparator) ---------------------------
+ * Sec. III-A, Eq. 1-4: per configuration, a Robot SDF over the voxels of
+ * the environment (per voxel, the minimum over links of the link's SDF
+ * transformed by its pose and aligned to the voxel grid), then at run time
+ * the distance of each configuration is the minimum of its Robot SDF over
+ * the voxels the obstacle points occupy.  The per-point query above is the
+ * library's method; these calls reproduce the paper's for comparison (its
+ * trade-off: C x V voxels of memory and a heavy preparation against a
+ * gather-only runtime).
+ * The environment: voxel v (0 <= v_a < n_a) spans [lo_a + v_a r,
+ * lo_a + (v_a + 1) r) (lo = -e_e, the paper's extent; r = voxel, its
+ * resolution).  Link i's block at configuration c covers voxels k .. k + 2m
+ * - 1 per axis with k = round((t - lo) / r) - m (Eq. 1-2 in double, t the
+ * link origin) and m = ceil(farthest grid-box corner from the link origin
+ * / r) + 2.  A voxel's value is the minimum, over the links whose block
+ * covers it, of the link grid's interpolant at the voxel centre
+ * lo + (v + 1/2) r (double, rounded once to float) moved into the link frame
+ * (Eq. 4), with the plain query's FP32 arithmetic (so each value equals the
+ * plain query at that point), +inf where none applies. */
+typedef struct {
+    float lo[3];      /* environment corner, metres */
+    float voxel;      /* voxel edge r > 0, metres */
+    int32_t n[3];     /* voxels per axis, 1..4096, at most 2^32 in all */
+} lsdf_env;
+
+/* Bytes of the Robot SDFs of C configurations: C * n_x * n_y * n_z * 4. */
+int lsdf_robot_sdf_size(int32_t C, const lsdf_env* env, size_t* bytes);
+int lsdf_robot_sdf_build_workspace_size(int32_t C, int32_t L, size_t* bytes);
+
+/* Preparation: fills robot_sdf, device float [C][n_z][n_y][n_x] (x
+ * fastest), from link poses link_T [C][L][3][4] and the link grids.  Every
+ * voxel is written.  workspace: device, 256-byte aligned, at least
+ * lsdf_robot_sdf_build_workspace_size(C, L) bytes; contents ignored. */
+int lsdf_robot_sdf_build(const float* link_T, int32_t C, int32_t L, const lsdf_grid* grids,
+                         const void* grid_buf, const lsdf_env* env, float* robot_sdf,
+                         void* workspace, size_t ws_bytes, void* stream);
+
+int lsdf_robot_sdf_query_workspace_size(const lsdf_env* env, int64_t M, size_t* bytes);
+
+/* Runtime: out_dist[c] = minimum of robot_sdf[c] over the distinct voxels
+ * holding at least one of the points (voxel of x: floor((x - lo) / r),
+ * in double; points outside the environment are ignored); +inf when no
+ * point is inside.  workspace: device, 256-byte aligned, at least
+ * lsdf_robot_sdf_query_workspace_size(env, M) bytes; contents ignored. */
+int lsdf_robot_sdf_query(const float* robot_sdf, int32_t C, const lsdf_env* env,
+                         const float* points, int64_t M, float* out_dist,
+                         void* workspace, size_t ws_bytes, void* stream);
 
 /* ---- link SDF construction -------------------------------------------------
  * Sec. III-A: each link's signed distance field is computed once, offline,

@@ -354,9 +354,11 @@ ORC_EXPORT void orc_reduce_f64(const double* cl, int32_t C, int32_t L, double* d
 /* ------------------------------------------------------------------------ */
 static float lerpf_(float p, float q, float f) { return fmaf(f, q, fmaf(-f, p, p)); }
 
-ORC_EXPORT void orc_query_f32(const float* T, int32_t C, int32_t L, const float* lo,
-                              const float* hi, const int32_t* n, const float* grids,
-                              const int64_t* offs, const float* P, int64_t M, float* out) {
+/* each != NULL also stores every pair's value, [C][L][M] (+inf outside the
+ * box). */
+static void query_f32_impl(const float* T, int32_t C, int32_t L, const float* lo, const float* hi,
+                           const int32_t* n, const float* grids, const int64_t* offs, const float* P, int64_t M,
+                           float* out, float* each) {
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t c = 0; c < C; ++c) {
         for (int32_t i = 0; i < L; ++i) {
@@ -375,10 +377,12 @@ ORC_EXPORT void orc_query_f32(const float* T, int32_t C, int32_t L, const float*
                 w[a] = fmaf(-invh[a], rt, cen[a]);
             }
             float best = INFINITY;
+            float* ev = each ? each + ((int64_t)c * L + i) * M : NULL;
             for (int64_t j = 0; j < M; ++j) {
                 float x = P[3 * j], y = P[3 * j + 1], z = P[3 * j + 2];
                 float v[3];
                 int inside = 1;
+                if (ev) ev[j] = INFINITY;
                 for (int a = 0; a < 3; ++a) {
                     v[a] = fmaf(Mx[a][0], x, fmaf(Mx[a][1], y, fmaf(Mx[a][2], z, w[a])));
                     if (!(fabsf(v[a]) <= half[a])) inside = 0;
@@ -403,11 +407,26 @@ ORC_EXPORT void orc_query_f32(const float* T, int32_t C, int32_t L, const float*
                 float e0 = lerpf_(e00, e10, f[1]);
                 float e1 = lerpf_(e01, e11, f[1]);
                 float val = lerpf_(e0, e1, f[2]) + 0.0f;
+                if (ev) ev[j] = val;
                 if (val < best) best = val;
             }
             out[(int64_t)c * L + i] = best;
         }
     }
+}
+
+ORC_EXPORT void orc_query_f32(const float* T, int32_t C, int32_t L, const float* lo, const float* hi,
+                              const int32_t* n, const float* grids, const int64_t* offs, const float* P, int64_t M,
+                              float* out) {
+    query_f32_impl(T, C, L, lo, hi, n, grids, offs, P, M, out, NULL);
+}
+
+/* The single-precision twin's value of every (configuration, link, point)
+ * triple, [C][L][M]; out receives the per-link minima as orc_query_f32. */
+ORC_EXPORT void orc_query_f32_each(const float* T, int32_t C, int32_t L, const float* lo, const float* hi,
+                                   const int32_t* n, const float* grids, const int64_t* offs, const float* P,
+                                   int64_t M, float* out, float* each) {
+    query_f32_impl(T, C, L, lo, hi, n, grids, offs, P, M, out, each);
 }
 
 ORC_EXPORT void orc_reduce_f32(const float* cl, int32_t C, int32_t L, float* d, int32_t* link) {

@@ -79,6 +79,9 @@ def load():
     lib.orc_judge_min.restype = None
     lib.orc_judge_min.argtypes = [_dp, ct.c_int32, ct.c_int32, _dp, _dp, _ip, _dp, _lp, ct.POINTER(_dp),
                                   ct.POINTER(_ip), ct.POINTER(_ip), _ip, _dp, _dp, _dp, _dp, _dp, ct.c_int64, _dp]
+    lib.orc_query_f32_each.restype = None
+    lib.orc_query_f32_each.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _fp, _ip, _fp, _lp, _fp, ct.c_int64, _fp,
+                                       _fp]
     lib.orc_align.restype = None
     lib.orc_align.argtypes = [_dp, _dp, ct.c_double, ct.c_int32, _lp, _dp]
     lib.orc_robot_sdf_f64.restype = None
@@ -286,6 +289,22 @@ def voxel_centres(env_lo, r, env_n, flat_index) -> np.ndarray:
     return (np.asarray(env_lo, np.float64) + (v + 0.5) * float(r)).astype(np.float32)
 
 
+def query_f32_each(T, lo, hi, n, grids, points) -> np.ndarray:
+    """Every pair's value [C][L][M] in the single-precision twin's order
+    (+inf outside the box)."""
+    lib = load()
+    T = _c(T, np.float32)
+    C, L = T.shape[0], T.shape[1]
+    lo, hi, n = _c(lo, np.float32), _c(hi, np.float32), _c(n, np.int32)
+    buf, offs = _pack(grids, np.float32)
+    P = _c(points, np.float32).reshape(-1, 3)
+    out = np.empty((C, L), dtype=np.float32)
+    each = np.empty((C, L, P.shape[0]), dtype=np.float32)
+    lib.orc_query_f32_each(_ptr(T, _fp), C, L, _ptr(lo, _fp), _ptr(hi, _fp), _ptr(n, _ip), _ptr(buf, _fp),
+                           _ptr(offs, _lp), _ptr(P, _fp), P.shape[0], _ptr(out, _fp), _ptr(each, _fp))
+    return each
+
+
 def exact_min(T, meshes, points) -> np.ndarray:
     """Grid-free per-link minima [C][L]: exact mesh SDF at every point."""
     lib = load()
@@ -420,5 +439,5 @@ def mlp_unpack(params):
 
 
 __all__ = ["align", "robot_sdf_f64", "robot_sdf_query", "voxel_centres", "voxel_index", "build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
-           "query_batched", "query_f32", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids",
+           "query_batched", "query_f32", "query_f32_each", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids",
            "MLP_HIDDEN", "adam_step", "judge_min", "mlp_forward", "mlp_loss_grad", "mlp_nparam", "mlp_unpack"]

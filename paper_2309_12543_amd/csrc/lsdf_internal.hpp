@@ -33,7 +33,7 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // ---- order-preserving float <-> uint32 map ----------------------------------
 // ordered(a) < ordered(b) iff a < b for non-NaN floats (-0 below +0; callers
 // canonicalise -0 to +0 first).  Keys in the query workspace are stored
-// complemented (~ordered) so that an all-zero workspace means "empty" and the
+// complemented (~ordered) so that a zero key means "empty" and the
 // combining operation is an unsigned atomic max.
 __device__ inline uint32_t ordered_bits(float v) {
     uint32_t b = __float_as_uint(v);
@@ -64,9 +64,14 @@ int prepare_link_grid(const lsdf_grid& g, int index, LinkGrid* out);
 // (both NULL when none); taking them clears the setting.
 void take_kernel_events(hipEvent_t* before, hipEvent_t* after);
 
-// Turns the query workspace keys into out_dist / out_link / out_link_dist
-// and clears them (shared by the plain and the learned query).
-int launch_query_finalize(uint32_t* keys, float* out_dist, int32_t* out_link, float* out_link_dist, int32_t C,
-                          int32_t L, hipStream_t s, uint32_t* scratch = nullptr, int64_t scratch_words = 0);
+// Turns the query keys [C][L] into out_dist / out_link / out_link_dist
+// (shared by the plain and the learned query); keys == NULL gives +inf and
+// -1 everywhere.
+int launch_query_finalize(const uint32_t* keys, float* out_dist, int32_t* out_link, float* out_link_dist, int32_t C,
+                          int32_t L, hipStream_t s);
+
+// Zeroes n 32-bit words on stream s with a small kernel (no memset node,
+// so the call can sit in a captured graph).
+int launch_zero_words(uint32_t* w, int64_t n, hipStream_t s);
 
 }  // namespace lsdf

@@ -661,6 +661,7 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
         const int64_t per_link = std::max<int64_t>(
             1, std::min<int64_t>(((int64_t)cus * kBlocksPerCu + L - 1) / L, (a.tiles_per_link + kWaves - 1) / kWaves));
         const dim3 grid((unsigned)per_link, L);
+        if ((rc = launch_zero_words(a.keys, (int64_t)C * L, s)) != LSDF_OK) return rc;
         hipEvent_t ev0, ev1;
         take_kernel_events(&ev0, &ev1);
         if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return fail(LSDF_E_DEVICE, "query_mlp: event record failed");
@@ -675,7 +676,8 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
         if ((rc = check_launch("query_min_distance_mlp")) != LSDF_OK) return rc;
         if (ev1 && hipEventRecord(ev1, s) != hipSuccess) return fail(LSDF_E_DEVICE, "query_mlp: event record failed");
     }
-    return lsdf::launch_query_finalize(static_cast<uint32_t*>(workspace), out_dist, out_link, out_link_dist, C, L, s);
+    return lsdf::launch_query_finalize(a.tiles_per_link > 0 ? a.keys : nullptr, out_dist, out_link, out_link_dist, C, L,
+                                       s);
 }
 
 LSDF_API int lsdf_mlp_train_workspace_size(int32_t L, int32_t B, size_t* bytes) {

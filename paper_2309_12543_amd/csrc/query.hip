@@ -25,18 +25,22 @@
 //     the first kernel, so that no call reads anything back to the host and
 //     a whole step can be captured once in a graph and replayed with new
 //     ranges;
+//   * the first kernel also writes, per (link, configuration), the lane's
+//     map and culling thresholds into a field-major table (one coalesced
+//     load per field per chunk) and zeroes the keys;
 //   * the iteration space (trajectory, link, 64-configuration group, point)
-//     is cut into chunks of a tunable number of 8-point blocks; each XCD
-//     (blocks b = x mod 8) takes a contiguous slice of chunks, which keeps
-//     it on one or two links' grids in its L2, and deals its slice
-//     round-robin to its waves, which spreads dense regions of a cloud over
-//     many waves;
+//     is cut into chunks of a tunable number of 8-point blocks, dealt to the
+//     waves round-robin, either over the whole grid or inside per-XCD slices
+//     (blocks b = x mod 8 take a contiguous slice, which keeps an XCD on one
+//     or two links' grids in its L2); round-robin spreads dense regions of
+//     a cloud over many waves;
 //   * per-pair minima merge across waves with one unsigned atomic max on a
-//     complemented order-preserving key; a second small kernel turns the
-//     keys into the outputs and clears them, leaving the workspace zero (the
-//     kernel boundary orders it after every atomic, with no device fence).
+//     complemented order-preserving key; a last small kernel turns the keys
+//     into the outputs (the kernel boundary orders it after every atomic,
+//     with no device fence).
 #include <algorithm>
 
+#include "fk_chain.hpp"
 #include "grid_sample.hpp"
 
 namespace {
@@ -60,14 +64,17 @@ constexpr float kFar = 1e30f;       // centred coordinate of unused lanes: never
 #define LSDF_QUERY_GATHER 4         // points whose gathers are in flight together
 #endif
 constexpr int kBlockPts = 8;        // points per culling sphere
+constexpr int kSphereBatch = 4;     // culling spheres tested together
 constexpr int kUnroll = LSDF_QUERY_UNROLL;
 constexpr int kGather = LSDF_QUERY_GATHER;
 static_assert(kUnroll % kGather == 0, "gather batch must divide the unroll");
 static_assert(kUnroll == kBlockPts, "blocks of 8 points");
 
-// Default tiling: 4 blocks (32 points) per chunk, 8 workgroups per CU.
+// Default tiling: 4 blocks (32 points) per chunk, 8 workgroups per CU,
+// chunks in per-XCD slices.
 constexpr int kDefaultChunkPoints = 32;
 constexpr int kDefaultBlocksPerCu = 8;
+constexpr int kDefaultSchedule = LSDF_SCHED_XCD_SLICES;
 constexpr int kMaxChunkPoints = 8192;
 constexpr int kMaxBlocksPerCu = 16;
 
@@ -85,18 +92,32 @@ static_assert(sizeof(TrajPlan) == 48, "plan entry layout");
 
 struct QueryArgs {
     LinkGrid link[LSDF_MAX_LINKS];
-    const float* link_T;
+    const float* maps;       // [L][kMapFields][C]
     uint32_t* keys;          // [C][L] complemented ordered keys, 0 = empty
+    int32_t C;
     int32_t K;               // trajectories
     int32_t L;
     int32_t chunk_blocks;    // 8-point blocks per chunk
     int32_t blocks_per_xcd;
+    int32_t schedule;        // LSDF_SCHED_*
 };
 
+// Per (link, configuration): the world-to-grid map and the culling
+// thresholds, stored field-major ([L][kMapFields][C]) so that a wave's 64
+// consecutive configurations read each field with one coalesced load.
+constexpr int kMapFields = 18;   // M (9, row-major), w (3), ||M_a|| (3), k_a (3)
+
 struct PrepArgs {
+    LinkGrid link[LSDF_MAX_LINKS];
+    lsdf::DhTable dh;        // used when q != NULL
+    const float* q;          // joint angles [C][dof], or NULL: poses come from link_T
+    float* link_T_out;       // poses computed from q are stored here when not NULL
+    const float* link_T;
     const float* points;
     float4* spheres;         // [ceil(M / 8)]
     TrajPlan* plan;          // [K + 1]
+    float* maps;             // [L][kMapFields][C]
+    uint32_t* keys;          // [C][L], zeroed here
     const int32_t* c_off;    // device [K + 1] or NULL (one trajectory of all C)
     const int64_t* m_off;    // device [K + 1] or NULL (one trajectory of all M)
     int64_t M;
@@ -107,15 +128,79 @@ struct PrepArgs {
 };
 
 struct FinalizeArgs {
-    uint32_t* keys;
+    const uint32_t* keys;    // [C][L], or NULL
     float* out_dist;
     int32_t* out_link;
     float* out_link_dist;
-    uint32_t* scratch;       // other scratch words to clear (culling spheres, plan), or NULL
-    int64_t scratch_words;
     int32_t C;
     int32_t L;
 };
+
+// One 8-point block against every lane's box: the point tests, then the
+// corner gathers and interpolation of the points inside some lane's box.
+template <bool CUBIC, int DT>
+__device__ __forceinline__ void block_min(const float* __restrict__ points, int64_t j, int64_t m_lo, int64_t m_hi,
+                                          const LinkGrid& lg, const typename GridT<DT>::T* __restrict__ G,
+                                          int nx, int nxy, float m00, float m01, float m02, float w0, float m10,
+                                          float m11, float m12, float w1, float m20, float m21, float m22, float w2,
+                                          float& best) {
+    using E = GridT<DT>;
+    if (j >= m_lo && j + kUnroll <= m_hi) {
+        float v0[kUnroll], v1[kUnroll], v2[kUnroll];
+        bool in[kUnroll];
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const float x = points[3 * j + 3 * u + 0];
+            const float y = points[3 * j + 3 * u + 1];
+            const float z = points[3 * j + 3 * u + 2];
+            v0[u] = fmaf(m00, x, fmaf(m01, y, fmaf(m02, z, w0)));
+            v1[u] = fmaf(m10, x, fmaf(m11, y, fmaf(m12, z, w1)));
+            v2[u] = fmaf(m20, x, fmaf(m21, y, fmaf(m22, z, w2)));
+            in[u] = inside<CUBIC>(lg, v0[u], v1[u], v2[u]);
+            any |= in[u];
+        }
+        if (!__ballot(any)) return;
+#pragma unroll
+        for (int b = 0; b < kUnroll; b += kGather) {
+            // issue every corner load of the batch, then interpolate
+            float c00[kGather], c10[kGather], c01[kGather], c11[kGather];
+            float d00[kGather], d10[kGather], d01[kGather], d11[kGather];
+            Cell cell[kGather];
+#pragma unroll
+            for (int u = 0; u < kGather; ++u) {
+                cell[u] = locate(lg, v0[b + u], v1[b + u], v2[b + u]);
+                // lanes outside the box read the first cell (discarded)
+                const typename E::T* cp = G + (in[b + u] ? cell[u].idx : 0);
+                c00[u] = E::get(cp, 0);        d00[u] = E::get(cp, 1);
+                c10[u] = E::get(cp, nx);       d10[u] = E::get(cp, nx + 1);
+                c01[u] = E::get(cp, nxy);      d01[u] = E::get(cp, nxy + 1);
+                c11[u] = E::get(cp, nxy + nx); d11[u] = E::get(cp, nxy + nx + 1);
+            }
+#pragma unroll
+            for (int u = 0; u < kGather; ++u) {
+                const float val = interpolate(c00[u], d00[u], c10[u], d10[u], c01[u], d01[u], c11[u], d11[u], cell[u]);
+                if (in[b + u]) best = fminf(best, val);
+            }
+        }
+    } else {
+        // a block at either end of the trajectory's points
+        const int64_t ja = max(j, m_lo), jz = min(j + kBlockPts, m_hi);
+        for (int64_t jj = ja; jj < jz; ++jj) {
+            const float x = points[3 * jj + 0], y = points[3 * jj + 1], z = points[3 * jj + 2];
+            const float v0 = fmaf(m00, x, fmaf(m01, y, fmaf(m02, z, w0)));
+            const float v1 = fmaf(m10, x, fmaf(m11, y, fmaf(m12, z, w1)));
+            const float v2 = fmaf(m20, x, fmaf(m21, y, fmaf(m22, z, w2)));
+            if (inside<CUBIC>(lg, v0, v1, v2)) {
+                const Cell ce = locate(lg, v0, v1, v2);
+                const typename E::T* cp = G + ce.idx;
+                best = fminf(best, interpolate(E::get(cp, 0), E::get(cp, 1), E::get(cp, nx), E::get(cp, nx + 1),
+                                               E::get(cp, nxy), E::get(cp, nxy + 1), E::get(cp, nxy + nx),
+                                               E::get(cp, nxy + nx + 1), ce));
+            }
+        }
+    }
+}
 
 template <bool CUBIC, int DT>
 __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float* __restrict__ points,
@@ -125,33 +210,53 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
     using E = GridT<DT>;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int xcd = blockIdx.x % kXcds;
-    const int slot = blockIdx.x / kXcds;
-    const int waves_per_xcd = p.blocks_per_xcd * kWavesPerBlock;
-    const int wx = slot * kWavesPerBlock + wave;                 // wave index inside the XCD
     const int64_t total = plan[p.K].chunk_start;
-    const int64_t q_lo = total * xcd / kXcds;                    // this XCD's slice of chunks
-    const int64_t q_hi = total * (xcd + 1) / kXcds;
-    if (q_lo + wx >= q_hi) return;
+    int64_t q_first, q_end, q_step;
+    if (p.schedule == LSDF_SCHED_XCD_SLICES) {
+        // each XCD (blocks b = x mod 8) takes a contiguous slice of chunks
+        // and deals it round-robin to its waves
+        const int xcd = blockIdx.x % kXcds;
+        const int slot = blockIdx.x / kXcds;
+        q_first = total * xcd / kXcds + slot * kWavesPerBlock + wave;
+        q_end = total * (xcd + 1) / kXcds;
+        q_step = (int64_t)p.blocks_per_xcd * kWavesPerBlock;
+    } else {
+        // every wave of the grid takes every W-th chunk
+        q_first = (int64_t)blockIdx.x * kWavesPerBlock + wave;
+        q_end = total;
+        q_step = (int64_t)gridDim.x * kWavesPerBlock;
+    }
+    if (q_first >= q_end) return;
 
     // trajectory of the first chunk: the last entry whose start is <= q
     int k = 0;
     {
         int hi = p.K - 1;
-        const int64_t q0 = q_lo + wx;
         while (k < hi) {
             const int mid = (k + hi + 1) >> 1;
-            if (plan[mid].chunk_start <= q0) k = mid; else hi = mid - 1;
+            if (plan[mid].chunk_start <= q_first) k = mid; else hi = mid - 1;
         }
     }
+    // the current trajectory's plan, kept in registers until q passes its end
+    int64_t t_start = plan[k].chunk_start, t_next = plan[k + 1].chunk_start;
+    int64_t m_lo = plan[k].m_lo, m_hi = plan[k].m_hi;
+    int c_lo = plan[k].c_lo, c_n = plan[k].c_n, cgroups = plan[k].cgroups, cpg = plan[k].chunks_per_group;
 
-    for (int64_t q = q_lo + wx; q < q_hi; q += waves_per_xcd) {
-        while (plan[k + 1].chunk_start <= q) ++k;   // stops at k + 1 = K at the latest: q < total
-        k = __builtin_amdgcn_readfirstlane(k);
-        const int64_t local = q - plan[k].chunk_start;
-        const int64_t m_lo = plan[k].m_lo, m_hi = plan[k].m_hi;
-        const int c_lo = plan[k].c_lo, c_n = plan[k].c_n;
-        const int cgroups = plan[k].cgroups, cpg = plan[k].chunks_per_group;
+    for (int64_t q = q_first; q < q_end; q += q_step) {
+        if (q >= t_next) {   // stops at k + 1 = K at the latest: q < total
+            do {
+                ++k;
+                t_next = plan[k + 1].chunk_start;
+            } while (q >= t_next);
+            t_start = plan[k].chunk_start;
+            m_lo = plan[k].m_lo;
+            m_hi = plan[k].m_hi;
+            c_lo = plan[k].c_lo;
+            c_n = plan[k].c_n;
+            cgroups = plan[k].cgroups;
+            cpg = plan[k].chunks_per_group;
+        }
+        const int64_t local = q - t_start;
         int64_t g, mc;
         if (local < ((int64_t)1 << 32)) {
             const uint32_t l32 = (uint32_t)local;
@@ -171,119 +276,109 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
         const int64_t jb0 = ((m_lo >> 3) + mc * p.chunk_blocks) * kBlockPts;
         const int64_t jb1 = min(m_hi, jb0 + (int64_t)p.chunk_blocks * kBlockPts);
 
-        // this lane's map: v = M [x; y; z] + w (centred grid coordinates)
+        // this lane's map v = M [x; y; z] + w (centred grid coordinates) and
+        // its culling thresholds, from the table the first kernel built;
+        // lanes past the trajectory's configurations are never near or inside
         float m00 = 0.f, m01 = 0.f, m02 = 0.f, w0 = kFar;
         float m10 = 0.f, m11 = 0.f, m12 = 0.f, w1 = kFar;
         float m20 = 0.f, m21 = 0.f, m22 = 0.f, w2 = kFar;
+        float nr0 = 0.f, nr1 = 0.f, nr2 = 0.f, k0 = 0.f, k1 = 0.f, k2 = 0.f;
         if (cl < c_n) {
-            const float* T = p.link_T + ((int64_t)c * p.L + i) * 12;
-            const float r00 = T[0], r01 = T[1], r02 = T[2], t0 = T[3];
-            const float r10 = T[4], r11 = T[5], r12 = T[6], t1 = T[7];
-            const float r20 = T[8], r21 = T[9], r22 = T[10], t2 = T[11];
-            // row a of R^T scaled by invh_a; offset -invh_a (R^T t)_a + cen_a
-            m00 = lg.invh[0] * r00; m01 = lg.invh[0] * r10; m02 = lg.invh[0] * r20;
-            m10 = lg.invh[1] * r01; m11 = lg.invh[1] * r11; m12 = lg.invh[1] * r21;
-            m20 = lg.invh[2] * r02; m21 = lg.invh[2] * r12; m22 = lg.invh[2] * r22;
-            w0 = fmaf(-lg.invh[0], fmaf(r00, t0, fmaf(r10, t1, r20 * t2)), lg.cen[0]);
-            w1 = fmaf(-lg.invh[1], fmaf(r01, t0, fmaf(r11, t1, r21 * t2)), lg.cen[1]);
-            w2 = fmaf(-lg.invh[2], fmaf(r02, t0, fmaf(r12, t1, r22 * t2)), lg.cen[2]);
+            const float* mp = p.maps + (int64_t)i * kMapFields * p.C + c;
+            const int64_t C = p.C;
+            m00 = mp[0 * C]; m01 = mp[1 * C]; m02 = mp[2 * C];
+            m10 = mp[3 * C]; m11 = mp[4 * C]; m12 = mp[5 * C];
+            m20 = mp[6 * C]; m21 = mp[7 * C]; m22 = mp[8 * C];
+            w0 = mp[9 * C]; w1 = mp[10 * C]; w2 = mp[11 * C];
+            nr0 = mp[12 * C]; nr1 = mp[13 * C]; nr2 = mp[14 * C];
+            k0 = mp[15 * C]; k1 = mp[16 * C]; k2 = mp[17 * C];
         }
         const int nx = lg.n[0];
         const int nxy = lg.n[0] * lg.n[1];
 
-        // culling threshold of this lane per axis: half_a + ||M_a|| rho + slack,
-        // where rho (per block) already holds the radius and the rounding bound
-        // that scales with the coordinates; ||M_a|| is the row's own norm
-        const float nr0 = sqrtf(fmaf(m00, m00, fmaf(m01, m01, m02 * m02))) * 1.000001f;
-        const float nr1 = sqrtf(fmaf(m10, m10, fmaf(m11, m11, m12 * m12))) * 1.000001f;
-        const float nr2 = sqrtf(fmaf(m20, m20, fmaf(m21, m21, m22 * m22))) * 1.000001f;
-        const float k0 = lg.half[0] + fmaf(1e-4f, fabsf(w0), 1e-3f);
-        const float k1 = lg.half[1] + fmaf(1e-4f, fabsf(w1), 1e-3f);
-        const float k2 = lg.half[2] + fmaf(1e-4f, fabsf(w2), 1e-3f);
-
         float best = INFINITY;
-        for (int64_t j = jb0; j < jb1; j += kBlockPts) {
-            // the sphere bounds all 8 points of the block, so also the
-            // trajectory's share of a block it shares with its neighbour
-            const float4 sph = spheres[j / kBlockPts];
-            const float s0 = fmaf(m00, sph.x, fmaf(m01, sph.y, fmaf(m02, sph.z, w0)));
-            const float s1 = fmaf(m10, sph.x, fmaf(m11, sph.y, fmaf(m12, sph.z, w1)));
-            const float s2 = fmaf(m20, sph.x, fmaf(m21, sph.y, fmaf(m22, sph.z, w2)));
-            const bool near = (fabsf(s0) <= fmaf(nr0, sph.w, k0)) & (fabsf(s1) <= fmaf(nr1, sph.w, k1)) &
-                              (fabsf(s2) <= fmaf(nr2, sph.w, k2));
-            if (!__ballot(near)) continue;   // no point of the block is in any lane's box
-            if (j >= m_lo && j + kUnroll <= m_hi) {
-                float v0[kUnroll], v1[kUnroll], v2[kUnroll];
-                bool in[kUnroll];
-                bool any = false;
+        for (int64_t jb = jb0; jb < jb1; jb += kSphereBatch * kBlockPts) {
+            // the spheres of up to 4 blocks are loaded together (the sphere
+            // array has kSphereBatch - 1 spare entries past its end); a sphere
+            // bounds all 8 points of its block, so also the trajectory's share
+            // of a block it shares with its neighbour
+            uint32_t near_mask = 0;
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const float x = points[3 * j + 3 * u + 0];
-                    const float y = points[3 * j + 3 * u + 1];
-                    const float z = points[3 * j + 3 * u + 2];
-                    v0[u] = fmaf(m00, x, fmaf(m01, y, fmaf(m02, z, w0)));
-                    v1[u] = fmaf(m10, x, fmaf(m11, y, fmaf(m12, z, w1)));
-                    v2[u] = fmaf(m20, x, fmaf(m21, y, fmaf(m22, z, w2)));
-                    in[u] = inside<CUBIC>(lg, v0[u], v1[u], v2[u]);
-                    any |= in[u];
-                }
-                if (__ballot(any)) {
-#pragma unroll
-                    for (int b = 0; b < kUnroll; b += kGather) {
-                        // issue every corner load of the batch, then interpolate
-                        float c00[kGather], c10[kGather], c01[kGather], c11[kGather];
-                        float d00[kGather], d10[kGather], d01[kGather], d11[kGather];
-                        Cell cell[kGather];
-#pragma unroll
-                        for (int u = 0; u < kGather; ++u) {
-                            cell[u] = locate(lg, v0[b + u], v1[b + u], v2[b + u]);
-                            // lanes outside the box read the first cell (discarded)
-                            const typename E::T* cp = G + (in[b + u] ? cell[u].idx : 0);
-                            c00[u] = E::get(cp, 0);        d00[u] = E::get(cp, 1);
-                            c10[u] = E::get(cp, nx);       d10[u] = E::get(cp, nx + 1);
-                            c01[u] = E::get(cp, nxy);      d01[u] = E::get(cp, nxy + 1);
-                            c11[u] = E::get(cp, nxy + nx); d11[u] = E::get(cp, nxy + nx + 1);
-                        }
-#pragma unroll
-                        for (int u = 0; u < kGather; ++u) {
-                            const float val = interpolate(c00[u], d00[u], c10[u], d10[u], c01[u], d01[u], c11[u],
-                                                          d11[u], cell[u]);
-                            if (in[b + u]) best = fminf(best, val);
-                        }
-                    }
-                }
-            } else {
-                // a block at either end of the trajectory's points
-                const int64_t ja = max(j, m_lo), jz = min(j + kBlockPts, m_hi);
-                for (int64_t jj = ja; jj < jz; ++jj) {
-                    const float x = points[3 * jj + 0], y = points[3 * jj + 1], z = points[3 * jj + 2];
-                    const float v0 = fmaf(m00, x, fmaf(m01, y, fmaf(m02, z, w0)));
-                    const float v1 = fmaf(m10, x, fmaf(m11, y, fmaf(m12, z, w1)));
-                    const float v2 = fmaf(m20, x, fmaf(m21, y, fmaf(m22, z, w2)));
-                    if (inside<CUBIC>(lg, v0, v1, v2)) {
-                        const Cell ce = locate(lg, v0, v1, v2);
-                        const typename E::T* cp = G + ce.idx;
-                        best = fminf(best, interpolate(E::get(cp, 0), E::get(cp, 1), E::get(cp, nx), E::get(cp, nx + 1),
-                                                       E::get(cp, nxy), E::get(cp, nxy + 1), E::get(cp, nxy + nx),
-                                                       E::get(cp, nxy + nx + 1), ce));
-                    }
-                }
+            for (int u = 0; u < kSphereBatch; ++u) {
+                const float4 sph = spheres[jb / kBlockPts + u];
+                const float s0 = fmaf(m00, sph.x, fmaf(m01, sph.y, fmaf(m02, sph.z, w0)));
+                const float s1 = fmaf(m10, sph.x, fmaf(m11, sph.y, fmaf(m12, sph.z, w1)));
+                const float s2 = fmaf(m20, sph.x, fmaf(m21, sph.y, fmaf(m22, sph.z, w2)));
+                const bool near = (fabsf(s0) <= fmaf(nr0, sph.w, k0)) & (fabsf(s1) <= fmaf(nr1, sph.w, k1)) &
+                                  (fabsf(s2) <= fmaf(nr2, sph.w, k2));
+                if (__ballot(near) && jb + u * kBlockPts < jb1) near_mask |= 1u << u;
+            }
+            while (near_mask) {   // wave-uniform: blocks some lane's box may reach
+                const int u = __builtin_ctz(near_mask);
+                near_mask &= near_mask - 1;
+                block_min<CUBIC, DT>(points, jb + u * kBlockPts, m_lo, m_hi, lg, G, nx, nxy, m00, m01, m02, w0, m10,
+                                     m11, m12, w1, m20, m21, m22, w2, best);
             }
         }
         if (cl < c_n && best < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(best));
     }
 }
 
-// First kernel of a query.  Every thread bounds one block of 8 consecutive
-// points of the concatenated cloud by a sphere: the centre of the block's
-// box and a radius widened by a relative 1e-5, by 1e-4 of the sum of the
-// coordinates' magnitudes (which bounds FP32 rounding of the mapped
-// coordinates) and by 1e-6 m.  Workgroup 0 also builds the plan: each
+// First kernel of a query.  Thread t < C L zeroes key t and writes the map
+// table entry of (link t / C, configuration t mod C), from the given pose or,
+// in the fused form, from the pose it computes from the joint angles.  Thread t < ceil(M / 8)
+// bounds block t of 8 consecutive points of the concatenated cloud by a
+// sphere: the centre of the block's box and a radius widened by a relative
+// 1e-5, by 1e-4 of the sum of the coordinates' magnitudes (which bounds FP32
+// rounding of the mapped coordinates) and by 1e-6 m.  Workgroup 0 also
+// builds the plan: each
 // trajectory's ranges clamped into [0, C) and [0, M) (so a bad offset table
 // gives wrong ranges, never an access out of bounds), its chunk count and
 // the exclusive prefix sum of the counts.
 __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b < (int64_t)a.C * a.L) {
+        a.keys[b] = 0u;
+        // map of link i at configuration c: row a of R^T scaled by invh_a,
+        // offset -invh_a (R^T t)_a + cen_a (the inverse pose of Eq. 4 with
+        // the grid scaling folded in); then the culling thresholds: the
+        // row norms (x (1 + 1e-6)) and half_a plus a bound on FP32 rounding
+        const int i = (int)(b / a.C);
+        const int64_t c = b - (int64_t)i * a.C;
+        const LinkGrid& lg = a.link[i];
+        float Tq[12];
+        const float* T = a.link_T + (c * a.L + i) * 12;
+        if (a.q) {
+            // the pose from the joint angles, with the kinematics kernel's
+            // arithmetic (same bits as lsdf_fk_batch)
+            lsdf::chain_pose(a.dh, a.q + c * a.dh.dof, i, Tq);
+            if (a.link_T_out) {
+                float* o = a.link_T_out + (c * a.L + i) * 12;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) o[k] = Tq[k];
+            }
+            T = Tq;
+        }
+        const float r00 = T[0], r01 = T[1], r02 = T[2], t0 = T[3];
+        const float r10 = T[4], r11 = T[5], r12 = T[6], t1 = T[7];
+        const float r20 = T[8], r21 = T[9], r22 = T[10], t2 = T[11];
+        float f[kMapFields];
+        f[0] = lg.invh[0] * r00; f[1] = lg.invh[0] * r10; f[2] = lg.invh[0] * r20;
+        f[3] = lg.invh[1] * r01; f[4] = lg.invh[1] * r11; f[5] = lg.invh[1] * r21;
+        f[6] = lg.invh[2] * r02; f[7] = lg.invh[2] * r12; f[8] = lg.invh[2] * r22;
+        f[9] = fmaf(-lg.invh[0], fmaf(r00, t0, fmaf(r10, t1, r20 * t2)), lg.cen[0]);
+        f[10] = fmaf(-lg.invh[1], fmaf(r01, t0, fmaf(r11, t1, r21 * t2)), lg.cen[1]);
+        f[11] = fmaf(-lg.invh[2], fmaf(r02, t0, fmaf(r12, t1, r22 * t2)), lg.cen[2]);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const float* m = f + 3 * ax;
+            f[12 + ax] = sqrtf(fmaf(m[0], m[0], fmaf(m[1], m[1], m[2] * m[2]))) * 1.000001f;
+            f[15 + ax] = lg.half[ax] + fmaf(1e-4f, fabsf(f[9 + ax]), 1e-3f);
+        }
+        float* out = a.maps + (int64_t)i * kMapFields * a.C + c;
+#pragma unroll
+        for (int k = 0; k < kMapFields; ++k) out[(int64_t)k * a.C] = f[k];
+    }
     const int64_t j0 = b * kBlockPts;
     if (j0 < a.M) {
         const float* points = a.points;
@@ -349,23 +444,20 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
     }
 }
 
-// Keys -> outputs, one lane per configuration; clears the keys and the
-// rest of the scratch, so that the whole workspace is zero again.
+// Keys -> outputs, one lane per configuration (keys == NULL: no pair was
+// evaluated, every configuration gets +inf and -1).
 __global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs p) {
     const int c = blockIdx.x * kBlock + threadIdx.x;
-    for (int64_t k = c; k < p.scratch_words; k += (int64_t)gridDim.x * kBlock) p.scratch[k] = 0u;
     if (c >= p.C) return;
-    uint32_t* row = p.keys + (int64_t)c * p.L;
     uint32_t k[LSDF_MAX_LINKS];
 #pragma unroll
     for (int i = 0; i < LSDF_MAX_LINKS; ++i)
-        if (i < p.L) k[i] = row[i];
+        if (i < p.L) k[i] = p.keys ? p.keys[(int64_t)c * p.L + i] : 0u;
     uint32_t bestk = 0;
     int arg = -1;
 #pragma unroll
     for (int i = 0; i < LSDF_MAX_LINKS; ++i) {
         if (i < p.L) {
-            row[i] = 0u;
             if (p.out_link_dist) p.out_link_dist[(int64_t)c * p.L + i] = k[i] ? lsdf::from_ordered_bits(~k[i]) : INFINITY;
             if (k[i] > bestk) {   // strict: ties keep the lowest link
                 bestk = k[i];
@@ -377,22 +469,42 @@ __global__ __launch_bounds__(kBlock) void finalize_kernel(FinalizeArgs p) {
     p.out_link[c] = arg;
 }
 
+// Zeroes n words (the learned query's keys before its main kernel).
+__global__ __launch_bounds__(kBlock) void zero_kernel(uint32_t* w, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) w[t] = 0u;
+}
+
 }  // namespace
 
-int lsdf::launch_query_finalize(uint32_t* keys, float* out_dist, int32_t* out_link, float* out_link_dist, int32_t C,
-                                int32_t L, hipStream_t s, uint32_t* scratch, int64_t scratch_words) {
-    FinalizeArgs f{keys, out_dist, out_link, out_link_dist, scratch, scratch_words, C, L};
-    const int64_t rows = std::max<int64_t>(C, std::min<int64_t>(scratch_words, (int64_t)1 << 20));
-    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)std::max<int64_t>(1, (rows + kBlock - 1) / kBlock)), dim3(kBlock),
-                       0, s, f);
+int lsdf::launch_query_finalize(const uint32_t* keys, float* out_dist, int32_t* out_link, float* out_link_dist, int32_t C,
+                                int32_t L, hipStream_t s) {
+    FinalizeArgs f{keys, out_dist, out_link, out_link_dist, C, L};
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((C + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, f);
     return check_launch("query finalize");
+}
+
+int lsdf::launch_zero_words(uint32_t* w, int64_t n, hipStream_t s) {
+    if (n <= 0) return LSDF_OK;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, w, n);
+    return check_launch("zero words");
 }
 
 namespace {
 
 size_t keys_bytes(int64_t C, int64_t L) { return ((size_t)(C * L) * 4 + 255) / 256 * 256; }
-size_t sphere_bytes(int64_t M) { return ((size_t)((M + kBlockPts - 1) / kBlockPts) * 16 + 255) / 256 * 256; }
+// kSphereBatch - 1 spare spheres past the end: the query loads spheres in
+// batches and ignores those past a chunk's last block
+size_t sphere_bytes(int64_t M) {
+    return ((size_t)((M + kBlockPts - 1) / kBlockPts + kSphereBatch - 1) * 16 + 255) / 256 * 256;
+}
 size_t plan_bytes(int64_t K) { return ((size_t)(K + 1) * sizeof(TrajPlan) + 255) / 256 * 256; }
+size_t map_bytes(int64_t C, int64_t L) { return ((size_t)(C * L) * kMapFields * 4 + 255) / 256 * 256; }
+
+// Workspace: keys | spheres | plan | maps, each 256-byte aligned.
+size_t workspace_bytes(int64_t K, int64_t C, int64_t L, int64_t M) {
+    return keys_bytes(C, L) + sphere_bytes(M) + plan_bytes(K) + map_bytes(C, L);
+}
 
 int device_cus() {
     int dev = 0, cus = 0;
@@ -401,10 +513,12 @@ int device_cus() {
     return cus;
 }
 
-int check_tuning(const char* who, const lsdf_query_tuning* t, int* chunk_blocks, int* blocks_per_cu) {
+int check_tuning(const char* who, const lsdf_query_tuning* t, int* chunk_blocks, int* blocks_per_cu,
+                 int* schedule) {
     using lsdf::fail;
     *chunk_blocks = kDefaultChunkPoints / kBlockPts;
     *blocks_per_cu = kDefaultBlocksPerCu;
+    *schedule = kDefaultSchedule;
     if (!t) return LSDF_OK;
     if (t->chunk_points != 0) {
         if (t->chunk_points < kBlockPts || t->chunk_points > kMaxChunkPoints || t->chunk_points % kBlockPts != 0)
@@ -418,14 +532,23 @@ int check_tuning(const char* who, const lsdf_query_tuning* t, int* chunk_blocks,
                         kMaxBlocksPerCu);
         *blocks_per_cu = t->blocks_per_cu;
     }
+    if (t->schedule != LSDF_SCHED_DEFAULT) {
+        if (t->schedule != LSDF_SCHED_XCD_SLICES && t->schedule != LSDF_SCHED_INTERLEAVED)
+            return fail(LSDF_E_INVALID_ARG, "%s: unknown schedule %d", who, (int)t->schedule);
+        *schedule = t->schedule;
+    }
+    if (t->reserved != 0) return fail(LSDF_E_INVALID_ARG, "%s: tuning.reserved must be 0", who);
     return LSDF_OK;
 }
 
 // Shared body of the plain (K = 1, no offset arrays) and batched queries.
+// With dh != NULL the poses are computed from the joint angles q in the
+// first kernel (and stored in link_T when it is not NULL).
 int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m_off, const float* link_T, int32_t C,
               int32_t L, const lsdf_grid* grids, const void* grid_buf, const float* points, int64_t M, float* out_dist,
               int32_t* out_link, float* out_link_dist, const lsdf_query_tuning* tuning, uint32_t flags,
-              void* workspace, size_t ws_bytes, void* stream) {
+              void* workspace, size_t ws_bytes, void* stream, const lsdf::DhTable* dh = nullptr,
+              const float* q = nullptr) {
     using namespace lsdf;
     if (flags != 0) return fail(LSDF_E_UNSUPPORTED, "%s: unsupported flags 0x%x", who, flags);
     if (C < 0 || M < 0 || M > LSDF_MAX_POINTS)
@@ -434,16 +557,18 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
     if (K < 1 || K > LSDF_MAX_TRAJECTORIES)
         return fail(LSDF_E_SHAPE, "%s: K = %d out of [1, %d]", who, (int)K, LSDF_MAX_TRAJECTORIES);
     if (!grids) return fail(LSDF_E_INVALID_ARG, "%s: grids is NULL", who);
-    int chunk_blocks = 0, blocks_per_cu = 0;
-    int rc = check_tuning(who, tuning, &chunk_blocks, &blocks_per_cu);
+    int chunk_blocks = 0, blocks_per_cu = 0, schedule = 0;
+    int rc = check_tuning(who, tuning, &chunk_blocks, &blocks_per_cu, &schedule);
     if (rc != LSDF_OK) return rc;
     if (C == 0) return LSDF_OK;
-    if (!link_T || !grid_buf || !out_dist || !out_link || !workspace)
+    if ((!dh && !link_T) || (dh && !q) || !grid_buf || !out_dist || !out_link || !workspace)
         return fail(LSDF_E_INVALID_ARG, "%s: NULL device pointer", who);
+    if (dh && L != dh->dof + 1)
+        return fail(LSDF_E_SHAPE, "%s: %d grids for a %d-joint arm (needs dof + 1)", who, (int)L, (int)dh->dof);
     if (M > 0 && !points) return fail(LSDF_E_INVALID_ARG, "%s: points is NULL", who);
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return fail(LSDF_E_INVALID_ARG, "%s: workspace is not 256-byte aligned", who);
-    const size_t need = keys_bytes(C, L) + sphere_bytes(M) + plan_bytes(K);
+    const size_t need = workspace_bytes(K, C, L, M);
     if (ws_bytes < need) return fail(LSDF_E_SHAPE, "%s: workspace has %zu bytes, needs %zu", who, ws_bytes, need);
 
     QueryArgs p{};
@@ -459,11 +584,43 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
     char* ws = static_cast<char*>(workspace);
     float4* spheres = reinterpret_cast<float4*>(ws + keys_bytes(C, L));
     TrajPlan* plan = reinterpret_cast<TrajPlan*>(ws + keys_bytes(C, L) + sphere_bytes(M));
-    p.link_T = link_T;
+    float* maps = reinterpret_cast<float*>(ws + keys_bytes(C, L) + sphere_bytes(M) + plan_bytes(K));
+    p.maps = maps;
     p.keys = reinterpret_cast<uint32_t*>(ws);
+    p.C = C;
     p.K = K;
     p.L = L;
     p.chunk_blocks = chunk_blocks;
+    p.schedule = schedule;
+    // the first kernel runs when there are points to test, or when poses
+    // computed from joint angles are asked for
+    if (M > 0 || (dh && link_T)) {
+        PrepArgs a{};
+        for (int i = 0; i < L; ++i) a.link[i] = p.link[i];
+        if (dh) {
+            a.dh = *dh;
+            a.q = q;
+            a.link_T_out = const_cast<float*>(link_T);   // an output in the fused form
+        }
+        a.link_T = link_T;
+        a.points = points;
+        a.spheres = spheres;
+        a.plan = plan;
+        a.maps = maps;
+        a.keys = p.keys;
+        a.c_off = c_off;
+        a.m_off = m_off;
+        a.M = M;
+        a.C = C;
+        a.K = K;
+        a.L = L;
+        a.chunk_blocks = chunk_blocks;
+        const int64_t nsph = (M + kBlockPts - 1) / kBlockPts;
+        const int64_t threads = std::max<int64_t>(nsph, (int64_t)C * L);
+        hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
+        rc = check_launch(who);
+        if (rc != LSDF_OK) return rc;
+    }
     if (M > 0) {
         const int cus = device_cus();
         if (cus <= 0) return fail(LSDF_E_DEVICE, "%s: cannot read the device's compute-unit count", who);
@@ -478,12 +635,6 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
         }
         blocks = (blocks + kXcds - 1) / kXcds * kXcds;
         p.blocks_per_xcd = (int32_t)(blocks / kXcds);
-
-        PrepArgs a{points, spheres, plan, c_off, m_off, M, C, K, L, chunk_blocks};
-        const int64_t nsph = (M + kBlockPts - 1) / kBlockPts;
-        hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((nsph + 255) / 256)), dim3(256), 0, s, a);
-        rc = check_launch(who);
-        if (rc != LSDF_OK) return rc;
         const float4* sph = spheres;
         const TrajPlan* pl = plan;
         const dim3 gd((unsigned)blocks), bd(kBlock);
@@ -502,11 +653,9 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
         if (rc != LSDF_OK) return rc;
         if (ev1 && hipEventRecord(ev1, s) != hipSuccess) return fail(LSDF_E_DEVICE, "%s: event record failed", who);
     }
-    // the spheres and the plan are cleared with the keys: the next call may
-    // lay its keys over them
-    uint32_t* scratch = reinterpret_cast<uint32_t*>(spheres);
-    const int64_t scratch_words = M > 0 ? (int64_t)(sphere_bytes(M) + plan_bytes(K)) / 4 : 0;
-    return launch_query_finalize(p.keys, out_dist, out_link, out_link_dist, C, L, s, scratch, scratch_words);
+    // M = 0: no prep kernel ran and no key is meaningful; every
+    // configuration gets +inf and -1
+    return launch_query_finalize(M > 0 ? p.keys : nullptr, out_dist, out_link, out_link_dist, C, L, s);
 }
 
 }  // namespace
@@ -523,7 +672,7 @@ LSDF_API int lsdf_query_batched_workspace_size(int32_t K, int32_t C, int32_t L, 
     if (L < 1 || L > LSDF_MAX_LINKS) return fail(LSDF_E_SHAPE, "query_workspace_size: L = %d out of [1, %d]", (int)L, LSDF_MAX_LINKS);
     if (K < 1 || K > LSDF_MAX_TRAJECTORIES)
         return fail(LSDF_E_SHAPE, "query_workspace_size: K = %d out of [1, %d]", (int)K, LSDF_MAX_TRAJECTORIES);
-    *bytes = keys_bytes(C, L) + sphere_bytes(M) + plan_bytes(K);
+    *bytes = workspace_bytes(K, C, L, M);
     return LSDF_OK;
 }
 
@@ -549,6 +698,25 @@ LSDF_API int lsdf_query_min_distance_batched(int32_t K, const int32_t* traj_c_of
                      out_dist, out_link, out_link_dist, tuning, flags, workspace, ws_bytes, stream);
 }
 
+LSDF_API int lsdf_query_from_joints(const lsdf_dh* dh, int32_t dof, const float* base_T, const float* q,
+                                    int32_t K, const int32_t* traj_c_offset, const int64_t* traj_m_offset,
+                                    int32_t C, const lsdf_grid* grids, const void* grid_buf, const float* points,
+                                    int64_t M, float* link_T, float* out_dist, int32_t* out_link,
+                                    float* out_link_dist, const lsdf_query_tuning* tuning, uint32_t flags,
+                                    void* workspace, size_t ws_bytes, void* stream) {
+    using namespace lsdf;
+    clear_error();
+    DhTable t;
+    int rc = make_dh_table("query_from_joints", dh, dof, base_T, &t);
+    if (rc != LSDF_OK) return rc;
+    if ((traj_c_offset == nullptr) != (traj_m_offset == nullptr))
+        return fail(LSDF_E_INVALID_ARG, "query_from_joints: give both offset arrays or neither");
+    if (!traj_c_offset && K != 1)
+        return fail(LSDF_E_SHAPE, "query_from_joints: K = %d without offset arrays (must be 1)", (int)K);
+    return run_query("query_from_joints", K, traj_c_offset, traj_m_offset, link_T, C, dof + 1, grids, grid_buf,
+                     points, M, out_dist, out_link, out_link_dist, tuning, flags, workspace, ws_bytes, stream, &t, q);
+}
+
 LSDF_API int lsdf_query_autotune(int32_t K, const int32_t* traj_c_offset, const int64_t* traj_m_offset,
                                  const float* link_T, int32_t C, int32_t L, const lsdf_grid* grids,
                                  const void* grid_buf, const float* points, int64_t M, float* out_dist,
@@ -561,8 +729,13 @@ LSDF_API int lsdf_query_autotune(int32_t K, const int32_t* traj_c_offset, const 
     if (!best) return fail(LSDF_E_INVALID_ARG, "query_autotune: best is NULL");
     if (reps < 1 || reps > 1000) return fail(LSDF_E_INVALID_ARG, "query_autotune: reps = %d out of [1, 1000]", (int)reps);
     static const lsdf_query_tuning kGrid[] = {
-        {8, 8},   {16, 8},  {32, 8},  {64, 8},  {128, 8}, {256, 8}, {1024, 8},
-        {16, 4},  {32, 4},  {64, 4},  {128, 4}, {32, 2},  {64, 2},  {128, 2},
+        {32, 8, LSDF_SCHED_XCD_SLICES, 0},    {32, 8, LSDF_SCHED_INTERLEAVED, 0},
+        {64, 8, LSDF_SCHED_XCD_SLICES, 0},    {64, 8, LSDF_SCHED_INTERLEAVED, 0},
+        {128, 8, LSDF_SCHED_XCD_SLICES, 0},   {128, 8, LSDF_SCHED_INTERLEAVED, 0},
+        {256, 8, LSDF_SCHED_XCD_SLICES, 0},   {256, 8, LSDF_SCHED_INTERLEAVED, 0},
+        {1024, 8, LSDF_SCHED_XCD_SLICES, 0},  {1024, 8, LSDF_SCHED_INTERLEAVED, 0},
+        {4096, 8, LSDF_SCHED_INTERLEAVED, 0}, {128, 4, LSDF_SCHED_INTERLEAVED, 0},
+        {256, 4, LSDF_SCHED_INTERLEAVED, 0},  {1024, 4, LSDF_SCHED_INTERLEAVED, 0},
     };
     if (!candidates) {
         candidates = kGrid;
@@ -570,8 +743,8 @@ LSDF_API int lsdf_query_autotune(int32_t K, const int32_t* traj_c_offset, const 
     }
     if (n_candidates < 1) return fail(LSDF_E_INVALID_ARG, "query_autotune: no candidates");
     for (int32_t c = 0; c < n_candidates; ++c) {
-        int cb = 0, bpc = 0;
-        int rc = check_tuning("query_autotune", &candidates[c], &cb, &bpc);
+        int cb = 0, bpc = 0, sch = 0;
+        int rc = check_tuning("query_autotune", &candidates[c], &cb, &bpc, &sch);
         if (rc != LSDF_OK) return rc;
     }
     hipStream_t s = as_stream(stream);

@@ -1,0 +1,336 @@
+// The paper's own pipeline (Sec. III-A, Eq. 1-4): per configuration, a
+// "Robot SDF" over the voxels of the environment, the minimum over links of
+// each link's SDF transformed by its pose and aligned to the environment
+// grid; at run time the distance of a configuration is a pure gather, the
+// minimum of its Robot SDF over the voxels the obstacle points occupy.
+// It is kept here as the comparator of the per-point query: heavy
+// preparation and C x V voxels of memory against a trivial runtime.
+//
+// Build (one thread per environment voxel, voxels x fastest, so every
+// store is coalesced and each voxel is written exactly once, without
+// atomics):
+//   * link i's block at configuration c covers voxels k .. k + 2m - 1 per
+//     axis, with k from the alignment of Eq. 1-3 (computed in double from
+//     the link origin: T_O = t - lo, k = round(T_O / r) - m) and m the
+//     block half-width in voxels (the farthest corner of the link's grid box
+//     from the link origin, rounded up, plus two voxels, so that the block
+//     holds every voxel whose centre can fall in the box);
+//   * a voxel's value is the minimum, over the links whose block covers it,
+//     of the link grid's interpolant at the voxel centre moved into the link
+//     frame (the transformation of Eq. 4), +inf where no such link's box
+//     holds the centre.  The centre is lo + (v + 1/2) r (double, rounded
+//     once to float) and the interpolant uses the plain query's arithmetic,
+//     so each value is bit-identical to the plain query at that point.
+// Runtime: zero an occupancy bitmap and a counter; voxelise the points
+// (floor((x - lo) / r) in double), keeping the first point of each voxel
+// in a list of distinct occupied voxels; one workgroup per configuration
+// takes the minimum of its Robot SDF over the list.
+#include <algorithm>
+
+#include "grid_sample.hpp"
+
+namespace {
+
+using lsdf::GridT;
+using lsdf::LinkGrid;
+
+constexpr int kBlock = 256;
+
+struct LinkBlock {   // per (configuration, link): block corner and grid map
+    int32_t k[3];
+    int32_t pad;
+    lsdf::GridMap gm;
+};
+static_assert(sizeof(LinkBlock) == 64, "LinkBlock layout");
+
+struct BuildArgs {
+    LinkGrid link[LSDF_MAX_LINKS];
+    int32_t halfw[LSDF_MAX_LINKS];   // m_i
+    double lo[3];
+    double r;
+    int32_t n[3];
+    int32_t C, L;
+    const float* link_T;
+    LinkBlock* blocks;               // [C][L]
+    float* rs;                       // [C][n_z][n_y][n_x]
+};
+
+__global__ __launch_bounds__(kBlock) void align_kernel(BuildArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)a.C * a.L) return;
+    const int i = (int)(t % a.L);
+    const LinkGrid& lg = a.link[i];
+    const float* T = a.link_T + t * 12;
+    LinkBlock b{};
+    // Eq. 1-2: T_O = t - lo, k = round(T_O / r) - m
+    const float tr[3] = {T[3], T[7], T[11]};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) b.k[ax] = (int32_t)rint(((double)tr[ax] - a.lo[ax]) / a.r) - a.halfw[i];
+    // the plain query's world-to-grid map of this pose (the transformation
+    // of Eq. 4 with the grid scaling folded in)
+    b.gm = lsdf::grid_map(lg, T);
+    a.blocks[t] = b;
+}
+
+template <bool CUBIC, int DT>
+__global__ __launch_bounds__(kBlock) void build_kernel(BuildArgs a, const typename GridT<DT>::T* __restrict__ grid) {
+    const int64_t V = (int64_t)a.n[0] * a.n[1] * a.n[2];
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= V * a.C) return;
+    const int c = (int)(g / V);
+    const int64_t v = g - (int64_t)c * V;
+    const int vx = (int)(v % a.n[0]);
+    const int vy = (int)((v / a.n[0]) % a.n[1]);
+    const int vz = (int)(v / ((int64_t)a.n[0] * a.n[1]));
+    const float x = (float)(a.lo[0] + ((double)vx + 0.5) * a.r);
+    const float y = (float)(a.lo[1] + ((double)vy + 0.5) * a.r);
+    const float z = (float)(a.lo[2] + ((double)vz + 0.5) * a.r);
+    const LinkBlock* bl = a.blocks + (int64_t)c * a.L;
+    float best = INFINITY;
+    for (int i = 0; i < a.L; ++i) {
+        const LinkBlock& b = bl[i];
+        const int w = 2 * a.halfw[i];
+        // only the links whose aligned block covers this voxel
+        if (vx < b.k[0] || vx >= b.k[0] + w || vy < b.k[1] || vy >= b.k[1] + w || vz < b.k[2] || vz >= b.k[2] + w)
+            continue;
+        const LinkGrid& lg = a.link[i];
+        best = fminf(best, lsdf::sample_or_inf<CUBIC, DT>(grid + lg.offset, lg, b.gm, x, y, z));
+    }
+    a.rs[g] = best;
+}
+
+struct RuntimeArgs {
+    double lo[3];
+    double r;
+    int32_t n[3];
+    int32_t C;
+    const float* points;
+    int64_t M;
+    uint32_t* bitmap;    // [ceil(V / 32)]
+    uint32_t* count;     // distinct occupied voxels
+    uint32_t* list;      // [min(M, V)]
+    int64_t bitmap_words;
+    const float* rs;
+    float* out_dist;
+};
+
+__global__ __launch_bounds__(kBlock) void runtime_zero_kernel(RuntimeArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < a.bitmap_words) a.bitmap[t] = 0u;
+    if (t == 0) *a.count = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void voxelise_kernel(RuntimeArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= a.M) return;
+    int64_t q[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const double u = floor(((double)a.points[3 * j + ax] - a.lo[ax]) / a.r);
+        if (!(u >= 0.0 && u < (double)a.n[ax])) return;   // outside the environment
+        q[ax] = (int64_t)u;
+    }
+    const int64_t v = (q[2] * a.n[1] + q[1]) * (int64_t)a.n[0] + q[0];
+    const uint32_t bit = 1u << (v & 31);
+    const uint32_t old = atomicOr(&a.bitmap[v >> 5], bit);
+    if (!(old & bit)) a.list[atomicAdd(a.count, 1u)] = (uint32_t)v;   // first point of this voxel
+}
+
+// One workgroup per configuration: the minimum of its Robot SDF over the
+// occupied voxels.
+__global__ __launch_bounds__(kBlock) void gather_kernel(RuntimeArgs a) {
+    const int c = blockIdx.x;
+    const int64_t V = (int64_t)a.n[0] * a.n[1] * a.n[2];
+    const float* rs = a.rs + (int64_t)c * V;
+    const uint32_t cnt = *a.count;
+    float best = INFINITY;
+    for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) best = fminf(best, rs[a.list[k]]);
+    // workgroup minimum
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) best = fminf(best, __shfl_xor(best, off));
+    __shared__ float wmin[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = wmin[0];
+        for (int w = 1; w < kBlock / 64; ++w) m = fminf(m, wmin[w]);
+        a.out_dist[c] = m;
+    }
+}
+
+int check_env(const char* who, const lsdf_env* env, int64_t* V) {
+    using lsdf::fail;
+    if (!env) return fail(LSDF_E_INVALID_ARG, "%s: env is NULL", who);
+    if (!lsdf::finite3(env->lo) || !std::isfinite(env->voxel) || !(env->voxel > 0.0f))
+        return fail(LSDF_E_INVALID_ARG, "%s: env needs a finite corner and a positive voxel edge", who);
+    for (int a = 0; a < 3; ++a)
+        if (env->n[a] < 1 || env->n[a] > 4096)
+            return fail(LSDF_E_SHAPE, "%s: env n[%d] = %d out of [1, 4096]", who, a, (int)env->n[a]);
+    *V = (int64_t)env->n[0] * env->n[1] * env->n[2];
+    if (*V > ((int64_t)1 << 32)) return fail(LSDF_E_SHAPE, "%s: more than 2^32 voxels", who);
+    return LSDF_OK;
+}
+
+size_t blocks_bytes(int64_t C, int64_t L) { return ((size_t)(C * L) * sizeof(LinkBlock) + 255) / 256 * 256; }
+
+}  // namespace
+
+LSDF_API int lsdf_robot_sdf_size(int32_t C, const lsdf_env* env, size_t* bytes) {
+    using namespace lsdf;
+    clear_error();
+    int64_t V = 0;
+    int rc = check_env("robot_sdf_size", env, &V);
+    if (rc != LSDF_OK) return rc;
+    if (C < 0) return fail(LSDF_E_SHAPE, "robot_sdf_size: C < 0");
+    if (!bytes) return fail(LSDF_E_INVALID_ARG, "robot_sdf_size: bytes is NULL");
+    *bytes = (size_t)C * (size_t)V * 4;
+    return LSDF_OK;
+}
+
+LSDF_API int lsdf_robot_sdf_build_workspace_size(int32_t C, int32_t L, size_t* bytes) {
+    using namespace lsdf;
+    clear_error();
+    if (C < 0 || L < 1 || L > LSDF_MAX_LINKS) return fail(LSDF_E_SHAPE, "robot_sdf_build_workspace_size: bad C or L");
+    if (!bytes) return fail(LSDF_E_INVALID_ARG, "robot_sdf_build_workspace_size: bytes is NULL");
+    *bytes = blocks_bytes(C, L);
+    return LSDF_OK;
+}
+
+LSDF_API int lsdf_robot_sdf_build(const float* link_T, int32_t C, int32_t L, const lsdf_grid* grids,
+                                  const void* grid_buf, const lsdf_env* env, float* robot_sdf, void* workspace,
+                                  size_t ws_bytes, void* stream) {
+    using namespace lsdf;
+    clear_error();
+    int64_t V = 0;
+    int rc = check_env("robot_sdf_build", env, &V);
+    if (rc != LSDF_OK) return rc;
+    if (C < 0) return fail(LSDF_E_SHAPE, "robot_sdf_build: C < 0");
+    if (L < 1 || L > LSDF_MAX_LINKS) return fail(LSDF_E_SHAPE, "robot_sdf_build: L = %d out of [1, %d]", (int)L, LSDF_MAX_LINKS);
+    if (!grids) return fail(LSDF_E_INVALID_ARG, "robot_sdf_build: grids is NULL");
+    if (C == 0) return LSDF_OK;
+    if (!link_T || !grid_buf || !robot_sdf || !workspace)
+        return fail(LSDF_E_INVALID_ARG, "robot_sdf_build: NULL device pointer");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(LSDF_E_INVALID_ARG, "robot_sdf_build: workspace is not 256-byte aligned");
+    if (ws_bytes < blocks_bytes(C, L))
+        return fail(LSDF_E_SHAPE, "robot_sdf_build: workspace has %zu bytes, needs %zu", ws_bytes, blocks_bytes(C, L));
+    BuildArgs a{};
+    bool cubic = true;
+    const int dtype = grids[0].dtype;
+    for (int i = 0; i < L; ++i) {
+        rc = prepare_link_grid(grids[i], i, &a.link[i]);
+        if (rc != LSDF_OK) return rc;
+        if (grids[i].dtype != dtype) return fail(LSDF_E_UNSUPPORTED, "robot_sdf_build: grids must share a dtype");
+        cubic = cubic && a.link[i].cubic;
+        // block half-width: farthest box corner from the link origin, in
+        // voxels, rounded up, plus two
+        double far2 = 0.0;
+        for (int k = 0; k < 8; ++k) {
+            double s = 0.0;
+            for (int ax = 0; ax < 3; ++ax) {
+                const double cc = (k >> ax) & 1 ? grids[i].hi[ax] : grids[i].lo[ax];
+                s += cc * cc;
+            }
+            far2 = std::max(far2, s);
+        }
+        const double hw = std::ceil(std::sqrt(far2) / (double)env->voxel) + 2.0;
+        if (hw > 65536.0) return fail(LSDF_E_SHAPE, "robot_sdf_build: link %d's block is too wide", i);
+        a.halfw[i] = (int32_t)hw;
+    }
+    for (int ax = 0; ax < 3; ++ax) {
+        a.lo[ax] = env->lo[ax];
+        a.n[ax] = env->n[ax];
+    }
+    a.r = env->voxel;
+    a.C = C;
+    a.L = L;
+    a.link_T = link_T;
+    a.blocks = static_cast<LinkBlock*>(workspace);
+    a.rs = robot_sdf;
+    hipStream_t s = as_stream(stream);
+    const int64_t CL = (int64_t)C * L;
+    hipLaunchKernelGGL(align_kernel, dim3((unsigned)((CL + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
+    if ((rc = check_launch("robot_sdf_build (align)")) != LSDF_OK) return rc;
+    const int64_t total = V * C;
+    if ((total + kBlock - 1) / kBlock > 0x7fffffffLL) return fail(LSDF_E_SHAPE, "robot_sdf_build: too many voxels");
+    const dim3 gd((unsigned)((total + kBlock - 1) / kBlock)), bd(kBlock);
+    switch (dtype * 2 + (cubic ? 1 : 0)) {
+        case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((build_kernel<true, LSDF_F32>), gd, bd, 0, s, a, static_cast<const float*>(grid_buf)); break;
+        case LSDF_F32 * 2: hipLaunchKernelGGL((build_kernel<false, LSDF_F32>), gd, bd, 0, s, a, static_cast<const float*>(grid_buf)); break;
+        case LSDF_BF16 * 2 + 1: hipLaunchKernelGGL((build_kernel<true, LSDF_BF16>), gd, bd, 0, s, a, static_cast<const uint16_t*>(grid_buf)); break;
+        case LSDF_BF16 * 2: hipLaunchKernelGGL((build_kernel<false, LSDF_BF16>), gd, bd, 0, s, a, static_cast<const uint16_t*>(grid_buf)); break;
+        case LSDF_F16 * 2 + 1: hipLaunchKernelGGL((build_kernel<true, LSDF_F16>), gd, bd, 0, s, a, static_cast<const _Float16*>(grid_buf)); break;
+        default: hipLaunchKernelGGL((build_kernel<false, LSDF_F16>), gd, bd, 0, s, a, static_cast<const _Float16*>(grid_buf)); break;
+    }
+    return check_launch("robot_sdf_build");
+}
+
+namespace {
+
+size_t words256(int64_t words) { return ((size_t)words * 4 + 255) / 256 * 256; }
+
+void runtime_layout(int64_t V, int64_t M, int64_t* bitmap_words, size_t* list_off, size_t* total) {
+    *bitmap_words = (V + 31) / 32;
+    const size_t count_off = words256(*bitmap_words);
+    *list_off = count_off + 256;
+    *total = *list_off + words256(std::min<int64_t>(M, V));
+}
+
+}  // namespace
+
+LSDF_API int lsdf_robot_sdf_query_workspace_size(const lsdf_env* env, int64_t M, size_t* bytes) {
+    using namespace lsdf;
+    clear_error();
+    int64_t V = 0;
+    int rc = check_env("robot_sdf_query_workspace_size", env, &V);
+    if (rc != LSDF_OK) return rc;
+    if (M < 0) return fail(LSDF_E_SHAPE, "robot_sdf_query_workspace_size: M < 0");
+    if (!bytes) return fail(LSDF_E_INVALID_ARG, "robot_sdf_query_workspace_size: bytes is NULL");
+    int64_t bw = 0;
+    size_t lo = 0;
+    runtime_layout(V, M, &bw, &lo, bytes);
+    return LSDF_OK;
+}
+
+LSDF_API int lsdf_robot_sdf_query(const float* robot_sdf, int32_t C, const lsdf_env* env, const float* points,
+                                  int64_t M, float* out_dist, void* workspace, size_t ws_bytes, void* stream) {
+    using namespace lsdf;
+    clear_error();
+    int64_t V = 0;
+    int rc = check_env("robot_sdf_query", env, &V);
+    if (rc != LSDF_OK) return rc;
+    if (C < 0 || M < 0 || M > LSDF_MAX_POINTS) return fail(LSDF_E_SHAPE, "robot_sdf_query: size out of range");
+    if (C == 0) return LSDF_OK;
+    if (!robot_sdf || !out_dist || !workspace || (M > 0 && !points))
+        return fail(LSDF_E_INVALID_ARG, "robot_sdf_query: NULL device pointer");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(LSDF_E_INVALID_ARG, "robot_sdf_query: workspace is not 256-byte aligned");
+    RuntimeArgs a{};
+    size_t list_off = 0, need = 0;
+    runtime_layout(V, M, &a.bitmap_words, &list_off, &need);
+    if (ws_bytes < need) return fail(LSDF_E_SHAPE, "robot_sdf_query: workspace has %zu bytes, needs %zu", ws_bytes, need);
+    for (int ax = 0; ax < 3; ++ax) {
+        a.lo[ax] = env->lo[ax];
+        a.n[ax] = env->n[ax];
+    }
+    a.r = env->voxel;
+    a.C = C;
+    a.points = points;
+    a.M = M;
+    char* ws = static_cast<char*>(workspace);
+    a.bitmap = reinterpret_cast<uint32_t*>(ws);
+    a.count = reinterpret_cast<uint32_t*>(ws + words256(a.bitmap_words));
+    a.list = reinterpret_cast<uint32_t*>(ws + list_off);
+    a.rs = robot_sdf;
+    a.out_dist = out_dist;
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(runtime_zero_kernel, dim3((unsigned)((a.bitmap_words + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       a);
+    if ((rc = check_launch("robot_sdf_query (zero)")) != LSDF_OK) return rc;
+    if (M > 0) {
+        hipLaunchKernelGGL(voxelise_kernel, dim3((unsigned)((M + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
+        if ((rc = check_launch("robot_sdf_query (voxelise)")) != LSDF_OK) return rc;
+    }
+    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)C), dim3(kBlock), 0, s, a);
+    return check_launch("robot_sdf_query (gather)");
+}

@@ -44,11 +44,32 @@ class lsdf_mlp_domain(ct.Structure):
     _fields_ = [("centre", ct.c_float * 3), ("half", ct.c_float * 3)]
 
 
+LSDF_SCHED_DEFAULT, LSDF_SCHED_XCD_SLICES, LSDF_SCHED_INTERLEAVED = 0, 1, 2
+
+
 class lsdf_query_tuning(ct.Structure):
-    _fields_ = [("chunk_points", ct.c_int32), ("blocks_per_cu", ct.c_int32)]
+    _fields_ = [("chunk_points", ct.c_int32), ("blocks_per_cu", ct.c_int32), ("schedule", ct.c_int32),
+                ("reserved", ct.c_int32)]
 
     def __repr__(self):
-        return f"lsdf_query_tuning(chunk_points={self.chunk_points}, blocks_per_cu={self.blocks_per_cu})"
+        return (f"lsdf_query_tuning(chunk_points={self.chunk_points}, blocks_per_cu={self.blocks_per_cu}, "
+                f"schedule={self.schedule})")
+
+    def as_tuple(self):
+        return (self.chunk_points, self.blocks_per_cu, self.schedule)
+
+
+class lsdf_env(ct.Structure):
+    _fields_ = [("lo", ct.c_float * 3), ("voxel", ct.c_float), ("n", ct.c_int32 * 3)]
+
+
+def make_env(lo, voxel, n) -> lsdf_env:
+    e = lsdf_env()
+    for a in range(3):
+        e.lo[a] = float(lo[a])
+        e.n[a] = int(n[a])
+    e.voxel = float(voxel)
+    return e
 
 
 class lsdf_dh(ct.Structure):
@@ -88,9 +109,23 @@ def load_library():
     lib.lsdf_query_min_distance_batched.restype = ct.c_int
     lib.lsdf_query_min_distance_batched.argtypes = [i32, vp, vp, vp, i32, i32, ct.POINTER(lsdf_grid), vp, vp, i64,
                                                     vp, vp, vp, tun, u32, vp, sz, vp]
+    lib.lsdf_query_from_joints.restype = ct.c_int
+    lib.lsdf_query_from_joints.argtypes = [ct.POINTER(lsdf_dh), i32, ct.POINTER(ct.c_float), vp, i32, vp, vp, i32,
+                                           ct.POINTER(lsdf_grid), vp, vp, i64, vp, vp, vp, vp, tun, u32, vp, sz, vp]
     lib.lsdf_query_autotune.restype = ct.c_int
     lib.lsdf_query_autotune.argtypes = [i32, vp, vp, vp, i32, i32, ct.POINTER(lsdf_grid), vp, vp, i64, vp, vp,
                                         tun, i32, i32, vp, sz, vp, tun, ct.POINTER(ct.c_float)]
+    env = ct.POINTER(lsdf_env)
+    lib.lsdf_robot_sdf_size.restype = ct.c_int
+    lib.lsdf_robot_sdf_size.argtypes = [i32, env, ct.POINTER(sz)]
+    lib.lsdf_robot_sdf_build_workspace_size.restype = ct.c_int
+    lib.lsdf_robot_sdf_build_workspace_size.argtypes = [i32, i32, ct.POINTER(sz)]
+    lib.lsdf_robot_sdf_build.restype = ct.c_int
+    lib.lsdf_robot_sdf_build.argtypes = [vp, i32, i32, ct.POINTER(lsdf_grid), vp, env, vp, vp, sz, vp]
+    lib.lsdf_robot_sdf_query_workspace_size.restype = ct.c_int
+    lib.lsdf_robot_sdf_query_workspace_size.argtypes = [env, i64, ct.POINTER(sz)]
+    lib.lsdf_robot_sdf_query.restype = ct.c_int
+    lib.lsdf_robot_sdf_query.argtypes = [vp, i32, env, vp, i64, vp, vp, sz, vp]
     lib.lsdf_build_link_sdf.restype = ct.c_int
     lib.lsdf_build_link_sdf.argtypes = [vp, i32, vp, i32, ct.POINTER(ct.c_int32), i32, ct.POINTER(lsdf_grid),
                                         vp, vp]
@@ -248,14 +283,15 @@ def _cached_workspace(need: int, device) -> torch.Tensor:
     key = (dev.type, dev.index if dev.index is not None else torch.cuda.current_device())
     ws = _workspaces.get(key)
     if ws is None or ws.numel() < need:
-        ws = torch.zeros(max(need, 1 << 16), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(need, 1 << 16), dtype=torch.uint8, device=dev)
         _workspaces[key] = ws
     return ws
 
 
 def query_workspace(C: int, L: int, M: int, device, K: int = 1) -> torch.Tensor:
-    """A zero-filled workspace, cached per device and kept for reuse (every
-    call leaves it zero-filled again)."""
+    """A query workspace, cached per device and reused by every call that
+    passes none (calls on one device share it, so they must not overlap in
+    time: same stream is fine)."""
     return _cached_workspace(query_batched_workspace_size(K, C, L, M), device)
 
 
@@ -290,8 +326,8 @@ def _query_outputs(out, C, L, dev, link_dist):
     return dist, link, ld
 
 
-def make_tuning(chunk_points: int = 0, blocks_per_cu: int = 0) -> lsdf_query_tuning:
-    return lsdf_query_tuning(int(chunk_points), int(blocks_per_cu))
+def make_tuning(chunk_points: int = 0, blocks_per_cu: int = 0, schedule: int = 0) -> lsdf_query_tuning:
+    return lsdf_query_tuning(int(chunk_points), int(blocks_per_cu), int(schedule), 0)
 
 
 def query_min_distance(link_T: torch.Tensor, grids: GridSet, points: torch.Tensor, *,
@@ -346,6 +382,60 @@ def query_min_distance_batched(link_T: torch.Tensor, grids: GridSet, points: tor
     return (dist, link, ld) if link_dist else (dist, link)
 
 
+def _dh_rows(dh):
+    dh = np.asarray(dh, dtype=np.float64).reshape(-1, 4)
+    return (lsdf_dh * dh.shape[0])(*[lsdf_dh(*map(float, r)) for r in dh]), dh.shape[0]
+
+
+def _base_ptr(base_T):
+    if base_T is None:
+        return None, None
+    b = np.ascontiguousarray(np.asarray(base_T, dtype=np.float32).reshape(12))
+    return b, b.ctypes.data_as(ct.POINTER(ct.c_float))
+
+
+def query_from_joints(dh, q: torch.Tensor, grids: GridSet, points: torch.Tensor, *, base_T=None,
+                      c_offsets: torch.Tensor | None = None, m_offsets: torch.Tensor | None = None,
+                      link_T: torch.Tensor | None = None, link_dist: bool = False, tuning=None,
+                      workspace: torch.Tensor | None = None, out=None, stream=None):
+    """Kinematics and clearance in one call (lsdf_query_from_joints): joint
+    angles q [C][dof] in, (dist [C], link [C][, link_dist [C][L]]) out; the
+    poses go to ``link_T`` [C][dof+1][3][4] when given.  With c_offsets /
+    m_offsets (device, [K+1]) it is the batched query."""
+    lib = load_library()
+    rows, dof = _dh_rows(dh)
+    if q.dim() != 2 or q.shape[1] != dof:
+        raise ValueError(f"q must be [C][{dof}]")
+    _require(q, "q", torch.float32)
+    C, L, dev = int(q.shape[0]), dof + 1, q.device
+    if grids.L != L:
+        raise ValueError(f"grids has {grids.L} links, the arm has {L} frames")
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be [M][3]")
+    _require(points, "points", torch.float32)
+    M = int(points.shape[0])
+    if grids.buf.device != dev or points.device != dev:
+        raise ValueError("q, grids and points must be on one device")
+    if (c_offsets is None) != (m_offsets is None):
+        raise ValueError("give both offset arrays or neither")
+    K = 1 if c_offsets is None else _offsets(c_offsets, m_offsets, dev)
+    if link_T is not None:
+        _require(link_T, "link_T", torch.float32, (C, L, 3, 4))
+    dist, link, ld = _query_outputs(out, C, L, dev, link_dist)
+    if workspace is None:
+        workspace = query_workspace(C, L, M, dev, K=K)
+    _require(workspace, "workspace", torch.uint8)
+    b, base_p = _base_ptr(base_T)
+    tun = ct.byref(tuning) if tuning is not None else None
+    _check(lib.lsdf_query_from_joints(
+        rows, dof, base_p, q.data_ptr(), K, c_offsets.data_ptr() if c_offsets is not None else None,
+        m_offsets.data_ptr() if m_offsets is not None else None, C, grids.desc, grids.buf.data_ptr(),
+        points.data_ptr() if M > 0 else None, M, link_T.data_ptr() if link_T is not None else None,
+        dist.data_ptr(), link.data_ptr(), ld.data_ptr() if ld is not None else None, tun, 0,
+        workspace.data_ptr(), workspace.numel(), _stream_handle(stream, dev)))
+    return (dist, link, ld) if link_dist else (dist, link)
+
+
 def query_autotune(link_T: torch.Tensor, grids: GridSet, points: torch.Tensor, c_offsets: torch.Tensor,
                    m_offsets: torch.Tensor, *, candidates=None, reps: int = 5, workspace=None, stream=None):
     """Times the batched query under each candidate tiling
@@ -369,6 +459,52 @@ def query_autotune(link_T: torch.Tensor, grids: GridSet, points: torch.Tensor, c
         points.data_ptr() if M > 0 else None, M, dist.data_ptr(), link.data_ptr(), arr, n, reps,
         workspace.data_ptr(), workspace.numel(), _stream_handle(stream, dev), ct.byref(best), ct.byref(ms)))
     return best, float(ms.value), (dist, link)
+
+
+def robot_sdf_build(link_T: torch.Tensor, grids: GridSet, env: lsdf_env, out: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """The paper's Robot SDFs [C][n_z][n_y][n_x] float32 (lsdf_robot_sdf_build)."""
+    lib = load_library()
+    if link_T.dim() != 4 or tuple(link_T.shape[2:]) != (3, 4):
+        raise ValueError("link_T must be [C][L][3][4]")
+    _require(link_T, "link_T", torch.float32)
+    C, L, dev = int(link_T.shape[0]), int(link_T.shape[1]), link_T.device
+    if L != grids.L:
+        raise ValueError(f"link_T has {L} links, grids has {grids.L}")
+    shape = (C, int(env.n[2]), int(env.n[1]), int(env.n[0]))
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=dev)
+    _require(out, "robot_sdf", torch.float32, shape)
+    n = ct.c_size_t(0)
+    _check(lib.lsdf_robot_sdf_build_workspace_size(C, L, ct.byref(n)))
+    ws = _cached_workspace(int(n.value), dev)
+    _check(lib.lsdf_robot_sdf_build(link_T.data_ptr(), C, L, grids.desc, grids.buf.data_ptr(), ct.byref(env),
+                                    out.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream, dev)))
+    return out
+
+
+def robot_sdf_query(robot_sdf: torch.Tensor, env: lsdf_env, points: torch.Tensor, out: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+    """Per configuration, the minimum of its Robot SDF over the voxels the
+    points occupy (lsdf_robot_sdf_query)."""
+    lib = load_library()
+    _require(robot_sdf, "robot_sdf", torch.float32)
+    C, dev = int(robot_sdf.shape[0]), robot_sdf.device
+    if tuple(robot_sdf.shape[1:]) != (int(env.n[2]), int(env.n[1]), int(env.n[0])):
+        raise ValueError("robot_sdf does not match the environment")
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be [M][3]")
+    _require(points, "points", torch.float32)
+    M = int(points.shape[0])
+    if out is None:
+        out = torch.empty(C, dtype=torch.float32, device=dev)
+    _require(out, "out_dist", torch.float32, (C,))
+    n = ct.c_size_t(0)
+    _check(lib.lsdf_robot_sdf_query_workspace_size(ct.byref(env), M, ct.byref(n)))
+    ws = _cached_workspace(int(n.value), dev)
+    _check(lib.lsdf_robot_sdf_query(robot_sdf.data_ptr(), C, ct.byref(env), points.data_ptr() if M > 0 else None, M,
+                                    out.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream, dev)))
+    return out
 
 
 def build_link_sdf(verts: torch.Tensor, tris: torch.Tensor, comp_first, grids: GridSet, index: int, stream=None):

@@ -27,9 +27,12 @@ class StepGraph:
     """
 
     def __init__(self, dh, base_T, grids: lsdf.GridSet, C_cap: int, M_cap: int, K_cap: int, *, tuning=None,
-                 link_dist: bool = False, device="cuda"):
+                 link_dist: bool = False, fused: bool = True, device="cuda"):
+        """fused: kinematics inside the query's first kernel
+        (lsdf_query_from_joints, one launch fewer) instead of lsdf_fk_batch
+        followed by the batched query; both give the same bits."""
         dev = torch.device(device)
-        self.dh, self.base_T, self.grids, self.tuning = dh, base_T, grids, tuning
+        self.dh, self.base_T, self.grids, self.tuning, self.fused = dh, base_T, grids, tuning, fused
         self.dof = len(dh)
         self.C_cap, self.M_cap, self.K_cap = int(C_cap), int(M_cap), int(K_cap)
         L = grids.L
@@ -57,6 +60,12 @@ class StepGraph:
             self._step()
 
     def _step(self):
+        if self.fused:
+            lsdf.query_from_joints(self.dh, self.q, self.grids, self.points, base_T=self.base_T,
+                                   c_offsets=self.c_off, m_offsets=self.m_off, link_T=self.link_T,
+                                   link_dist=self.link_dist is not None, tuning=self.tuning,
+                                   workspace=self.workspace, out=(self.dist, self.link, self.link_dist))
+            return
         lsdf.fk_batch(self.dh, self.q, self.base_T, out=self.link_T)
         lsdf.query_min_distance_batched(self.link_T, self.grids, self.points, self.c_off, self.m_off,
                                         link_dist=self.link_dist is not None, tuning=self.tuning,

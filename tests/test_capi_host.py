@@ -174,9 +174,12 @@ def test_batched_query_argument_errors(lib):
     assert q(m_off=None) == B.LSDF_E_INVALID_ARG
     assert q(flags=4) == B.LSDF_E_UNSUPPORTED
     assert q(M=(1 << 34) + 1) == B.LSDF_E_SHAPE
-    for bad in [(12, 0), (4, 0), (8200, 0), (0, 17), (0, -1)]:
+    for bad in [(12, 0), (4, 0), (8200, 0), (0, 17), (0, -1), (0, 0, 3), (0, 0, -1)]:
         assert q(tuning=ct.byref(B.make_tuning(*bad))) == B.LSDF_E_INVALID_ARG, bad
-    assert b"chunk_points" in lib.lsdf_last_error() or b"blocks_per_cu" in lib.lsdf_last_error()
+    assert b"schedule" in lib.lsdf_last_error()
+    t = B.make_tuning(32, 8, 1)
+    t.reserved = 5
+    assert q(tuning=ct.byref(t)) == B.LSDF_E_INVALID_ARG
     # the plan of K trajectories lives in the workspace: K = 3 fits where K = 60000 does not
     n = ct.c_size_t(0)
     assert lib.lsdf_query_batched_workspace_size(3, 4, 2, 10, ct.byref(n)) == 0
@@ -217,3 +220,46 @@ def test_set_kernel_events_arguments(lib):
     assert lib.lsdf_set_kernel_events(FAKE, None) == B.LSDF_E_INVALID_ARG
     assert lib.lsdf_set_kernel_events(None, FAKE) == B.LSDF_E_INVALID_ARG
     assert lib.lsdf_set_kernel_events(None, None) == B.LSDF_OK
+
+
+def test_query_from_joints_argument_errors(lib):
+    from paper_2309_12543_amd import lsdf as B
+    rows = (B.lsdf_dh * 6)()
+    g = grid_array(7)
+
+    def f(dh=rows, dof=6, q=FAKE, K=1, co=None, mo=None, C=4, M=10):
+        return lib.lsdf_query_from_joints(dh, dof, None, q, K, co, mo, C, g, FAKE, FAKE, M, None, FAKE, FAKE, None,
+                                          None, 0, FAKE, 1 << 20, None)
+    assert f(dh=None) == B.LSDF_E_INVALID_ARG
+    assert f(dof=0) == B.LSDF_E_SHAPE
+    assert f(dof=16) == B.LSDF_E_SHAPE
+    assert f(co=FAKE) == B.LSDF_E_INVALID_ARG          # one offset array without the other
+    assert f(K=2) == B.LSDF_E_SHAPE                    # K > 1 needs offset arrays
+    assert f(q=None) == B.LSDF_E_INVALID_ARG
+    assert f(C=0) == B.LSDF_OK
+
+
+def test_robot_sdf_argument_errors(lib):
+    from paper_2309_12543_amd import lsdf as B
+    env = B.make_env((-2, -2, -2), 1 / 32, (128, 128, 128))
+    n = ct.c_size_t(0)
+    assert lib.lsdf_robot_sdf_size(500, ct.byref(env), ct.byref(n)) == 0 and n.value == 500 * 128 ** 3 * 4
+    bad = B.make_env((-2, -2, -2), 0.0, (128, 128, 128))
+    assert lib.lsdf_robot_sdf_size(5, ct.byref(bad), ct.byref(n)) == B.LSDF_E_INVALID_ARG
+    bad = B.make_env((-2, float("nan"), -2), 0.1, (8, 8, 8))
+    assert lib.lsdf_robot_sdf_size(5, ct.byref(bad), ct.byref(n)) == B.LSDF_E_INVALID_ARG
+    bad = B.make_env((-2, -2, -2), 0.1, (8, 0, 8))
+    assert lib.lsdf_robot_sdf_size(5, ct.byref(bad), ct.byref(n)) == B.LSDF_E_SHAPE
+    assert lib.lsdf_robot_sdf_size(5, None, ct.byref(n)) == B.LSDF_E_INVALID_ARG
+    g = grid_array(2)
+    assert lib.lsdf_robot_sdf_build_workspace_size(4, 2, ct.byref(n)) == 0
+    assert lib.lsdf_robot_sdf_build(FAKE, 4, 2, g, FAKE, ct.byref(env), FAKE, FAKE, 16, None) == B.LSDF_E_SHAPE
+    assert lib.lsdf_robot_sdf_build(FAKE, 4, 2, None, FAKE, ct.byref(env), FAKE, FAKE, n.value, None) \
+        == B.LSDF_E_INVALID_ARG
+    assert lib.lsdf_robot_sdf_build(FAKE, 4, 17, g, FAKE, ct.byref(env), FAKE, FAKE, n.value, None) == B.LSDF_E_SHAPE
+    assert lib.lsdf_robot_sdf_build(FAKE, 0, 2, g, FAKE, ct.byref(env), FAKE, FAKE, n.value, None) == B.LSDF_OK
+    assert lib.lsdf_robot_sdf_query_workspace_size(ct.byref(env), 1000, ct.byref(n)) == 0
+    assert lib.lsdf_robot_sdf_query(FAKE, 4, ct.byref(env), FAKE, 1000, FAKE, FAKE, 16, None) == B.LSDF_E_SHAPE
+    assert lib.lsdf_robot_sdf_query(FAKE, 4, ct.byref(env), None, 1000, FAKE, FAKE, n.value, None) \
+        == B.LSDF_E_INVALID_ARG
+    assert lib.lsdf_robot_sdf_query(FAKE, 0, ct.byref(env), FAKE, 1000, FAKE, FAKE, n.value, None) == B.LSDF_OK

@@ -126,13 +126,14 @@ def test_batched_equals_plain_per_trajectory(B, orc, small, tiny_grids):
         assert np.array_equal(l.cpu().numpy(), bl[c0:c1])
 
 
-@pytest.mark.parametrize("chunk,bpc", [(8, 8), (24, 3), (64, 1), (1024, 16), (8192, 2)])
-def test_tiling_does_not_change_bits(B, orc, small, tiny_grids, chunk, bpc):
+@pytest.mark.parametrize("chunk,bpc,sched", [(8, 8, 1), (24, 3, 2), (64, 1, 1), (1024, 16, 2), (8192, 2, 1),
+                                             (40, 8, 2)])
+def test_tiling_does_not_change_bits(B, orc, small, tiny_grids, chunk, bpc, sched):
     T32 = poses32(orc, small)
     pts = small.points.astype(np.float32)
     gs = upload_grids(B, small, tiny_grids)
     ref = gpu_batched(B, T32, gs, pts, small.c_off, small.m_off)
-    got = gpu_batched(B, T32, gs, pts, small.c_off, small.m_off, tuning=B.make_tuning(chunk, bpc))
+    got = gpu_batched(B, T32, gs, pts, small.c_off, small.m_off, tuning=B.make_tuning(chunk, bpc, sched))
     for a, b in zip(got, ref):
         assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
@@ -152,7 +153,8 @@ def test_bad_offsets_are_clamped(B, orc, small, tiny_grids):
     assert_bit_exact(got, ref)
 
 
-def test_step_graph_replays_match_eager(B, orc, small, tiny_grids):
+@pytest.mark.parametrize("fused", [True, False])
+def test_step_graph_replays_match_eager(B, orc, small, tiny_grids, fused):
     """FK + batched query captured once; each replay after loading a new
     batch (fewer trajectories, other sizes) gives the eager step's bits."""
     from paper_2309_12543_amd.step_graph import StepGraph
@@ -160,7 +162,7 @@ def test_step_graph_replays_match_eager(B, orc, small, tiny_grids):
     dh, base = small.robot.dh, small.robot.base_T
     C_cap, M_cap, K_cap = small.C + 7, small.M + 5, small.K + 2
     say(f"capture StepGraph C_cap={C_cap} M_cap={M_cap} K_cap={K_cap}")
-    g = StepGraph(dh, base, gs, C_cap, M_cap, K_cap, link_dist=True)
+    g = StepGraph(dh, base, gs, C_cap, M_cap, K_cap, link_dist=True, fused=fused)
     batches = [(small.c_off, small.m_off, small.C, small.M)]
     # a second batch: the first 4 trajectories with the last one's points trimmed
     c2 = small.c_off[:5].copy()
@@ -189,16 +191,43 @@ def test_step_graph_replays_match_eager(B, orc, small, tiny_grids):
         assert torch.all(torch.isinf(d[C:])) and torch.all(l[C:] == -1)
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_query_from_joints_equals_separate_calls(B, orc, small, tiny_grids, batched):
+    """Kinematics inside the query's first kernel: the poses it stores and
+    the clearances are the bits of lsdf_fk_batch followed by the query."""
+    gs = upload_grids(B, small, tiny_grids)
+    q = to_dev(small.q.astype(np.float32))
+    pts = to_dev(small.points.astype(np.float32))
+    dh, base = small.robot.dh, small.robot.base_T
+    kw = {}
+    if batched:
+        kw = dict(c_offsets=to_dev(small.c_off, torch.int32), m_offsets=to_dev(small.m_off, torch.int64))
+    say(f"query_from_joints batched={batched} C={small.C} M={small.M}")
+    T_ref = B.fk_batch(dh, q, base)
+    if batched:
+        ref = B.query_min_distance_batched(T_ref, gs, pts, kw["c_offsets"], kw["m_offsets"], link_dist=True)
+    else:
+        ref = B.query_min_distance(T_ref, gs, pts, link_dist=True)
+    T_out = torch.full_like(T_ref, float("nan"))
+    got = B.query_from_joints(dh, q, gs, pts, base_T=base, link_T=T_out, link_dist=True, **kw)
+    got2 = B.query_from_joints(dh, q, gs, pts, base_T=base, link_dist=True, **kw)     # no pose output
+    torch.cuda.synchronize()
+    assert torch.equal(T_out.view(torch.int32), T_ref.view(torch.int32))
+    for a, b, c in zip(got, ref, got2):
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+        assert torch.equal(c.view(torch.int32), b.view(torch.int32))
+
+
 def test_autotune_returns_a_candidate(B, orc, small, tiny_grids):
     T32 = poses32(orc, small)
     pts = small.points.astype(np.float32)
     gs = upload_grids(B, small, tiny_grids)
-    cands = [(8, 8), (32, 8), (128, 4)]
+    cands = [(8, 8, 1), (32, 8, 2), (128, 4, 2)]
     say("autotune over 3 candidates")
     best, ms, (d, l) = B.query_autotune(to_dev(T32), gs, to_dev(pts), to_dev(small.c_off, torch.int32),
                                         to_dev(small.m_off, torch.int64), candidates=cands, reps=3)
     torch.cuda.synchronize()
-    assert (best.chunk_points, best.blocks_per_cu) in cands and ms > 0
+    assert best.as_tuple() in cands and ms > 0
     ref = twin_batched(orc, small, T32, tiny_grids, pts, small.c_off, small.m_off)
     assert np.array_equal(d.cpu().numpy().view(np.uint32), ref[0].astype(np.float32).view(np.uint32))
     assert np.array_equal(l.cpu().numpy(), ref[1])

@@ -160,7 +160,10 @@ def test_query_mlp_all_fallback_equals_plain(B, orc, tiny, tiny_grids):
     P = dev(params_f32(7, 3))
     say("query_mlp margin=+inf vs plain")
     d0, l0, ld0 = B.query_min_distance(T, gs, pts, link_dist=True)
-    d1, l1, ld1 = B.query_min_distance_mlp(T, gs, P, (cen, half), pts, margin=float("inf"), link_dist=True)
+    # a workspace full of 0xFF: the learned query clears its keys first
+    ws = torch.full((B.query_workspace_size(tiny.C, 7, tiny.M),), 0xFF, dtype=torch.uint8, device="cuda")
+    d1, l1, ld1 = B.query_min_distance_mlp(T, gs, P, (cen, half), pts, margin=float("inf"), link_dist=True,
+                                           workspace=ws)
     torch.cuda.synchronize()
     assert torch.equal(ld0.view(torch.int32), ld1.view(torch.int32))
     assert torch.equal(d0.view(torch.int32), d1.view(torch.int32)) and torch.equal(l0, l1)

@@ -247,12 +247,13 @@ def test_build_link_sdf_half_storage(B, orc, tiny, tiny_grids, dt):
 
 
 def test_query_workspace_reuse_across_shapes(B, orc, tiny, tiny_grids):
-    """One workspace serving calls of different sizes: every call must leave
-    it all-zero (keys and culling scratch), so that a later call with more
-    configurations reads no stale bytes as keys."""
+    """One workspace serving calls of different sizes, holding random bytes
+    before the first call: a call ignores what the workspace holds (the
+    first kernel clears the keys), so a later call with more configurations
+    reads no stale bytes as keys."""
     gs = upload_grids(B, tiny, tiny_grids)
     rng = np.random.default_rng(34)
-    ws = torch.zeros(B.query_workspace_size(200, 7, 20000), dtype=torch.uint8, device="cuda")
+    ws = torch.randint(0, 256, (B.query_workspace_size(200, 7, 20000),), dtype=torch.uint8, device="cuda")
     for C, M in ((3, 2049), (129, 16385), (7, 300), (200, 20000)):
         q = synth.make_waypoints(tiny.robot.qmin, tiny.robot.qmax, C, 199 + C)
         T32 = orc.fk(tiny.robot.dh, q, tiny.robot.base_T).astype(np.float32)
@@ -261,19 +262,20 @@ def test_query_workspace_reuse_across_shapes(B, orc, tiny, tiny_grids):
         say(f"shared workspace C={C} M={M}")
         d, l, ld = B.query_min_distance(to_dev(T32), gs, to_dev(pts), link_dist=True, workspace=ws)
         torch.cuda.synchronize()
-        assert int(ws.count_nonzero()) == 0
         assert_bit_exact((d.cpu().numpy(), l.cpu().numpy(), ld.cpu().numpy()), twin(orc, tiny, T32, tiny_grids, pts))
 
 
-def test_query_workspace_cleared_and_repeatable(B, orc, tiny, tiny_grids):
+def test_query_workspace_contents_ignored_and_repeatable(B, orc, tiny, tiny_grids):
     T32 = to_dev(orc.fk(tiny.robot.dh, tiny.q, tiny.robot.base_T).astype(np.float32))
     gs = upload_grids(B, tiny, tiny_grids)
     pts = to_dev(tiny.points.astype(np.float32))
-    ws = torch.zeros(B.query_workspace_size(tiny.C, 7, tiny.M), dtype=torch.uint8, device="cuda")
-    say("query repeat x3 with a private workspace")
-    outs = [B.query_min_distance(T32, gs, pts, link_dist=True, workspace=ws) for _ in range(3)]
+    ws = torch.full((B.query_workspace_size(tiny.C, 7, tiny.M),), 0xFF, dtype=torch.uint8, device="cuda")
+    say("query repeat x3 with a private workspace, refilled with 0xFF before each call")
+    outs = []
+    for _ in range(3):
+        outs.append(B.query_min_distance(T32, gs, pts, link_dist=True, workspace=ws))
+        ws.fill_(0xFF)
     torch.cuda.synchronize()
-    assert int(ws.count_nonzero()) == 0
     for d, l, ld in outs[1:]:
         assert torch.equal(d, outs[0][0]) and torch.equal(l, outs[0][1]) and torch.equal(ld, outs[0][2])
     # permuting the cloud changes nothing, bit for bit
