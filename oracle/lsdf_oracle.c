@@ -762,3 +762,107 @@ ORC_EXPORT void orc_robot_sdf_query(const double* rs, int32_t C, const double* e
         }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* The paper's tiny network for the Euclidean grid transformation           */
+/* (Sec. III-B-1, Eq. 4-5): f(R) approximates G = R^T P, the rotated         */
+/* normalised centres of the (2m)^3 voxels of a transformed Link SDF block.  */
+/*   P_j = ((j_x + 1/2) / m - 1, (j_y + 1/2) / m - 1, (j_z + 1/2) / m - 1),  */
+/*   voxel j = (j_z * 2m + j_y) * 2m + j_x, output o = 3 j + a:              */
+/*   target_o = sum_b R[b][a] P_j[b]   (R^T P_j, axis a)                     */
+/* Network: x = R row-major (9 inputs), h = ReLU(W1 x + b1) (32 units),     */
+/* out = W2 h + b2 (3 V outputs, V = (2m)^3).  Parameters, in order:         */
+/* W1[32][9], b1[32], W2[3V][32], b2[3V].  Loss: mean absolute error over    */
+/* the batch and the outputs (the paper trains it with an L1 loss and Adam,  */
+/* Sec. IV-B); subgradient sign(0) = 0, ReLU'(0) = 0.                        */
+/* ------------------------------------------------------------------------ */
+#define ORC_FR_H 32
+
+ORC_EXPORT int64_t orc_frnn_nparam(int32_t m) {
+    const int64_t V = (int64_t)(2 * m) * (2 * m) * (2 * m);
+    return ORC_FR_H * 9 + ORC_FR_H + 3 * V * ORC_FR_H + 3 * V;
+}
+
+/* Exact R^T P for N rotations R [N][9] (row-major): out [N][3V]. */
+ORC_EXPORT void orc_frnn_target(int32_t m, const double* R, int64_t N, double* out) {
+    const int32_t w = 2 * m;
+    const int64_t V = (int64_t)w * w * w;
+    for (int64_t s = 0; s < N; ++s) {
+        const double* r = R + 9 * s;
+        for (int64_t j = 0; j < V; ++j) {
+            const int32_t jx = (int32_t)(j % w), jy = (int32_t)((j / w) % w), jz = (int32_t)(j / ((int64_t)w * w));
+            const double P[3] = {(jx + 0.5) / m - 1.0, (jy + 0.5) / m - 1.0, (jz + 0.5) / m - 1.0};
+            for (int a = 0; a < 3; ++a)
+                out[s * 3 * V + 3 * j + a] = r[0 * 3 + a] * P[0] + r[1 * 3 + a] * P[1] + r[2 * 3 + a] * P[2];
+        }
+    }
+}
+
+ORC_EXPORT void orc_frnn_forward(const double* params, int32_t m, const double* R, int64_t N, double* out) {
+    const int64_t V = (int64_t)(2 * m) * (2 * m) * (2 * m), O = 3 * V;
+    const double* W1 = params;
+    const double* b1 = W1 + ORC_FR_H * 9;
+    const double* W2 = b1 + ORC_FR_H;
+    const double* b2 = W2 + O * ORC_FR_H;
+    for (int64_t s = 0; s < N; ++s) {
+        double h[ORC_FR_H];
+        for (int u = 0; u < ORC_FR_H; ++u) {
+            double z = b1[u];
+            for (int k = 0; k < 9; ++k) z += W1[u * 9 + k] * R[9 * s + k];
+            h[u] = z > 0.0 ? z : 0.0;
+        }
+        for (int64_t o = 0; o < O; ++o) {
+            double y = b2[o];
+            for (int u = 0; u < ORC_FR_H; ++u) y += W2[o * ORC_FR_H + u] * h[u];
+            out[s * O + o] = y;
+        }
+    }
+}
+
+/* Mean absolute error against R^T P over N rotations, and its gradient. */
+ORC_EXPORT double orc_frnn_loss_grad(const double* params, int32_t m, const double* R, int64_t N, double* grad) {
+    const int64_t V = (int64_t)(2 * m) * (2 * m) * (2 * m), O = 3 * V;
+    const int64_t np = orc_frnn_nparam(m);
+    const double* W1 = params;
+    const double* b1 = W1 + ORC_FR_H * 9;
+    const double* W2 = b1 + ORC_FR_H;
+    const double* b2 = W2 + O * ORC_FR_H;
+    double* gW1 = grad;
+    double* gb1 = gW1 + ORC_FR_H * 9;
+    double* gW2 = gb1 + ORC_FR_H;
+    double* gb2 = gW2 + O * ORC_FR_H;
+    memset(grad, 0, sizeof(double) * (size_t)np);
+    double* tgt = (double*)malloc(sizeof(double) * (size_t)O);
+    const double scale = 1.0 / ((double)N * (double)O);
+    double loss = 0.0;
+    for (int64_t s = 0; s < N; ++s) {
+        const double* x = R + 9 * s;
+        orc_frnn_target(m, x, 1, tgt);
+        double z[ORC_FR_H], h[ORC_FR_H], dh[ORC_FR_H];
+        for (int u = 0; u < ORC_FR_H; ++u) {
+            z[u] = b1[u];
+            for (int k = 0; k < 9; ++k) z[u] += W1[u * 9 + k] * x[k];
+            h[u] = z[u] > 0.0 ? z[u] : 0.0;
+            dh[u] = 0.0;
+        }
+        for (int64_t o = 0; o < O; ++o) {
+            double y = b2[o];
+            for (int u = 0; u < ORC_FR_H; ++u) y += W2[o * ORC_FR_H + u] * h[u];
+            const double e = y - tgt[o];
+            loss += fabs(e) * scale;
+            const double g = (e > 0.0 ? 1.0 : (e < 0.0 ? -1.0 : 0.0)) * scale;
+            gb2[o] += g;
+            for (int u = 0; u < ORC_FR_H; ++u) {
+                gW2[o * ORC_FR_H + u] += g * h[u];
+                dh[u] += g * W2[o * ORC_FR_H + u];
+            }
+        }
+        for (int u = 0; u < ORC_FR_H; ++u) {
+            const double dz = z[u] > 0.0 ? dh[u] : 0.0;
+            gb1[u] += dz;
+            for (int k = 0; k < 9; ++k) gW1[u * 9 + k] += dz * x[k];
+        }
+    }
+    free(tgt);
+    return loss;
+}

@@ -82,6 +82,14 @@ def load():
     lib.orc_query_f32_each.restype = None
     lib.orc_query_f32_each.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _fp, _ip, _fp, _lp, _fp, ct.c_int64, _fp,
                                        _fp]
+    lib.orc_frnn_nparam.restype = ct.c_int64
+    lib.orc_frnn_nparam.argtypes = [ct.c_int32]
+    lib.orc_frnn_target.restype = None
+    lib.orc_frnn_target.argtypes = [ct.c_int32, _dp, ct.c_int64, _dp]
+    lib.orc_frnn_forward.restype = None
+    lib.orc_frnn_forward.argtypes = [_dp, ct.c_int32, _dp, ct.c_int64, _dp]
+    lib.orc_frnn_loss_grad.restype = ct.c_double
+    lib.orc_frnn_loss_grad.argtypes = [_dp, ct.c_int32, _dp, ct.c_int64, _dp]
     lib.orc_align.restype = None
     lib.orc_align.argtypes = [_dp, _dp, ct.c_double, ct.c_int32, _lp, _dp]
     lib.orc_robot_sdf_f64.restype = None
@@ -305,6 +313,47 @@ def query_f32_each(T, lo, hi, n, grids, points) -> np.ndarray:
     return each
 
 
+# ---------------------------------------------------------------------------
+# the paper's tiny network for the grid transformation (Sec. III-B-1)
+# ---------------------------------------------------------------------------
+
+FRNN_HIDDEN = 32
+
+
+def frnn_nparam(m: int) -> int:
+    return int(load().orc_frnn_nparam(int(m)))
+
+
+def frnn_target(m: int, R) -> np.ndarray:
+    """Exact R^T P_j for rotations R [N][3][3]: [N][3 V] (o = 3 j + a)."""
+    lib = load()
+    R = _c(np.asarray(R).reshape(-1, 9), np.float64)
+    V = (2 * m) ** 3
+    out = np.empty((R.shape[0], 3 * V), dtype=np.float64)
+    lib.orc_frnn_target(int(m), _ptr(R, _dp), R.shape[0], _ptr(out, _dp))
+    return out
+
+
+def frnn_forward(params, m: int, R) -> np.ndarray:
+    lib = load()
+    P = _c(params, np.float64)
+    R = _c(np.asarray(R).reshape(-1, 9), np.float64)
+    V = (2 * m) ** 3
+    out = np.empty((R.shape[0], 3 * V), dtype=np.float64)
+    lib.orc_frnn_forward(_ptr(P, _dp), int(m), _ptr(R, _dp), R.shape[0], _ptr(out, _dp))
+    return out
+
+
+def frnn_loss_grad(params, m: int, R):
+    """(mean absolute error against R^T P, gradient [nparam])."""
+    lib = load()
+    P = _c(params, np.float64)
+    R = _c(np.asarray(R).reshape(-1, 9), np.float64)
+    g = np.empty(P.shape[0], dtype=np.float64)
+    loss = lib.orc_frnn_loss_grad(_ptr(P, _dp), int(m), _ptr(R, _dp), R.shape[0], _ptr(g, _dp))
+    return float(loss), g
+
+
 def exact_min(T, meshes, points) -> np.ndarray:
     """Grid-free per-link minima [C][L]: exact mesh SDF at every point."""
     lib = load()
@@ -438,6 +487,6 @@ def mlp_unpack(params):
     return out
 
 
-__all__ = ["align", "robot_sdf_f64", "robot_sdf_query", "voxel_centres", "voxel_index", "build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
+__all__ = ["FRNN_HIDDEN", "frnn_forward", "frnn_loss_grad", "frnn_nparam", "frnn_target", "align", "robot_sdf_f64", "robot_sdf_query", "voxel_centres", "voxel_index", "build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
            "query_batched", "query_f32", "query_f32_each", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids",
            "MLP_HIDDEN", "adam_step", "judge_min", "mlp_forward", "mlp_loss_grad", "mlp_nparam", "mlp_unpack"]
