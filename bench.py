@@ -310,6 +310,141 @@ def batched_variant(dev, steps: int, warmup: int):
     }
 
 
+def robot_sdf_variant(dev, steps: int, judge_waypoints: int = 16):
+    """The paper's own pipeline on the same 500 x 20,000 x 7 workload: Robot
+    SDFs of every waypoint over a 4 m environment of 3.125 cm voxels (the
+    preparation), then the gather-only runtime; against the per-point query
+    on time, memory and error (both judged against the double-precision
+    oracle at the points on sampled waypoints)."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_2309_12543_amd import lsdf
+
+    w = synth.make_workload("paper")
+    lo, r, n = (-2.0, -2.0, -2.0), 1.0 / 32.0, (128, 128, 128)
+    env = lsdf.make_env(lo, r, n)
+    log(f"robot-sdf variant: C={w.C} env {n} voxels of {r * 100:.3f} cm")
+    gs = lsdf.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device=dev)
+    q = torch.as_tensor(w.q, dtype=torch.float32, device=dev)
+    pts = torch.as_tensor(w.points, dtype=torch.float32, device=dev)
+    T = lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T)
+    rs = torch.empty((w.C, n[2], n[1], n[0]), dtype=torch.float32, device=dev)
+    build_ms = time_calls(lambda: lsdf.robot_sdf_build(T, gs, env, out=rs), max(3, steps // 10), 1)
+    d_rs = torch.empty(w.C, dtype=torch.float32, device=dev)
+    run_ms = time_calls(lambda: lsdf.robot_sdf_query(rs, env, pts, out=d_rs), steps, 5)
+    d_q, _ = lsdf.query_min_distance(T, gs, pts)
+    torch.cuda.synchronize()
+    sel = np.linspace(0, w.C - 1, judge_waypoints).round().astype(int)
+    grids = oracle_grids(w)
+    T64 = oracle.fk(w.robot.dh, w.q[sel], w.robot.base_T)
+    ref, _ = oracle.reduce(oracle.query_f64(T64, w.grid_lo, w.grid_hi, w.grid_n, grids, w.points))
+    a = d_rs.cpu().numpy().astype(np.float64)[sel]
+    b = d_q.cpu().numpy().astype(np.float64)[sel]
+    ok = np.isfinite(ref) & np.isfinite(a) & np.isfinite(b)
+    e_rs, e_q = np.abs(a[ok] - ref[ok]) * 1e3, np.abs(b[ok] - ref[ok]) * 1e3
+    flat = np.floor((w.points - np.array(lo)) / r).astype(np.int64)
+    occ = len(np.unique((flat[:, 2] * n[1] + flat[:, 1]) * n[0] + flat[:, 0]))
+    out = {
+        "workload": f"paper: {w.C} waypoints x {w.M} points x {w.L} links; environment {n[0]}^3 voxels of "
+                    f"{r * 100:.3f} cm over a 4 m cube",
+        "prep_ms_robot_sdf_build": round(build_ms, 3),
+        "runtime_ms_gather": round(run_ms, 4),
+        "robot_sdf_gb": round(rs.numel() * 4 / 1e9, 3),
+        "occupied_voxels": occ,
+        "judged_waypoints": int(ok.sum()),
+        "max_err_mm_robot_sdf": round(float(e_rs.max()), 3) if e_rs.size else None,
+        "mean_err_mm_robot_sdf": round(float(e_rs.mean()), 3) if e_rs.size else None,
+        "max_err_mm_per_point_query": round(float(e_q.max()), 5) if e_q.size else None,
+        "discretisation_bound_mm": round(0.5 * np.sqrt(3) * r * 1e3, 2),
+    }
+    del rs
+    torch.cuda.empty_cache()
+    return out
+
+
+def random_rotations_dev(n: int, gen, dev):
+    """Uniform random rotations [n][3][3] on the device (unit quaternions)."""
+    import torch
+    q = torch.randn((n, 4), generator=gen, device=dev, dtype=torch.float64)
+    q = q / q.norm(dim=1, keepdim=True)
+    w, x, y, z = q.unbind(1)
+    R = torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)], -1),
+        torch.stack([2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)], -1),
+        torch.stack([2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], -1)], 1)
+    return R.to(torch.float32).contiguous()
+
+
+def frnn_variant(dev, train_steps: int, test_rotations: int):
+    """The paper's tiny network for the grid transformation (Sec. III-B-1):
+    trained on random rotations with the L1 loss and Adam, its maximum error
+    over random rotations, and the Robot SDFs of the 500-waypoint workload
+    built through it against the exact build (time and difference)."""
+    import math
+
+    import torch
+
+    import synth
+    from paper_2309_12543_amd import lsdf
+
+    w = synth.make_workload("paper")
+    lo, r, n = (-2.0, -2.0, -2.0), 1.0 / 32.0, (128, 128, 128)
+    far = max(math.sqrt(max(sum((w.grid_hi[i, a] if (k >> a) & 1 else w.grid_lo[i, a]) ** 2 for a in range(3))
+                            for k in range(8))) for i in range(w.L))
+    m = int(math.ceil(far / r)) + 2
+    npar = lsdf.frnn_nparam(m)
+    log(f"frnn variant: block half-width m={m} ({(2 * m) ** 3} voxels, {npar} parameters), {train_steps} steps")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.BASE_SEED + 7)
+    # uniform +-1/sqrt(fan_in) initialisation of both layers
+    fan = np.concatenate([np.full(32 * 9 + 32, 1 / 3.0), np.full(npar - 32 * 10, 1 / math.sqrt(32.0))])
+    P = ((torch.rand(npar, generator=gen, device=dev, dtype=torch.float32) * 2 - 1) *
+         torch.as_tensor(fan, dtype=torch.float32, device=dev)).contiguous()
+    mm, vv = torch.zeros_like(P), torch.zeros_like(P)
+    grad = torch.empty_like(P)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    lr0, lr1 = 1e-2, 1e-5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(1, train_steps + 1):
+        lr = lr1 + 0.5 * (lr0 - lr1) * (1 + math.cos(math.pi * t / train_steps))
+        lsdf.frnn_train_step(P, m, random_rotations_dev(64, gen, dev), adam=(mm, vv), t=t, lr=lr, grad=grad,
+                             loss=loss)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    Rt = random_rotations_dev(test_rotations, gen, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    err = float(lsdf.frnn_max_error(P, m, Rt).item())
+    eval_s = time.perf_counter() - t0
+    env = lsdf.make_env(lo, r, n)
+    gs = lsdf.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device=dev)
+    q = torch.as_tensor(w.q, dtype=torch.float32, device=dev)
+    T = lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T)
+    Csub = 100
+    rs_exact = lsdf.robot_sdf_build(T[:Csub].contiguous(), gs, env)
+    rs_nn = torch.empty_like(rs_exact)
+    nn_ms = time_calls(lambda: lsdf.robot_sdf_build_frnn(T[:Csub].contiguous(), gs, env, P, m, out=rs_nn), 3, 1)
+    ex_ms = time_calls(lambda: lsdf.robot_sdf_build(T[:Csub].contiguous(), gs, env, out=rs_exact), 3, 1)
+    both = torch.isfinite(rs_exact) & torch.isfinite(rs_nn)
+    diff = float((rs_exact[both] - rs_nn[both]).abs().max().item()) if bool(both.any()) else None
+    mismatch = int((torch.isfinite(rs_exact) != torch.isfinite(rs_nn)).sum().item())
+    del rs_exact, rs_nn
+    torch.cuda.empty_cache()
+    return {
+        "network": f"9-32-{3 * (2 * m) ** 3} ReLU, block half-width {m} voxels of {r * 100:.3f} cm (e_r = {m * r:.3f} m)",
+        "train_steps": train_steps, "batch": 64, "lr": "Adam, cosine 1e-2 -> 1e-5", "train_s": round(train_s, 2),
+        "final_l1": float(loss.item()),
+        "test_rotations": test_rotations, "max_error_normalised": err, "max_error_mm": round(err * m * r * 1e3, 3),
+        "max_error_eval_s": round(eval_s, 2),
+        "robot_sdf_build_ms_100_waypoints": {"network": round(nn_ms, 3), "exact": round(ex_ms, 3)},
+        "robot_sdf_max_abs_diff_mm": round(diff * 1e3, 3) if diff is not None else None,
+        "robot_sdf_finite_pattern_mismatches": mismatch,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,6 +457,11 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--no-precision", action="store_true", help="skip the 128^3 bf16/fp16 storage variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-trajectory batched variant")
+    ap.add_argument("--no-robot-sdf", action="store_true", help="skip the paper's Robot-SDF pipeline comparator")
+    ap.add_argument("--frnn-steps", type=int, default=10000,
+                    help="training steps of the grid-transformation network (0 skips that variant)")
+    ap.add_argument("--frnn-rotations", type=int, default=100000,
+                    help="random rotations of its max-error test (the paper uses 10^7)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB mebibytes (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -462,6 +602,11 @@ def main():
         rec["precision"] = precision_variant(dev, 50)
     if not args.no_batched:
         rec["batched"] = batched_variant(dev, 20, 3)
+    if not args.no_robot_sdf:
+        rec["robot_sdf_pipeline"] = robot_sdf_variant(dev, 50)
+        if args.frnn_steps > 0:
+            rec["robot_sdf_pipeline"]["grid_transformation_network"] = frnn_variant(dev, args.frnn_steps,
+                                                                                    args.frnn_rotations)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)

@@ -57,6 +57,8 @@ extern "C" {
 #define LSDF_MAX_DOF        15
 #define LSDF_MAX_COMPONENTS 16    /* closed parts per link mesh */
 #define LSDF_MAX_TRAJECTORIES 65536          /* trajectories per batched query */
+#define LSDF_FRNN_HIDDEN      32             /* hidden units of the grid-transformation network */
+#define LSDF_FRNN_MAX_HALF    64             /* its largest block half-width m (voxels) */
 #define LSDF_MAX_POINTS (((int64_t)1) << 34) /* obstacle points per query */
 
 /* One link's SDF grid (the "Link SDF" of Sec. III-A: extent e_r, resolution
@@ -167,16 +169,19 @@ int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L,
  * offset, pose and point contents (same C, M, K capacities).  Offsets out
  * of order or out of range are clamped into [0, C] and [0, M] on the device:
  * the results are then meaningless, but no access leaves the buffers. */
-#define LSDF_SCHED_DEFAULT     0   /* the library's choice (XCD slices) */
+#define LSDF_SCHED_DEFAULT     0   /* the library's choice (interleaved) */
 #define LSDF_SCHED_XCD_SLICES  1   /* each XCD takes a contiguous slice of
                                       the work (its L2 sees few link grids) */
 #define LSDF_SCHED_INTERLEAVED 2   /* every wave of the grid takes every W-th
                                       chunk (balances uneven work) */
 typedef struct {
     int32_t chunk_points;   /* points per work chunk: a multiple of 8 in
-                               [8, 8192]; 0 = default (32) */
+                               [8, 8192]; 0 = default (about two chunks
+                               per wave of the grid for C and M, 32 to 1024
+                               points) */
     int32_t blocks_per_cu;  /* workgroups of the persistent grid per compute
-                               unit, in [1, 16]; 0 = default (8) */
+                               unit, in [1, 16]; 0 = default (as many as fit
+                               on a CU at once) */
     int32_t schedule;       /* LSDF_SCHED_* */
     int32_t reserved;       /* must be 0 */
 } lsdf_query_tuning;
@@ -218,7 +223,7 @@ int lsdf_query_from_joints(const lsdf_dh* dh, int32_t dof, const float* base_T, 
  * (HIP events on `stream`) per candidate, and returns the candidate with
  * the lowest mean time in *best (and that time in ms in *best_ms, which may
  * be NULL).  candidates = NULL uses a built-in list (chunk_points 32 to
- * 4096, 4 and 8 workgroups per CU, both schedules).  1 <= reps <= 1000.
+ * 4096, 5 and 8 workgroups per CU, both schedules).  1 <= reps <= 1000.
  * It SYNCHRONISES the stream (not capturable); out_dist / out_link hold the
  * problem's results when it returns LSDF_OK. */
 int lsdf_query_autotune(int32_t K, const int32_t* traj_c_offset, const int64_t* traj_m_offset,
@@ -276,6 +281,46 @@ int lsdf_robot_sdf_query_workspace_size(const lsdf_env* env, int64_t M, size_t* 
 int lsdf_robot_sdf_query(const float* robot_sdf, int32_t C, const lsdf_env* env,
                          const float* points, int64_t M, float* out_dist,
                          void* workspace, size_t ws_bytes, void* stream);
+
+/* ---- the paper's grid-transformation network f(R) -------------------------
+ * Sec. III-B-1, Eq. 4-5: a tiny network maps a link rotation R to the
+ * rotated, normalised centres of the (2m)^3 voxels of a transformed Link
+ * SDF block, f(R) ~ R^T P_j with P_j = (j + 1/2) / m - 1 per axis; the
+ * block's link-frame points are then e_r (f(R) - R^T dt / e_r), e_r = m r.
+ *   x = R row-major (9), h = ReLU(W1 x + b1) (LSDF_FRNN_HIDDEN units),
+ *   out = W2 h + b2 (3 V outputs, V = (2m)^3, output 3 j + a for voxel
+ *   j = (j_z 2m + j_y) 2m + j_x and axis a).
+ * Parameters (FP32, device): W1[H][9], b1[H], W2[3V][H], b2[3V], H = 32;
+ * lsdf_frnn_nparam gives their count.  1 <= m <= LSDF_FRNN_MAX_HALF. */
+int lsdf_frnn_nparam(int32_t m, int64_t* n);
+int lsdf_frnn_train_workspace_size(int32_t m, int32_t B, size_t* bytes);
+
+/* One training step on B rotations R (device float [B][9], 1 <= B <= 64):
+ * the mean absolute error against R^T P over the batch and every output
+ * (the paper's L1 loss, Sec. IV-B) into loss_out (device float [1], may be
+ * NULL), its gradient into grad (device float [n]), then, when adam_m and
+ * adam_v (device float [n]) are given, one Adam update of params with step
+ * t >= 1 (bias-corrected).  With adam_m = adam_v = NULL only the loss and
+ * the gradient are computed.  FP32; deterministic (no float atomics). */
+int lsdf_frnn_train_step(float* params, float* adam_m, float* adam_v, int64_t t, float lr,
+                         float beta1, float beta2, float eps, int32_t m, const float* R, int32_t B,
+                         float* loss_out, float* grad, void* workspace, size_t ws_bytes, void* stream);
+
+/* max over N rotations (device float [N][9]) and all 3V outputs of
+ * |f(R) - R^T P| into out_max (device float [1]): the paper's test of the
+ * approximation over 10^7 random transformations (Sec. IV-B). */
+int lsdf_frnn_max_error(const float* params, int32_t m, const float* R, int64_t N, float* out_max,
+                        void* stream);
+
+/* lsdf_robot_sdf_build with the transformation taken from the network
+ * (Eq. 5) instead of computed exactly: every link uses the network's block
+ * half-width m (which must hold each link's grid box, else LSDF_E_SHAPE);
+ * block voxel j of link i at configuration c is read at the link-frame point
+ * e_r (f(R)_j - R^T dt / e_r).  Values are approximate (the network's
+ * error times e_r). */
+int lsdf_robot_sdf_build_frnn(const float* link_T, int32_t C, int32_t L, const lsdf_grid* grids,
+                              const void* grid_buf, const lsdf_env* env, const float* frnn_params,
+                              int32_t m, float* robot_sdf, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---- link SDF construction -------------------------------------------------
  * Sec. III-A: each link's signed distance field is computed once, offline,

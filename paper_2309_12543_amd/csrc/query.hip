@@ -39,6 +39,7 @@
 //     into the outputs (the kernel boundary orders it after every atomic,
 //     with no device fence).
 #include <algorithm>
+#include <atomic>
 
 #include "fk_chain.hpp"
 #include "grid_sample.hpp"
@@ -70,11 +71,21 @@ constexpr int kGather = LSDF_QUERY_GATHER;
 static_assert(kUnroll % kGather == 0, "gather batch must divide the unroll");
 static_assert(kUnroll == kBlockPts, "blocks of 8 points");
 
-// Default tiling: 4 blocks (32 points) per chunk, 8 workgroups per CU,
-// chunks in per-XCD slices.
-constexpr int kDefaultChunkPoints = 32;
+// Default tiling: as many workgroups per CU as can be resident at once (so
+// that no wave of the persistent grid waits for another to finish; 8 if
+// the runtime cannot say), chunks dealt over the whole grid, about two
+// chunks per wave of the grid for the call's sizes (with offset arrays, the
+// capacities C and M), a power of two between 4 and 128 blocks of 8 points.
+constexpr int kDefaultChunkPoints = 1024;
 constexpr int kDefaultBlocksPerCu = 8;
-constexpr int kDefaultSchedule = LSDF_SCHED_XCD_SLICES;
+constexpr int kDefaultSchedule = LSDF_SCHED_INTERLEAVED;
+
+int default_chunk_blocks(int64_t C, int64_t L, int64_t M, int64_t waves) {
+    const int64_t units = L * ((C + 63) / 64) * ((M + kBlockPts - 1) / kBlockPts);
+    int64_t cb = 4;
+    while (cb < 128 && 2 * cb * 2 * waves <= units) cb *= 2;
+    return (int)cb;
+}
 constexpr int kMaxChunkPoints = 8192;
 constexpr int kMaxBlocksPerCu = 16;
 
@@ -146,7 +157,10 @@ __device__ __forceinline__ void block_min(const float* __restrict__ points, int6
                                           float& best) {
     using E = GridT<DT>;
     if (j >= m_lo && j + kUnroll <= m_hi) {
-        float v0[kUnroll], v1[kUnroll], v2[kUnroll];
+        // first the box tests of the 8 points (lane masks), then the gathers
+        // of the points some lane holds, a batch at a time; the mapped
+        // coordinates are recomputed for the gathers rather than kept, which
+        // keeps register use (and so the number of resident waves) in check
         bool in[kUnroll];
         bool any = false;
 #pragma unroll
@@ -154,10 +168,10 @@ __device__ __forceinline__ void block_min(const float* __restrict__ points, int6
             const float x = points[3 * j + 3 * u + 0];
             const float y = points[3 * j + 3 * u + 1];
             const float z = points[3 * j + 3 * u + 2];
-            v0[u] = fmaf(m00, x, fmaf(m01, y, fmaf(m02, z, w0)));
-            v1[u] = fmaf(m10, x, fmaf(m11, y, fmaf(m12, z, w1)));
-            v2[u] = fmaf(m20, x, fmaf(m21, y, fmaf(m22, z, w2)));
-            in[u] = inside<CUBIC>(lg, v0[u], v1[u], v2[u]);
+            const float v0 = fmaf(m00, x, fmaf(m01, y, fmaf(m02, z, w0)));
+            const float v1 = fmaf(m10, x, fmaf(m11, y, fmaf(m12, z, w1)));
+            const float v2 = fmaf(m20, x, fmaf(m21, y, fmaf(m22, z, w2)));
+            in[u] = inside<CUBIC>(lg, v0, v1, v2);
             any |= in[u];
         }
         if (!__ballot(any)) return;
@@ -169,7 +183,13 @@ __device__ __forceinline__ void block_min(const float* __restrict__ points, int6
             Cell cell[kGather];
 #pragma unroll
             for (int u = 0; u < kGather; ++u) {
-                cell[u] = locate(lg, v0[b + u], v1[b + u], v2[b + u]);
+                const float x = points[3 * j + 3 * (b + u) + 0];
+                const float y = points[3 * j + 3 * (b + u) + 1];
+                const float z = points[3 * j + 3 * (b + u) + 2];
+                const float v0 = fmaf(m00, x, fmaf(m01, y, fmaf(m02, z, w0)));
+                const float v1 = fmaf(m10, x, fmaf(m11, y, fmaf(m12, z, w1)));
+                const float v2 = fmaf(m20, x, fmaf(m21, y, fmaf(m22, z, w2)));
+                cell[u] = locate(lg, v0, v1, v2);
                 // lanes outside the box read the first cell (discarded)
                 const typename E::T* cp = G + (in[b + u] ? cell[u].idx : 0);
                 c00[u] = E::get(cp, 0);        d00[u] = E::get(cp, 1);
@@ -506,6 +526,31 @@ size_t workspace_bytes(int64_t K, int64_t C, int64_t L, int64_t M) {
     return keys_bytes(C, L) + sphere_bytes(M) + plan_bytes(K) + map_bytes(C, L);
 }
 
+// Workgroups of the query kernel variant that fit on one CU at once.
+template <bool CUBIC, int DT>
+int resident_blocks_of() {
+    static std::atomic<int> cached{0};
+    int v = cached.load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, query_kernel<CUBIC, DT>, kBlock, 0) != hipSuccess || n < 1)
+        n = kDefaultBlocksPerCu;
+    n = std::min(n, kMaxBlocksPerCu);
+    cached.store(n, std::memory_order_relaxed);
+    return n;
+}
+
+int resident_blocks(int dtype, bool cubic) {
+    switch (dtype * 2 + (cubic ? 1 : 0)) {
+        case LSDF_F32 * 2 + 1: return resident_blocks_of<true, LSDF_F32>();
+        case LSDF_F32 * 2: return resident_blocks_of<false, LSDF_F32>();
+        case LSDF_BF16 * 2 + 1: return resident_blocks_of<true, LSDF_BF16>();
+        case LSDF_BF16 * 2: return resident_blocks_of<false, LSDF_BF16>();
+        case LSDF_F16 * 2 + 1: return resident_blocks_of<true, LSDF_F16>();
+        default: return resident_blocks_of<false, LSDF_F16>();
+    }
+}
+
 int device_cus() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -580,6 +625,11 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
         if (grids[i].dtype != dtype) return fail(LSDF_E_UNSUPPORTED, "%s: grids of one query must share a dtype", who);
         cubic = cubic && p.link[i].cubic;
     }
+    const int cus = device_cus();
+    if (cus <= 0) return fail(LSDF_E_DEVICE, "%s: cannot read the device's compute-unit count", who);
+    if (!(tuning && tuning->blocks_per_cu != 0)) blocks_per_cu = resident_blocks(dtype, cubic);
+    if (!(tuning && tuning->chunk_points != 0))   // from the capacities C and M when offsets are given
+        chunk_blocks = default_chunk_blocks(C, L, M, (int64_t)cus * blocks_per_cu * kWavesPerBlock);
     hipStream_t s = as_stream(stream);
     char* ws = static_cast<char*>(workspace);
     float4* spheres = reinterpret_cast<float4*>(ws + keys_bytes(C, L));
@@ -622,8 +672,6 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
         if (rc != LSDF_OK) return rc;
     }
     if (M > 0) {
-        const int cus = device_cus();
-        if (cus <= 0) return fail(LSDF_E_DEVICE, "%s: cannot read the device's compute-unit count", who);
         // persistent grid: blocks_per_cu workgroups per CU, a multiple of
         // the XCD count; when the chunk count is known here (one trajectory
         // given by C and M), no more waves than chunks
@@ -729,13 +777,12 @@ LSDF_API int lsdf_query_autotune(int32_t K, const int32_t* traj_c_offset, const 
     if (!best) return fail(LSDF_E_INVALID_ARG, "query_autotune: best is NULL");
     if (reps < 1 || reps > 1000) return fail(LSDF_E_INVALID_ARG, "query_autotune: reps = %d out of [1, 1000]", (int)reps);
     static const lsdf_query_tuning kGrid[] = {
-        {32, 8, LSDF_SCHED_XCD_SLICES, 0},    {32, 8, LSDF_SCHED_INTERLEAVED, 0},
-        {64, 8, LSDF_SCHED_XCD_SLICES, 0},    {64, 8, LSDF_SCHED_INTERLEAVED, 0},
-        {128, 8, LSDF_SCHED_XCD_SLICES, 0},   {128, 8, LSDF_SCHED_INTERLEAVED, 0},
-        {256, 8, LSDF_SCHED_XCD_SLICES, 0},   {256, 8, LSDF_SCHED_INTERLEAVED, 0},
-        {1024, 8, LSDF_SCHED_XCD_SLICES, 0},  {1024, 8, LSDF_SCHED_INTERLEAVED, 0},
-        {4096, 8, LSDF_SCHED_INTERLEAVED, 0}, {128, 4, LSDF_SCHED_INTERLEAVED, 0},
-        {256, 4, LSDF_SCHED_INTERLEAVED, 0},  {1024, 4, LSDF_SCHED_INTERLEAVED, 0},
+        {32, 8, LSDF_SCHED_INTERLEAVED, 0},   {64, 8, LSDF_SCHED_INTERLEAVED, 0},
+        {128, 8, LSDF_SCHED_INTERLEAVED, 0},  {256, 8, LSDF_SCHED_INTERLEAVED, 0},
+        {1024, 8, LSDF_SCHED_INTERLEAVED, 0}, {32, 5, LSDF_SCHED_INTERLEAVED, 0},
+        {64, 5, LSDF_SCHED_INTERLEAVED, 0},   {32, 8, LSDF_SCHED_XCD_SLICES, 0},
+        {64, 8, LSDF_SCHED_XCD_SLICES, 0},    {256, 8, LSDF_SCHED_XCD_SLICES, 0},
+        {1024, 8, LSDF_SCHED_XCD_SLICES, 0},  {4096, 8, LSDF_SCHED_XCD_SLICES, 0},
     };
     if (!candidates) {
         candidates = kGrid;

@@ -72,16 +72,25 @@ __global__ __launch_bounds__(kBlock) void align_kernel(BuildArgs a) {
     a.blocks[t] = b;
 }
 
+// Voxel v of one configuration (32-bit decode, x fastest); false past the end.
+__device__ inline bool voxel_of(const int32_t n[3], uint32_t v, int& vx, int& vy, int& vz) {
+    const uint32_t nx = (uint32_t)n[0], ny = (uint32_t)n[1];
+    const uint32_t rest = v / nx;
+    vx = (int)(v - rest * nx);
+    vz = (int)(rest / ny);
+    vy = (int)(rest - (uint32_t)vz * ny);
+    return vz < n[2];
+}
+
+// Grid: x over the voxels of one configuration, y over configurations
+// c0 + blockIdx.y.
 template <bool CUBIC, int DT>
-__global__ __launch_bounds__(kBlock) void build_kernel(BuildArgs a, const typename GridT<DT>::T* __restrict__ grid) {
-    const int64_t V = (int64_t)a.n[0] * a.n[1] * a.n[2];
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= V * a.C) return;
-    const int c = (int)(g / V);
-    const int64_t v = g - (int64_t)c * V;
-    const int vx = (int)(v % a.n[0]);
-    const int vy = (int)((v / a.n[0]) % a.n[1]);
-    const int vz = (int)(v / ((int64_t)a.n[0] * a.n[1]));
+__global__ __launch_bounds__(kBlock) void build_kernel(BuildArgs a, int32_t c0,
+                                                       const typename GridT<DT>::T* __restrict__ grid) {
+    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    int vx, vy, vz;
+    if (!voxel_of(a.n, v, vx, vy, vz)) return;
+    const int c = c0 + (int)blockIdx.y;
     const float x = (float)(a.lo[0] + ((double)vx + 0.5) * a.r);
     const float y = (float)(a.lo[1] + ((double)vy + 0.5) * a.r);
     const float z = (float)(a.lo[2] + ((double)vz + 0.5) * a.r);
@@ -96,7 +105,101 @@ __global__ __launch_bounds__(kBlock) void build_kernel(BuildArgs a, const typena
         const LinkGrid& lg = a.link[i];
         best = fminf(best, lsdf::sample_or_inf<CUBIC, DT>(grid + lg.offset, lg, b.gm, x, y, z));
     }
-    a.rs[g] = best;
+    a.rs[(int64_t)c * ((int64_t)a.n[0] * a.n[1] * a.n[2]) + v] = best;
+}
+
+// The same build with the transformation of Eq. 5: each block voxel's
+// link-frame position comes from the grid-transformation network,
+// G = f(R) + dt_inv with dt_inv = -R^T dt / e_r, l = e_r G, e_r = m r, for a
+// block half-width m shared by all links (the network's).
+struct LinkBlockNN {
+    int32_t k[3];
+    int32_t pad;
+    float h[LSDF_FRNN_HIDDEN];       // hidden layer of f at this rotation
+    float dtinv[3];
+    float pad2;
+};
+static_assert(sizeof(LinkBlockNN) == 160, "LinkBlockNN layout");
+
+struct BuildNNArgs {
+    LinkGrid link[LSDF_MAX_LINKS];
+    double lo[3];
+    double r;
+    int32_t n[3];
+    int32_t C, L, m;
+    float er;                        // m r
+    const float* link_T;
+    const float* params;             // W1[32][9], b1[32], W2[3V][32], b2[3V]
+    LinkBlockNN* blocks;             // [C][L]
+    float* rs;
+};
+
+__global__ __launch_bounds__(kBlock) void align_nn_kernel(BuildNNArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)a.C * a.L) return;
+    const float* T = a.link_T + t * 12;
+    LinkBlockNN b{};
+    double dt[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        // Eq. 1-3: T_O = t - lo, k = round(T_O / r) - m, dt = T_O - (k + m) r
+        const double t_o = (double)T[4 * ax + 3] - a.lo[ax];
+        b.k[ax] = (int32_t)rint(t_o / a.r) - a.m;
+        dt[ax] = t_o - ((double)b.k[ax] + (double)a.m) * a.r;
+    }
+    // dt_inv = -R^T dt / e_r  (R[row][col] = T[4 row + col])
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+        b.dtinv[ax] = (float)(-((double)T[ax] * dt[0] + (double)T[4 + ax] * dt[1] + (double)T[8 + ax] * dt[2]) /
+                              (double)a.er);
+    const float x[9] = {T[0], T[1], T[2], T[4], T[5], T[6], T[8], T[9], T[10]};
+    const float* W1 = a.params;
+    const float* b1 = W1 + LSDF_FRNN_HIDDEN * 9;
+    for (int u = 0; u < LSDF_FRNN_HIDDEN; ++u) {
+        float acc = b1[u];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc = fmaf(W1[u * 9 + k], x[k], acc);
+        b.h[u] = fmaxf(acc, 0.0f);
+    }
+    a.blocks[t] = b;
+}
+
+template <bool CUBIC, int DT>
+__global__ __launch_bounds__(kBlock) void build_nn_kernel(BuildNNArgs a, int32_t c0,
+                                                          const typename GridT<DT>::T* __restrict__ grid) {
+    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
+    int vx, vy, vz;
+    if (!voxel_of(a.n, v, vx, vy, vz)) return;
+    const int c = c0 + (int)blockIdx.y;
+    const int w = 2 * a.m;
+    const int64_t O = 3 * (int64_t)w * w * w;
+    const float* W2 = a.params + LSDF_FRNN_HIDDEN * 10;
+    const float* b2 = W2 + O * LSDF_FRNN_HIDDEN;
+    const LinkBlockNN* bl = a.blocks + (int64_t)c * a.L;
+    float best = INFINITY;
+    for (int i = 0; i < a.L; ++i) {
+        const LinkBlockNN& b = bl[i];
+        const int jx = vx - b.k[0], jy = vy - b.k[1], jz = vz - b.k[2];
+        if (jx < 0 || jx >= w || jy < 0 || jy >= w || jz < 0 || jz >= w) continue;
+        const int64_t o = 3 * (((int64_t)jz * w + jy) * w + jx);
+        float l[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const float* row = W2 + (o + ax) * LSDF_FRNN_HIDDEN;
+            float y = b2[o + ax];
+#pragma unroll
+            for (int u = 0; u < LSDF_FRNN_HIDDEN; ++u) y = fmaf(row[u], b.h[u], y);
+            l[ax] = a.er * (y + b.dtinv[ax]);
+        }
+        // link-frame point to centred grid coordinates: v_a = l_a invh_a + cen_a
+        const LinkGrid& lg = a.link[i];
+        lsdf::GridMap id{};
+        id.m00 = lg.invh[0]; id.w0 = lg.cen[0];
+        id.m11 = lg.invh[1]; id.w1 = lg.cen[1];
+        id.m22 = lg.invh[2]; id.w2 = lg.cen[2];
+        best = fminf(best, lsdf::sample_or_inf<CUBIC, DT>(grid + lg.offset, lg, id, l[0], l[1], l[2]));
+    }
+    a.rs[(int64_t)c * ((int64_t)a.n[0] * a.n[1] * a.n[2]) + v] = best;
 }
 
 struct RuntimeArgs {
@@ -143,8 +246,18 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(RuntimeArgs a) {
     const int64_t V = (int64_t)a.n[0] * a.n[1] * a.n[2];
     const float* rs = a.rs + (int64_t)c * V;
     const uint32_t cnt = *a.count;
-    float best = INFINITY;
-    for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) best = fminf(best, rs[a.list[k]]);
+    // four independent loads in flight per step
+    float b0 = INFINITY, b1 = INFINITY, b2 = INFINITY, b3 = INFINITY;
+    uint32_t k = threadIdx.x;
+    for (; k + 3 * kBlock < cnt; k += 4 * kBlock) {
+        const uint32_t v0 = a.list[k], v1 = a.list[k + kBlock], v2 = a.list[k + 2 * kBlock], v3 = a.list[k + 3 * kBlock];
+        b0 = fminf(b0, rs[v0]);
+        b1 = fminf(b1, rs[v1]);
+        b2 = fminf(b2, rs[v2]);
+        b3 = fminf(b3, rs[v3]);
+    }
+    for (; k < cnt; k += kBlock) b0 = fminf(b0, rs[a.list[k]]);
+    float best = fminf(fminf(b0, b1), fminf(b2, b3));
     // workgroup minimum
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) best = fminf(best, __shfl_xor(best, off));
@@ -156,6 +269,21 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(RuntimeArgs a) {
         for (int w = 1; w < kBlock / 64; ++w) m = fminf(m, wmin[w]);
         a.out_dist[c] = m;
     }
+}
+
+// Block half-width of a link: the farthest grid-box corner from the link
+// origin, in voxels, rounded up, plus two.
+double block_halfwidth(const lsdf_grid& g, float voxel) {
+    double far2 = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        double s = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            const double cc = (k >> ax) & 1 ? g.hi[ax] : g.lo[ax];
+            s += cc * cc;
+        }
+        far2 = std::max(far2, s);
+    }
+    return std::ceil(std::sqrt(far2) / (double)voxel) + 2.0;
 }
 
 int check_env(const char* who, const lsdf_env* env, int64_t* V) {
@@ -171,7 +299,10 @@ int check_env(const char* who, const lsdf_env* env, int64_t* V) {
     return LSDF_OK;
 }
 
-size_t blocks_bytes(int64_t C, int64_t L) { return ((size_t)(C * L) * sizeof(LinkBlock) + 255) / 256 * 256; }
+// room for either form's per-(configuration, link) table
+size_t blocks_bytes(int64_t C, int64_t L) {
+    return ((size_t)(C * L) * std::max(sizeof(LinkBlock), sizeof(LinkBlockNN)) + 255) / 256 * 256;
+}
 
 }  // namespace
 
@@ -222,18 +353,7 @@ LSDF_API int lsdf_robot_sdf_build(const float* link_T, int32_t C, int32_t L, con
         if (rc != LSDF_OK) return rc;
         if (grids[i].dtype != dtype) return fail(LSDF_E_UNSUPPORTED, "robot_sdf_build: grids must share a dtype");
         cubic = cubic && a.link[i].cubic;
-        // block half-width: farthest box corner from the link origin, in
-        // voxels, rounded up, plus two
-        double far2 = 0.0;
-        for (int k = 0; k < 8; ++k) {
-            double s = 0.0;
-            for (int ax = 0; ax < 3; ++ax) {
-                const double cc = (k >> ax) & 1 ? grids[i].hi[ax] : grids[i].lo[ax];
-                s += cc * cc;
-            }
-            far2 = std::max(far2, s);
-        }
-        const double hw = std::ceil(std::sqrt(far2) / (double)env->voxel) + 2.0;
+        const double hw = block_halfwidth(grids[i], env->voxel);
         if (hw > 65536.0) return fail(LSDF_E_SHAPE, "robot_sdf_build: link %d's block is too wide", i);
         a.halfw[i] = (int32_t)hw;
     }
@@ -251,18 +371,87 @@ LSDF_API int lsdf_robot_sdf_build(const float* link_T, int32_t C, int32_t L, con
     const int64_t CL = (int64_t)C * L;
     hipLaunchKernelGGL(align_kernel, dim3((unsigned)((CL + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
     if ((rc = check_launch("robot_sdf_build (align)")) != LSDF_OK) return rc;
-    const int64_t total = V * C;
-    if ((total + kBlock - 1) / kBlock > 0x7fffffffLL) return fail(LSDF_E_SHAPE, "robot_sdf_build: too many voxels");
-    const dim3 gd((unsigned)((total + kBlock - 1) / kBlock)), bd(kBlock);
-    switch (dtype * 2 + (cubic ? 1 : 0)) {
-        case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((build_kernel<true, LSDF_F32>), gd, bd, 0, s, a, static_cast<const float*>(grid_buf)); break;
-        case LSDF_F32 * 2: hipLaunchKernelGGL((build_kernel<false, LSDF_F32>), gd, bd, 0, s, a, static_cast<const float*>(grid_buf)); break;
-        case LSDF_BF16 * 2 + 1: hipLaunchKernelGGL((build_kernel<true, LSDF_BF16>), gd, bd, 0, s, a, static_cast<const uint16_t*>(grid_buf)); break;
-        case LSDF_BF16 * 2: hipLaunchKernelGGL((build_kernel<false, LSDF_BF16>), gd, bd, 0, s, a, static_cast<const uint16_t*>(grid_buf)); break;
-        case LSDF_F16 * 2 + 1: hipLaunchKernelGGL((build_kernel<true, LSDF_F16>), gd, bd, 0, s, a, static_cast<const _Float16*>(grid_buf)); break;
-        default: hipLaunchKernelGGL((build_kernel<false, LSDF_F16>), gd, bd, 0, s, a, static_cast<const _Float16*>(grid_buf)); break;
+    // x: the voxels of one configuration, y: up to 65535 configurations per launch
+    const dim3 bd(kBlock);
+    for (int32_t c0 = 0; c0 < C; c0 += 65535) {
+        const dim3 gd((unsigned)((V + kBlock - 1) / kBlock), (unsigned)std::min<int32_t>(65535, C - c0));
+        switch (dtype * 2 + (cubic ? 1 : 0)) {
+            case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((build_kernel<true, LSDF_F32>), gd, bd, 0, s, a, c0, static_cast<const float*>(grid_buf)); break;
+            case LSDF_F32 * 2: hipLaunchKernelGGL((build_kernel<false, LSDF_F32>), gd, bd, 0, s, a, c0, static_cast<const float*>(grid_buf)); break;
+            case LSDF_BF16 * 2 + 1: hipLaunchKernelGGL((build_kernel<true, LSDF_BF16>), gd, bd, 0, s, a, c0, static_cast<const uint16_t*>(grid_buf)); break;
+            case LSDF_BF16 * 2: hipLaunchKernelGGL((build_kernel<false, LSDF_BF16>), gd, bd, 0, s, a, c0, static_cast<const uint16_t*>(grid_buf)); break;
+            case LSDF_F16 * 2 + 1: hipLaunchKernelGGL((build_kernel<true, LSDF_F16>), gd, bd, 0, s, a, c0, static_cast<const _Float16*>(grid_buf)); break;
+            default: hipLaunchKernelGGL((build_kernel<false, LSDF_F16>), gd, bd, 0, s, a, c0, static_cast<const _Float16*>(grid_buf)); break;
+        }
+        if ((rc = check_launch("robot_sdf_build")) != LSDF_OK) return rc;
     }
-    return check_launch("robot_sdf_build");
+    return LSDF_OK;
+}
+
+LSDF_API int lsdf_robot_sdf_build_frnn(const float* link_T, int32_t C, int32_t L, const lsdf_grid* grids,
+                                       const void* grid_buf, const lsdf_env* env, const float* frnn_params,
+                                       int32_t m, float* robot_sdf, void* workspace, size_t ws_bytes,
+                                       void* stream) {
+    using namespace lsdf;
+    clear_error();
+    int64_t V = 0;
+    int rc = check_env("robot_sdf_build_frnn", env, &V);
+    if (rc != LSDF_OK) return rc;
+    if (C < 0) return fail(LSDF_E_SHAPE, "robot_sdf_build_frnn: C < 0");
+    if (L < 1 || L > LSDF_MAX_LINKS) return fail(LSDF_E_SHAPE, "robot_sdf_build_frnn: L = %d out of [1, %d]", (int)L, LSDF_MAX_LINKS);
+    if (m < 1 || m > LSDF_FRNN_MAX_HALF) return fail(LSDF_E_SHAPE, "robot_sdf_build_frnn: m = %d out of [1, %d]", (int)m, LSDF_FRNN_MAX_HALF);
+    if (!grids) return fail(LSDF_E_INVALID_ARG, "robot_sdf_build_frnn: grids is NULL");
+    if (C == 0) return LSDF_OK;
+    if (!link_T || !grid_buf || !robot_sdf || !workspace || !frnn_params)
+        return fail(LSDF_E_INVALID_ARG, "robot_sdf_build_frnn: NULL device pointer");
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return fail(LSDF_E_INVALID_ARG, "robot_sdf_build_frnn: workspace is not 256-byte aligned");
+    if (ws_bytes < blocks_bytes(C, L))
+        return fail(LSDF_E_SHAPE, "robot_sdf_build_frnn: workspace has %zu bytes, needs %zu", ws_bytes, blocks_bytes(C, L));
+    BuildNNArgs a{};
+    bool cubic = true;
+    const int dtype = grids[0].dtype;
+    for (int i = 0; i < L; ++i) {
+        rc = prepare_link_grid(grids[i], i, &a.link[i]);
+        if (rc != LSDF_OK) return rc;
+        if (grids[i].dtype != dtype) return fail(LSDF_E_UNSUPPORTED, "robot_sdf_build_frnn: grids must share a dtype");
+        cubic = cubic && a.link[i].cubic;
+        if (block_halfwidth(grids[i], env->voxel) > (double)m)
+            return fail(LSDF_E_SHAPE, "robot_sdf_build_frnn: the network's block (m = %d) does not hold link %d's box",
+                        (int)m, i);
+    }
+    for (int ax = 0; ax < 3; ++ax) {
+        a.lo[ax] = env->lo[ax];
+        a.n[ax] = env->n[ax];
+    }
+    a.r = env->voxel;
+    a.C = C;
+    a.L = L;
+    a.m = m;
+    a.er = (float)((double)m * (double)env->voxel);
+    a.link_T = link_T;
+    a.params = frnn_params;
+    a.blocks = static_cast<LinkBlockNN*>(workspace);
+    a.rs = robot_sdf;
+    hipStream_t s = as_stream(stream);
+    const int64_t CL = (int64_t)C * L;
+    hipLaunchKernelGGL(align_nn_kernel, dim3((unsigned)((CL + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
+    if ((rc = check_launch("robot_sdf_build_frnn (align)")) != LSDF_OK) return rc;
+    // x: the voxels of one configuration, y: up to 65535 configurations per launch
+    const dim3 bd(kBlock);
+    for (int32_t c0 = 0; c0 < C; c0 += 65535) {
+        const dim3 gd((unsigned)((V + kBlock - 1) / kBlock), (unsigned)std::min<int32_t>(65535, C - c0));
+        switch (dtype * 2 + (cubic ? 1 : 0)) {
+            case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((build_nn_kernel<true, LSDF_F32>), gd, bd, 0, s, a, c0, static_cast<const float*>(grid_buf)); break;
+            case LSDF_F32 * 2: hipLaunchKernelGGL((build_nn_kernel<false, LSDF_F32>), gd, bd, 0, s, a, c0, static_cast<const float*>(grid_buf)); break;
+            case LSDF_BF16 * 2 + 1: hipLaunchKernelGGL((build_nn_kernel<true, LSDF_BF16>), gd, bd, 0, s, a, c0, static_cast<const uint16_t*>(grid_buf)); break;
+            case LSDF_BF16 * 2: hipLaunchKernelGGL((build_nn_kernel<false, LSDF_BF16>), gd, bd, 0, s, a, c0, static_cast<const uint16_t*>(grid_buf)); break;
+            case LSDF_F16 * 2 + 1: hipLaunchKernelGGL((build_nn_kernel<true, LSDF_F16>), gd, bd, 0, s, a, c0, static_cast<const _Float16*>(grid_buf)); break;
+            default: hipLaunchKernelGGL((build_nn_kernel<false, LSDF_F16>), gd, bd, 0, s, a, c0, static_cast<const _Float16*>(grid_buf)); break;
+        }
+        if ((rc = check_launch("robot_sdf_build_frnn")) != LSDF_OK) return rc;
+    }
+    return LSDF_OK;
 }
 
 namespace {

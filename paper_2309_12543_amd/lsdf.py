@@ -126,6 +126,17 @@ def load_library():
     lib.lsdf_robot_sdf_query_workspace_size.argtypes = [env, i64, ct.POINTER(sz)]
     lib.lsdf_robot_sdf_query.restype = ct.c_int
     lib.lsdf_robot_sdf_query.argtypes = [vp, i32, env, vp, i64, vp, vp, sz, vp]
+    lib.lsdf_frnn_nparam.restype = ct.c_int
+    lib.lsdf_frnn_nparam.argtypes = [i32, ct.POINTER(i64)]
+    lib.lsdf_frnn_train_workspace_size.restype = ct.c_int
+    lib.lsdf_frnn_train_workspace_size.argtypes = [i32, i32, ct.POINTER(sz)]
+    lib.lsdf_frnn_train_step.restype = ct.c_int
+    lib.lsdf_frnn_train_step.argtypes = [vp, vp, vp, i64, ct.c_float, ct.c_float, ct.c_float, ct.c_float, i32, vp,
+                                         i32, vp, vp, vp, sz, vp]
+    lib.lsdf_frnn_max_error.restype = ct.c_int
+    lib.lsdf_frnn_max_error.argtypes = [vp, i32, vp, i64, vp, vp]
+    lib.lsdf_robot_sdf_build_frnn.restype = ct.c_int
+    lib.lsdf_robot_sdf_build_frnn.argtypes = [vp, i32, i32, ct.POINTER(lsdf_grid), vp, env, vp, i32, vp, vp, sz, vp]
     lib.lsdf_build_link_sdf.restype = ct.c_int
     lib.lsdf_build_link_sdf.argtypes = [vp, i32, vp, i32, ct.POINTER(ct.c_int32), i32, ct.POINTER(lsdf_grid),
                                         vp, vp]
@@ -504,6 +515,79 @@ def robot_sdf_query(robot_sdf: torch.Tensor, env: lsdf_env, points: torch.Tensor
     ws = _cached_workspace(int(n.value), dev)
     _check(lib.lsdf_robot_sdf_query(robot_sdf.data_ptr(), C, ct.byref(env), points.data_ptr() if M > 0 else None, M,
                                     out.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream, dev)))
+    return out
+
+
+def frnn_nparam(m: int) -> int:
+    n = ct.c_int64(0)
+    _check(load_library().lsdf_frnn_nparam(int(m), ct.byref(n)))
+    return int(n.value)
+
+
+def frnn_train_step(params: torch.Tensor, m: int, R: torch.Tensor, *, adam=None, t: int = 1, lr: float = 1e-4,
+                    beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, grad: torch.Tensor | None = None,
+                    loss: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None):
+    """One step of the grid-transformation network (lsdf_frnn_train_step):
+    R [B][3][3] rotations; adam = (m, v) moment tensors or None (gradient
+    only).  Returns (loss [1], grad [n])."""
+    lib = load_library()
+    n = frnn_nparam(m)
+    _require(params, "params", torch.float32, (n,))
+    R = R.reshape(-1, 9)
+    _require(R, "R", torch.float32)
+    B, dev = int(R.shape[0]), params.device
+    grad = torch.empty(n, dtype=torch.float32, device=dev) if grad is None else grad
+    loss = torch.empty(1, dtype=torch.float32, device=dev) if loss is None else loss
+    if workspace is None:
+        need = ct.c_size_t(0)
+        _check(lib.lsdf_frnn_train_workspace_size(int(m), B, ct.byref(need)))
+        workspace = _cached_workspace(int(need.value), dev)
+    am, av = (None, None) if adam is None else adam
+    if am is not None:
+        _require(am, "adam_m", torch.float32, (n,))
+        _require(av, "adam_v", torch.float32, (n,))
+    _check(lib.lsdf_frnn_train_step(params.data_ptr(), am.data_ptr() if am is not None else None,
+                                    av.data_ptr() if av is not None else None, int(t), float(lr), float(beta1),
+                                    float(beta2), float(eps), int(m), R.data_ptr(), B, loss.data_ptr(),
+                                    grad.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                    _stream_handle(stream, dev)))
+    return loss, grad
+
+
+def frnn_max_error(params: torch.Tensor, m: int, R: torch.Tensor, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """max |f(R) - R^T P| over the rotations R [N][3][3] (lsdf_frnn_max_error)."""
+    lib = load_library()
+    _require(params, "params", torch.float32, (frnn_nparam(m),))
+    R = R.reshape(-1, 9)
+    _require(R, "R", torch.float32)
+    out = torch.empty(1, dtype=torch.float32, device=params.device) if out is None else out
+    _check(lib.lsdf_frnn_max_error(params.data_ptr(), int(m), R.data_ptr() if R.shape[0] else None,
+                                   int(R.shape[0]), out.data_ptr(), _stream_handle(stream, params.device)))
+    return out
+
+
+def robot_sdf_build_frnn(link_T: torch.Tensor, grids: GridSet, env: lsdf_env, frnn_params: torch.Tensor, m: int,
+                         out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Robot SDFs with the network's transformation (lsdf_robot_sdf_build_frnn)."""
+    lib = load_library()
+    if link_T.dim() != 4 or tuple(link_T.shape[2:]) != (3, 4):
+        raise ValueError("link_T must be [C][L][3][4]")
+    _require(link_T, "link_T", torch.float32)
+    _require(frnn_params, "frnn_params", torch.float32, (frnn_nparam(m),))
+    C, L, dev = int(link_T.shape[0]), int(link_T.shape[1]), link_T.device
+    if L != grids.L:
+        raise ValueError(f"link_T has {L} links, grids has {grids.L}")
+    shape = (C, int(env.n[2]), int(env.n[1]), int(env.n[0]))
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=dev)
+    _require(out, "robot_sdf", torch.float32, shape)
+    n = ct.c_size_t(0)
+    _check(lib.lsdf_robot_sdf_build_workspace_size(C, L, ct.byref(n)))
+    ws = _cached_workspace(int(n.value), dev)
+    _check(lib.lsdf_robot_sdf_build_frnn(link_T.data_ptr(), C, L, grids.desc, grids.buf.data_ptr(), ct.byref(env),
+                                         frnn_params.data_ptr(), int(m), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                         _stream_handle(stream, dev)))
     return out
 
 

@@ -178,7 +178,7 @@ def test_batched_query_argument_errors(lib):
         assert q(tuning=ct.byref(B.make_tuning(*bad))) == B.LSDF_E_INVALID_ARG, bad
     assert b"schedule" in lib.lsdf_last_error()
     t = B.make_tuning(32, 8, 1)
-    t.reserved = 5
+    t.reserved = 1
     assert q(tuning=ct.byref(t)) == B.LSDF_E_INVALID_ARG
     # the plan of K trajectories lives in the workspace: K = 3 fits where K = 60000 does not
     n = ct.c_size_t(0)
@@ -263,3 +263,33 @@ def test_robot_sdf_argument_errors(lib):
     assert lib.lsdf_robot_sdf_query(FAKE, 4, ct.byref(env), None, 1000, FAKE, FAKE, n.value, None) \
         == B.LSDF_E_INVALID_ARG
     assert lib.lsdf_robot_sdf_query(FAKE, 0, ct.byref(env), FAKE, 1000, FAKE, FAKE, n.value, None) == B.LSDF_OK
+
+
+def test_frnn_argument_errors(lib):
+    from paper_2309_12543_amd import lsdf as B
+    n = ct.c_int64(0)
+    assert lib.lsdf_frnn_nparam(2, ct.byref(n)) == 0 and n.value == 32 * 9 + 32 + 3 * 64 * 32 + 3 * 64
+    assert lib.lsdf_frnn_nparam(0, ct.byref(n)) == B.LSDF_E_SHAPE
+    assert lib.lsdf_frnn_nparam(65, ct.byref(n)) == B.LSDF_E_SHAPE
+    sz = ct.c_size_t(0)
+    assert lib.lsdf_frnn_train_workspace_size(2, 65, ct.byref(sz)) == B.LSDF_E_SHAPE
+    assert lib.lsdf_frnn_train_workspace_size(2, 64, ct.byref(sz)) == 0
+
+    def step(mo=FAKE, vo=FAKE, t=1, lr=1e-3, B_=8, wsb=1 << 24):
+        return lib.lsdf_frnn_train_step(FAKE, mo, vo, t, lr, 0.9, 0.999, 1e-8, 2, FAKE, B_, None, FAKE, FAKE, wsb,
+                                        None)
+    assert step(mo=None) == B.LSDF_E_INVALID_ARG          # one moment without the other
+    assert step(t=0) == B.LSDF_E_INVALID_ARG
+    assert step(lr=float("nan")) == B.LSDF_E_INVALID_ARG
+    assert step(B_=0) == B.LSDF_E_SHAPE
+    assert step(wsb=16) == B.LSDF_E_SHAPE
+    assert lib.lsdf_frnn_max_error(FAKE, 0, FAKE, 10, FAKE, None) == B.LSDF_E_SHAPE
+    assert lib.lsdf_frnn_max_error(None, 2, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG
+    env = B.make_env((-2, -2, -2), 1 / 32, (128, 128, 128))
+    g = grid_array(2)
+    assert lib.lsdf_robot_sdf_build_frnn(FAKE, 4, 2, g, FAKE, ct.byref(env), FAKE, 0, FAKE, FAKE, 1 << 20, None) \
+        == B.LSDF_E_SHAPE
+    # grid boxes of half-width 0.5 m need m >= ceil(0.866 / r) + 2 = 30 at r = 1/32: m = 10 is too small
+    assert lib.lsdf_robot_sdf_build_frnn(FAKE, 4, 2, g, FAKE, ct.byref(env), FAKE, 10, FAKE, FAKE, 1 << 20, None) \
+        == B.LSDF_E_SHAPE
+    assert b"does not hold" in lib.lsdf_last_error()

@@ -127,8 +127,9 @@ def test_batched_equals_plain_per_trajectory(B, orc, small, tiny_grids):
 
 
 @pytest.mark.parametrize("chunk,bpc,sched", [(8, 8, 1), (24, 3, 2), (64, 1, 1), (1024, 16, 2), (8192, 2, 1),
-                                             (40, 8, 2)])
+                                             (40, 8, 2), (520, 8, 2), (128, 5, 1)])
 def test_tiling_does_not_change_bits(B, orc, small, tiny_grids, chunk, bpc, sched):
+    """Chunk size, workgroups per CU and schedule change no result bit."""
     T32 = poses32(orc, small)
     pts = small.points.astype(np.float32)
     gs = upload_grids(B, small, tiny_grids)
@@ -222,7 +223,7 @@ def test_autotune_returns_a_candidate(B, orc, small, tiny_grids):
     T32 = poses32(orc, small)
     pts = small.points.astype(np.float32)
     gs = upload_grids(B, small, tiny_grids)
-    cands = [(8, 8, 1), (32, 8, 2), (128, 4, 2)]
+    cands = [(64, 8, 1), (128, 8, 2), (512, 4, 2)]
     say("autotune over 3 candidates")
     best, ms, (d, l) = B.query_autotune(to_dev(T32), gs, to_dev(pts), to_dev(small.c_off, torch.int32),
                                         to_dev(small.m_off, torch.int64), candidates=cands, reps=3)

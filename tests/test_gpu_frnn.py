@@ -1,0 +1,125 @@
+"""GPU parity of the paper's grid-transformation network f(R) (Sec. III-B-1,
+Eq. 4-5) through the C ABI.
+
+* the training step's loss and gradient against the oracle's double
+  precision ones, and its Adam update against the oracle's Adam;
+* the max-error kernel against the oracle's forward pass;
+* the network built by hand to represent R^T P exactly has an FP32-sized
+  maximum error, and the Robot SDFs built with it agree with the exact
+  build to FP32 rounding;
+* training from a random start lowers the loss.
+"""
+import numpy as np
+import pytest
+import torch
+
+from frnn_util import exact_params, random_rotations
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-frnn]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_12543_amd import lsdf
+    lsdf.load_library()
+    return lsdf
+
+
+def to_dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def random_params(orc, m, seed, scale=0.3):
+    return np.random.default_rng(seed).normal(scale=scale, size=orc.frnn_nparam(m))
+
+
+def test_loss_and_gradient_match_oracle(B, orc):
+    m, nb = 2, 64
+    p = random_params(orc, m, 110)
+    R = random_rotations(nb, 111)
+    say(f"frnn gradient m={m} B={nb}")
+    loss, grad = B.frnn_train_step(to_dev(p), m, to_dev(R))
+    loss, grad = float(loss.item()), grad.cpu().numpy().astype(np.float64)
+    l64, g64 = orc.frnn_loss_grad(p, m, R)
+    assert loss == pytest.approx(l64, rel=1e-5)
+    cos = g64 @ grad / np.linalg.norm(g64) / np.linalg.norm(grad)
+    rel = np.abs(grad - g64).max() / np.abs(g64).max()
+    say(f"loss {loss:.6g} vs {l64:.6g}; gradient cosine {cos:.8f}, max-norm rel {rel:.3g}")
+    assert cos > 0.99999 and rel < 1e-3
+
+
+def test_adam_update_matches_oracle(B, orc):
+    m, nb = 1, 32
+    p = random_params(orc, m, 112)
+    R = random_rotations(nb, 113)
+    P = to_dev(p)
+    mm, vv = torch.zeros_like(P), torch.zeros_like(P)
+    for t in (1, 2):
+        before = P.cpu().numpy().astype(np.float64)
+        m64, v64 = mm.cpu().numpy().astype(np.float64), vv.cpu().numpy().astype(np.float64)
+        _, g = B.frnn_train_step(P, m, to_dev(R), adam=(mm, vv), t=t, lr=1e-3)
+        g = g.cpu().numpy().astype(np.float64)
+        want = before.copy()
+        orc.adam_step(want, m64, v64, g, t, 1e-3)
+        assert np.abs(P.cpu().numpy() - want).max() <= 1e-6 * max(1.0, np.abs(want).max())
+
+
+def test_max_error_matches_oracle(B, orc):
+    m = 2
+    p = random_params(orc, m, 114)
+    R = random_rotations(1000, 115)
+    say("frnn max error, 1000 rotations")
+    got = float(B.frnn_max_error(to_dev(p), m, to_dev(R)).item())
+    want = np.abs(orc.frnn_forward(p, m, R) - orc.frnn_target(m, R)).max()
+    assert got == pytest.approx(want, rel=1e-5)
+    assert float(B.frnn_max_error(to_dev(p), m, to_dev(np.zeros((0, 3, 3)))).item()) == 0.0
+
+
+def test_exact_network_and_robot_sdf_build(B, orc, tiny, tiny_grids):
+    """The hand-built exact network: FP32-sized error, and Robot SDFs built
+    through it agree with the exact build."""
+    r = 1.0 / 16.0
+    lo, n = (-1.5, -1.5, -1.5), (48, 48, 40)
+    far = max(np.linalg.norm(np.array([[x, y, z] for x in (tiny.grid_lo[i, 0], tiny.grid_hi[i, 0])
+                                       for y in (tiny.grid_lo[i, 1], tiny.grid_hi[i, 1])
+                                       for z in (tiny.grid_lo[i, 2], tiny.grid_hi[i, 2])]), axis=1).max()
+              for i in range(tiny.L))
+    m = int(np.ceil(far / r)) + 2
+    P = to_dev(exact_params(m))
+    err = float(B.frnn_max_error(P, m, to_dev(random_rotations(2000, 116))).item())
+    say(f"exact network m={m}: max error {err:.3g}")
+    assert err < 2e-6
+    gs = B.GridSet(tiny.grid_lo, tiny.grid_hi, tiny.grid_n, device="cuda")
+    for i, g in enumerate(tiny_grids):
+        gs.set_grid(i, g.astype(np.float32))
+    T = to_dev(orc.fk(tiny.robot.dh, tiny.q[[4, 33]], tiny.robot.base_T).astype(np.float32))
+    env = B.make_env(lo, r, n)
+    exact = B.robot_sdf_build(T, gs, env).cpu().numpy()
+    nn = B.robot_sdf_build_frnn(T, gs, env, P, m).cpu().numpy()
+    fe, fn = np.isfinite(exact), np.isfinite(nn)
+    both = fe & fn
+    assert (fe != fn).sum() <= 0.002 * fe.sum()          # only voxels whose centre sits on a box face
+    assert np.abs(exact[both] - nn[both]).max() < 1e-4
+    with pytest.raises(B.LsdfError):                      # a block too small for the links
+        B.robot_sdf_build_frnn(T, gs, env, to_dev(exact_params(2)), 2)
+
+
+def test_training_lowers_the_loss(B, orc):
+    m, nb = 2, 64
+    P = to_dev(random_params(orc, m, 117, scale=0.1))
+    mm, vv = torch.zeros_like(P), torch.zeros_like(P)
+    rng_seed = 118
+    losses = []
+    for t in range(1, 301):
+        R = to_dev(random_rotations(nb, rng_seed + t))
+        loss, _ = B.frnn_train_step(P, m, R, adam=(mm, vv), t=t, lr=3e-3)
+        if t in (1, 300):
+            losses.append(float(loss.item()))
+    say(f"training loss {losses[0]:.4g} -> {losses[1]:.4g}")
+    assert losses[1] < 0.5 * losses[0]
