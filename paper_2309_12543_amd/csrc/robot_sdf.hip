@@ -6,9 +6,9 @@
 // It is kept here as the comparator of the per-point query: heavy
 // preparation and C x V voxels of memory against a trivial runtime.
 //
-// Build (one thread per environment voxel, voxels x fastest, so every
-// store is coalesced and each voxel is written exactly once, without
-// atomics):
+// Build (one thread per environment voxel column of 8, voxels x fastest,
+// so every store is coalesced and each voxel is written exactly once,
+// without atomics):
 //   * link i's block at configuration c covers voxels k .. k + 2m - 1 per
 //     axis, with k from the alignment of Eq. 1-3 (computed in double from
 //     the link origin: T_O = t - lo, k = round(T_O / r) - m) and m the
@@ -72,40 +72,72 @@ __global__ __launch_bounds__(kBlock) void align_kernel(BuildArgs a) {
     a.blocks[t] = b;
 }
 
-// Voxel v of one configuration (32-bit decode, x fastest); false past the end.
-__device__ inline bool voxel_of(const int32_t n[3], uint32_t v, int& vx, int& vy, int& vz) {
-    const uint32_t nx = (uint32_t)n[0], ny = (uint32_t)n[1];
-    const uint32_t rest = v / nx;
-    vx = (int)(v - rest * nx);
-    vz = (int)(rest / ny);
-    vy = (int)(rest - (uint32_t)vz * ny);
-    return vz < n[2];
+// Build tiles: a workgroup covers 64 (x, one per lane) x 4 (y, one per
+// wave) x kTileZ (z, looped) voxels of one configuration, so that each
+// wave reads a link's block corner and map once (scalar loads) for
+// kTileZ x 64 voxels and skips, with one uniform test, every link whose
+// block misses its tile.
+constexpr int kTileX = 64, kTileY = kBlock / 64, kTileZ = 8;
+
+struct Tile {
+    int vx, vy, z0;
+    bool lane_ok;        // this lane's x and the wave's y lie in the environment
+};
+
+__device__ inline Tile tile_of(const int32_t n[3]) {
+    const int tiles_x = (n[0] + kTileX - 1) / kTileX;
+    const int ty = (int)blockIdx.x / tiles_x;
+    const int tx = (int)blockIdx.x - ty * tiles_x;
+    Tile t;
+    t.vx = tx * kTileX + (int)(threadIdx.x & 63);
+    t.vy = ty * kTileY + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    t.z0 = (int)blockIdx.y * kTileZ;
+    t.lane_ok = t.vx < n[0] && t.vy < n[1];
+    return t;
 }
 
-// Grid: x over the voxels of one configuration, y over configurations
-// c0 + blockIdx.y.
+// Does the block [k, k + w) per axis meet this wave's tile (x over the
+// wave's 64 voxels, its y row, z over kTileZ levels)?  Wave-uniform.
+__device__ inline bool tile_meets(const Tile& t, const int32_t k[3], int w) {
+    const int x0 = t.vx - (int)(threadIdx.x & 63);
+    return k[0] < x0 + kTileX && k[0] + w > x0 && t.vy >= k[1] && t.vy < k[1] + w && k[2] < t.z0 + kTileZ &&
+           k[2] + w > t.z0;
+}
+
 template <bool CUBIC, int DT>
 __global__ __launch_bounds__(kBlock) void build_kernel(BuildArgs a, int32_t c0,
                                                        const typename GridT<DT>::T* __restrict__ grid) {
-    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
-    int vx, vy, vz;
-    if (!voxel_of(a.n, v, vx, vy, vz)) return;
-    const int c = c0 + (int)blockIdx.y;
-    const float x = (float)(a.lo[0] + ((double)vx + 0.5) * a.r);
-    const float y = (float)(a.lo[1] + ((double)vy + 0.5) * a.r);
-    const float z = (float)(a.lo[2] + ((double)vz + 0.5) * a.r);
-    const LinkBlock* bl = a.blocks + (int64_t)c * a.L;
-    float best = INFINITY;
-    for (int i = 0; i < a.L; ++i) {
-        const LinkBlock& b = bl[i];
-        const int w = 2 * a.halfw[i];
-        // only the links whose aligned block covers this voxel
-        if (vx < b.k[0] || vx >= b.k[0] + w || vy < b.k[1] || vy >= b.k[1] + w || vz < b.k[2] || vz >= b.k[2] + w)
-            continue;
-        const LinkGrid& lg = a.link[i];
-        best = fminf(best, lsdf::sample_or_inf<CUBIC, DT>(grid + lg.offset, lg, b.gm, x, y, z));
+    const Tile t = tile_of(a.n);
+    const int c = c0 + (int)blockIdx.z;
+    const float x = (float)(a.lo[0] + ((double)t.vx + 0.5) * a.r);
+    const float y = (float)(a.lo[1] + ((double)t.vy + 0.5) * a.r);
+    float zc[kTileZ], best[kTileZ];
+#pragma unroll
+    for (int dz = 0; dz < kTileZ; ++dz) {
+        zc[dz] = (float)(a.lo[2] + ((double)(t.z0 + dz) + 0.5) * a.r);
+        best[dz] = INFINITY;
     }
-    a.rs[(int64_t)c * ((int64_t)a.n[0] * a.n[1] * a.n[2]) + v] = best;
+    const LinkBlock* bl = a.blocks + (int64_t)c * a.L;
+    for (int i = 0; i < a.L; ++i) {
+        const LinkBlock b = bl[i];
+        const int w = 2 * a.halfw[i];
+        if (!tile_meets(t, b.k, w)) continue;
+        // only the voxels the link's aligned block covers
+        if (!(t.vx >= b.k[0] && t.vx < b.k[0] + w)) continue;
+        const LinkGrid& lg = a.link[i];
+#pragma unroll
+        for (int dz = 0; dz < kTileZ; ++dz) {
+            const int vz = t.z0 + dz;
+            if (vz >= b.k[2] && vz < b.k[2] + w)
+                best[dz] = fminf(best[dz], lsdf::sample_or_inf<CUBIC, DT>(grid + lg.offset, lg, b.gm, x, y, zc[dz]));
+        }
+    }
+    if (!t.lane_ok) return;
+    const int64_t V = (int64_t)a.n[0] * a.n[1] * a.n[2];
+    float* out = a.rs + (int64_t)c * V + ((int64_t)t.z0 * a.n[1] + t.vy) * a.n[0] + t.vx;
+#pragma unroll
+    for (int dz = 0; dz < kTileZ; ++dz)
+        if (t.z0 + dz < a.n[2]) out[(int64_t)dz * a.n[0] * a.n[1]] = best[dz];
 }
 
 // The same build with the transformation of Eq. 5: each block voxel's
@@ -167,39 +199,49 @@ __global__ __launch_bounds__(kBlock) void align_nn_kernel(BuildNNArgs a) {
 template <bool CUBIC, int DT>
 __global__ __launch_bounds__(kBlock) void build_nn_kernel(BuildNNArgs a, int32_t c0,
                                                           const typename GridT<DT>::T* __restrict__ grid) {
-    const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
-    int vx, vy, vz;
-    if (!voxel_of(a.n, v, vx, vy, vz)) return;
-    const int c = c0 + (int)blockIdx.y;
+    const Tile t = tile_of(a.n);
+    const int c = c0 + (int)blockIdx.z;
     const int w = 2 * a.m;
     const int64_t O = 3 * (int64_t)w * w * w;
     const float* W2 = a.params + LSDF_FRNN_HIDDEN * 10;
     const float* b2 = W2 + O * LSDF_FRNN_HIDDEN;
+    float best[kTileZ];
+#pragma unroll
+    for (int dz = 0; dz < kTileZ; ++dz) best[dz] = INFINITY;
     const LinkBlockNN* bl = a.blocks + (int64_t)c * a.L;
-    float best = INFINITY;
     for (int i = 0; i < a.L; ++i) {
         const LinkBlockNN& b = bl[i];
-        const int jx = vx - b.k[0], jy = vy - b.k[1], jz = vz - b.k[2];
-        if (jx < 0 || jx >= w || jy < 0 || jy >= w || jz < 0 || jz >= w) continue;
-        const int64_t o = 3 * (((int64_t)jz * w + jy) * w + jx);
-        float l[3];
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            const float* row = W2 + (o + ax) * LSDF_FRNN_HIDDEN;
-            float y = b2[o + ax];
-#pragma unroll
-            for (int u = 0; u < LSDF_FRNN_HIDDEN; ++u) y = fmaf(row[u], b.h[u], y);
-            l[ax] = a.er * (y + b.dtinv[ax]);
-        }
-        // link-frame point to centred grid coordinates: v_a = l_a invh_a + cen_a
+        if (!tile_meets(t, b.k, w)) continue;
+        const int jx = t.vx - b.k[0], jy = t.vy - b.k[1];
+        if (!(jx >= 0 && jx < w)) continue;
         const LinkGrid& lg = a.link[i];
+        // link-frame point to centred grid coordinates: v_a = l_a invh_a + cen_a
         lsdf::GridMap id{};
         id.m00 = lg.invh[0]; id.w0 = lg.cen[0];
         id.m11 = lg.invh[1]; id.w1 = lg.cen[1];
         id.m22 = lg.invh[2]; id.w2 = lg.cen[2];
-        best = fminf(best, lsdf::sample_or_inf<CUBIC, DT>(grid + lg.offset, lg, id, l[0], l[1], l[2]));
+        for (int dz = 0; dz < kTileZ; ++dz) {
+            const int jz = t.z0 + dz - b.k[2];
+            if (jz < 0 || jz >= w) continue;
+            const int64_t o = 3 * (((int64_t)jz * w + jy) * w + jx);
+            float l[3];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const float* row = W2 + (o + ax) * LSDF_FRNN_HIDDEN;
+                float yv = b2[o + ax];
+#pragma unroll
+                for (int u = 0; u < LSDF_FRNN_HIDDEN; ++u) yv = fmaf(row[u], b.h[u], yv);
+                l[ax] = a.er * (yv + b.dtinv[ax]);
+            }
+            best[dz] = fminf(best[dz], lsdf::sample_or_inf<CUBIC, DT>(grid + lg.offset, lg, id, l[0], l[1], l[2]));
+        }
     }
-    a.rs[(int64_t)c * ((int64_t)a.n[0] * a.n[1] * a.n[2]) + v] = best;
+    if (!t.lane_ok) return;
+    const int64_t V = (int64_t)a.n[0] * a.n[1] * a.n[2];
+    float* out = a.rs + (int64_t)c * V + ((int64_t)t.z0 * a.n[1] + t.vy) * a.n[0] + t.vx;
+#pragma unroll
+    for (int dz = 0; dz < kTileZ; ++dz)
+        if (t.z0 + dz < a.n[2]) out[(int64_t)dz * a.n[0] * a.n[1]] = best[dz];
 }
 
 struct RuntimeArgs {
@@ -371,10 +413,11 @@ LSDF_API int lsdf_robot_sdf_build(const float* link_T, int32_t C, int32_t L, con
     const int64_t CL = (int64_t)C * L;
     hipLaunchKernelGGL(align_kernel, dim3((unsigned)((CL + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
     if ((rc = check_launch("robot_sdf_build (align)")) != LSDF_OK) return rc;
-    // x: the voxels of one configuration, y: up to 65535 configurations per launch
+    // x, y: the tiles of one configuration, z: up to 65535 configurations per launch
     const dim3 bd(kBlock);
     for (int32_t c0 = 0; c0 < C; c0 += 65535) {
-        const dim3 gd((unsigned)((V + kBlock - 1) / kBlock), (unsigned)std::min<int32_t>(65535, C - c0));
+        const dim3 gd((unsigned)(((env->n[0] + kTileX - 1) / kTileX) * ((env->n[1] + kTileY - 1) / kTileY)),
+                      (unsigned)((env->n[2] + kTileZ - 1) / kTileZ), (unsigned)std::min<int32_t>(65535, C - c0));
         switch (dtype * 2 + (cubic ? 1 : 0)) {
             case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((build_kernel<true, LSDF_F32>), gd, bd, 0, s, a, c0, static_cast<const float*>(grid_buf)); break;
             case LSDF_F32 * 2: hipLaunchKernelGGL((build_kernel<false, LSDF_F32>), gd, bd, 0, s, a, c0, static_cast<const float*>(grid_buf)); break;
@@ -437,10 +480,11 @@ LSDF_API int lsdf_robot_sdf_build_frnn(const float* link_T, int32_t C, int32_t L
     const int64_t CL = (int64_t)C * L;
     hipLaunchKernelGGL(align_nn_kernel, dim3((unsigned)((CL + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a);
     if ((rc = check_launch("robot_sdf_build_frnn (align)")) != LSDF_OK) return rc;
-    // x: the voxels of one configuration, y: up to 65535 configurations per launch
+    // x, y: the tiles of one configuration, z: up to 65535 configurations per launch
     const dim3 bd(kBlock);
     for (int32_t c0 = 0; c0 < C; c0 += 65535) {
-        const dim3 gd((unsigned)((V + kBlock - 1) / kBlock), (unsigned)std::min<int32_t>(65535, C - c0));
+        const dim3 gd((unsigned)(((env->n[0] + kTileX - 1) / kTileX) * ((env->n[1] + kTileY - 1) / kTileY)),
+                      (unsigned)((env->n[2] + kTileZ - 1) / kTileZ), (unsigned)std::min<int32_t>(65535, C - c0));
         switch (dtype * 2 + (cubic ? 1 : 0)) {
             case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((build_nn_kernel<true, LSDF_F32>), gd, bd, 0, s, a, c0, static_cast<const float*>(grid_buf)); break;
             case LSDF_F32 * 2: hipLaunchKernelGGL((build_nn_kernel<false, LSDF_F32>), gd, bd, 0, s, a, c0, static_cast<const float*>(grid_buf)); break;

@@ -85,7 +85,7 @@ def test_exact_network_and_robot_sdf_build(B, orc, tiny, tiny_grids):
     """The hand-built exact network: FP32-sized error, and Robot SDFs built
     through it agree with the exact build."""
     r = 1.0 / 16.0
-    lo, n = (-1.5, -1.5, -1.5), (48, 48, 40)
+    lo, n = (-1.5, -1.5, -1.5), (50, 46, 37)
     far = max(np.linalg.norm(np.array([[x, y, z] for x in (tiny.grid_lo[i, 0], tiny.grid_hi[i, 0])
                                        for y in (tiny.grid_lo[i, 1], tiny.grid_hi[i, 1])
                                        for z in (tiny.grid_lo[i, 2], tiny.grid_hi[i, 2])]), axis=1).max()

@@ -22,7 +22,7 @@ pytestmark = pytest.mark.gpu
 
 R_SMALL = 1.0 / 16.0
 LO_SMALL = (-1.5, -1.5, -1.5)
-N_SMALL = (48, 48, 40)          # non-cubic on purpose
+N_SMALL = (50, 46, 37)          # non-cubic, and not whole build tiles, on purpose
 
 
 def say(*a):
