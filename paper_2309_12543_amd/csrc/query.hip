@@ -53,7 +53,10 @@ using lsdf::inside;
 using lsdf::interpolate;
 using lsdf::locate;
 
-constexpr int kBlock = 256;
+#ifndef LSDF_QUERY_BLOCK
+#define LSDF_QUERY_BLOCK 256         // threads per workgroup of the query kernel
+#endif
+constexpr int kBlock = LSDF_QUERY_BLOCK;
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kXcds = 8;
 constexpr float kFar = 1e30f;       // centred coordinate of unused lanes: never inside
@@ -96,7 +99,7 @@ struct TrajPlan {
     int64_t m_lo, m_hi;        // points [m_lo, m_hi) of the concatenated cloud
     int32_t c_lo, c_n;         // configurations [c_lo, c_lo + c_n)
     int32_t cgroups;           // ceil(c_n / 64)
-    int32_t chunks_per_group;  // ceil(8-point blocks touched / chunk_blocks)
+    int32_t chunks_per_group;  // ceil(quads of 4 blocks touched / chunk_quads)
     int32_t pad[2];
 };
 static_assert(sizeof(TrajPlan) == 48, "plan entry layout");
@@ -108,7 +111,7 @@ struct QueryArgs {
     int32_t C;
     int32_t K;               // trajectories
     int32_t L;
-    int32_t chunk_blocks;    // 8-point blocks per chunk
+    int32_t chunk_quads;     // quads (4 blocks of 8 points) per chunk
     int32_t blocks_per_xcd;
     int32_t schedule;        // LSDF_SCHED_*
 };
@@ -135,7 +138,7 @@ struct PrepArgs {
     int32_t C;
     int32_t K;
     int32_t L;
-    int32_t chunk_blocks;
+    int32_t chunk_quads;
 };
 
 struct FinalizeArgs {
@@ -292,9 +295,12 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
         const int c = c_lo + cl;
         const LinkGrid& lg = p.link[i];
         const typename E::T* __restrict__ G = grid + lg.offset;
-        // the chunk's 8-point blocks (aligned in the concatenated cloud)
-        const int64_t jb0 = ((m_lo >> 3) + mc * p.chunk_blocks) * kBlockPts;
-        const int64_t jb1 = min(m_hi, jb0 + (int64_t)p.chunk_blocks * kBlockPts);
+        // the trajectory's 8-point blocks (aligned in the concatenated
+        // cloud) form quads of 4; chunk mc takes every cpg-th quad from quad
+        // mc, so that points near a link, which lie together in the cloud,
+        // spread over the chunks rather than piling onto a few waves
+        const int64_t blk0 = m_lo >> 3;
+        const int64_t nblk = ((m_hi + kBlockPts - 1) >> 3) - blk0;
 
         // this lane's map v = M [x; y; z] + w (centred grid coordinates) and
         // its culling thresholds, from the table the first kernel built;
@@ -317,21 +323,22 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
         const int nxy = lg.n[0] * lg.n[1];
 
         float best = INFINITY;
-        for (int64_t jb = jb0; jb < jb1; jb += kSphereBatch * kBlockPts) {
-            // the spheres of up to 4 blocks are loaded together (the sphere
-            // array has kSphereBatch - 1 spare entries past its end); a sphere
-            // bounds all 8 points of its block, so also the trajectory's share
-            // of a block it shares with its neighbour
+        for (int64_t qd = mc * kSphereBatch; qd < nblk; qd += (int64_t)cpg * kSphereBatch) {
+            // the spheres of the quad's blocks are loaded together (the
+            // sphere array has kSphereBatch - 1 spare entries past its end); a
+            // sphere bounds all 8 points of its block, so also the
+            // trajectory's share of a block it shares with its neighbour
+            const int64_t jb = (blk0 + qd) * kBlockPts;
             uint32_t near_mask = 0;
 #pragma unroll
             for (int u = 0; u < kSphereBatch; ++u) {
-                const float4 sph = spheres[jb / kBlockPts + u];
+                const float4 sph = spheres[blk0 + qd + u];
                 const float s0 = fmaf(m00, sph.x, fmaf(m01, sph.y, fmaf(m02, sph.z, w0)));
                 const float s1 = fmaf(m10, sph.x, fmaf(m11, sph.y, fmaf(m12, sph.z, w1)));
                 const float s2 = fmaf(m20, sph.x, fmaf(m21, sph.y, fmaf(m22, sph.z, w2)));
                 const bool near = (fabsf(s0) <= fmaf(nr0, sph.w, k0)) & (fabsf(s1) <= fmaf(nr1, sph.w, k1)) &
                                   (fabsf(s2) <= fmaf(nr2, sph.w, k2));
-                if (__ballot(near) && jb + u * kBlockPts < jb1) near_mask |= 1u << u;
+                if (__ballot(near) && qd + u < nblk) near_mask |= 1u << u;
             }
             while (near_mask) {   // wave-uniform: blocks some lane's box may reach
                 const int u = __builtin_ctz(near_mask);
@@ -439,7 +446,8 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
             e.c_n = c1 - c0;
             e.cgroups = (e.c_n + 63) / 64;
             const int64_t nb = m1 > m0 ? ((m1 + kBlockPts - 1) / kBlockPts) - m0 / kBlockPts : 0;
-            e.chunks_per_group = (int32_t)((nb + a.chunk_blocks - 1) / a.chunk_blocks);
+            const int64_t nq = (nb + kSphereBatch - 1) / kSphereBatch;
+            e.chunks_per_group = (int32_t)((nq + a.chunk_quads - 1) / a.chunk_quads);
             n = (int64_t)a.L * e.cgroups * e.chunks_per_group;
         }
         scan[t] = n;
@@ -640,7 +648,7 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
     p.C = C;
     p.K = K;
     p.L = L;
-    p.chunk_blocks = chunk_blocks;
+    p.chunk_quads = (chunk_blocks + kSphereBatch - 1) / kSphereBatch;
     p.schedule = schedule;
     // the first kernel runs when there are points to test, or when poses
     // computed from joint angles are asked for
@@ -664,7 +672,7 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
         a.C = C;
         a.K = K;
         a.L = L;
-        a.chunk_blocks = chunk_blocks;
+        a.chunk_quads = p.chunk_quads;
         const int64_t nsph = (M + kBlockPts - 1) / kBlockPts;
         const int64_t threads = std::max<int64_t>(nsph, (int64_t)C * L);
         hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
@@ -677,8 +685,8 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
         // given by C and M), no more waves than chunks
         int64_t blocks = (int64_t)cus * blocks_per_cu;
         if (!c_off) {
-            const int64_t nb = (M + kBlockPts - 1) / kBlockPts;
-            const int64_t chunks = (int64_t)L * ((C + 63) / 64) * ((nb + chunk_blocks - 1) / chunk_blocks);
+            const int64_t nq = ((M + kBlockPts - 1) / kBlockPts + kSphereBatch - 1) / kSphereBatch;
+            const int64_t chunks = (int64_t)L * ((C + 63) / 64) * ((nq + p.chunk_quads - 1) / p.chunk_quads);
             blocks = std::min<int64_t>(blocks, (chunks + kWavesPerBlock - 1) / kWavesPerBlock);
         }
         blocks = (blocks + kXcds - 1) / kXcds * kXcds;
