@@ -462,6 +462,8 @@ def main():
                     help="training steps of the grid-transformation network (0 skips that variant)")
     ap.add_argument("--frnn-rotations", type=int, default=100000,
                     help="random rotations of its max-error test (the paper uses 10^7)")
+    ap.add_argument("--only", choices=["learned", "precision", "batched", "robot-sdf", "frnn"], default=None,
+                    help="run only this variant (for profiling) and print its record as one JSON line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB mebibytes (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -487,6 +489,14 @@ def main():
         log(f"copy probe: 5 copies of {args.copy_probe} MiB")
         return
     lsdf.load_library()
+    if args.only:
+        only = {"learned": lambda: learned_variant(dev, args.learned_epochs, args.learned_steps),
+                "precision": lambda: precision_variant(dev, 50),
+                "batched": lambda: batched_variant(dev, 20, 3),
+                "robot-sdf": lambda: robot_sdf_variant(dev, 50),
+                "frnn": lambda: frnn_variant(dev, args.frnn_steps, args.frnn_rotations)}
+        print(json.dumps({"variant": args.only, **only[args.only]()}), flush=True)
+        return
     w = synth.make_workload(args.workload)
     log(f"workload {w.name}: C={w.C} M={w.M} L={w.L} n={int(w.grid_n[0, 0])}")
     gs = lsdf.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device=dev)

@@ -408,18 +408,28 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
     }
     const int64_t j0 = b * kBlockPts;
     if (j0 < a.M) {
-        const float* points = a.points;
-        const int64_t j1 = min(a.M, j0 + kBlockPts);
-        float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
-        for (int64_t j = j0; j < j1; ++j) {
-            lo0 = fminf(lo0, points[3 * j + 0]); hi0 = fmaxf(hi0, points[3 * j + 0]);
-            lo1 = fminf(lo1, points[3 * j + 1]); hi1 = fmaxf(hi1, points[3 * j + 1]);
-            lo2 = fminf(lo2, points[3 * j + 2]); hi2 = fmaxf(hi2, points[3 * j + 2]);
+        // the block's points, loaded together; past the end of the cloud the
+        // last point repeats, which changes neither the box nor the radius
+        float x[kBlockPts], y[kBlockPts], z[kBlockPts];
+#pragma unroll
+        for (int k = 0; k < kBlockPts; ++k) {
+            const int64_t j = min(j0 + k, a.M - 1);
+            x[k] = a.points[3 * j + 0];
+            y[k] = a.points[3 * j + 1];
+            z[k] = a.points[3 * j + 2];
+        }
+        float lo0 = x[0], lo1 = y[0], lo2 = z[0], hi0 = x[0], hi1 = y[0], hi2 = z[0];
+#pragma unroll
+        for (int k = 1; k < kBlockPts; ++k) {
+            lo0 = fminf(lo0, x[k]); hi0 = fmaxf(hi0, x[k]);
+            lo1 = fminf(lo1, y[k]); hi1 = fmaxf(hi1, y[k]);
+            lo2 = fminf(lo2, z[k]); hi2 = fmaxf(hi2, z[k]);
         }
         const float cx = 0.5f * (lo0 + hi0), cy = 0.5f * (lo1 + hi1), cz = 0.5f * (lo2 + hi2);
         float r2 = 0.0f;
-        for (int64_t j = j0; j < j1; ++j) {
-            const float dx = points[3 * j + 0] - cx, dy = points[3 * j + 1] - cy, dz = points[3 * j + 2] - cz;
+#pragma unroll
+        for (int k = 0; k < kBlockPts; ++k) {
+            const float dx = x[k] - cx, dy = y[k] - cy, dz = z[k] - cz;
             r2 = fmaxf(r2, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
         }
         const float r = sqrtf(r2);
