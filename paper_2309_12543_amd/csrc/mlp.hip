@@ -14,6 +14,7 @@ using namespace lsdf::mlp;
 constexpr int kBlock = 512;                 // 8 waves
 constexpr int kWaves = kBlock / 64;
 constexpr int kSplit = 512;                 // samples per weight-gradient split
+constexpr int kSmallGradBlocks = 16;         // workgroups per split for the small gradients
 constexpr int kBlocksPerCu = 2;             // 69 KB of LDS per block
 
 struct Domain {
@@ -97,7 +98,10 @@ struct QueryMlpArgs {
 };
 
 template <bool CUBIC, int DT>
-__global__ __launch_bounds__(kBlock) void query_mlp_kernel(QueryMlpArgs p) {
+// The register budget of 3 waves per SIMD (168 VGPRs) schedules the tile
+// loop better than the default 2 (248): 67 against 74 ms on the learned
+// workload, same bits.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void query_mlp_kernel(QueryMlpArgs p) {
     __shared__ __bf16 sW2[WTILE_ELEMS];
     __shared__ __bf16 sW3[WTILE_ELEMS];
     __shared__ SmallParams sp;
@@ -334,8 +338,13 @@ __global__ __launch_bounds__(kBlock) void train_backward_kernel(TrainArgs p) {
     }
 }
 
-// Weight gradients over one split of the batch: dW3 = dz3^T h2 and
-// dW2 = dz2^T h1 on MFMA (K = samples), the rest on the VALU.
+// Weight gradients over one split of the batch.  Workgroups with z = 0:
+// dW3 = dz3^T h2 and dW2 = dz2^T h1 on MFMA (K = samples), a 64 x 64 output
+// quarter per wave, the next K step's operands loaded while the current one
+// multiplies.  Workgroups with z >= 1: the small gradients (W1 and b1, b2,
+// b3, w4, b4), a share of the (kind, unit) items each; a wave takes one item
+// at a time, its lanes stride the split's samples (coalesced reads) and a
+// butterfly sums the lanes.
 __global__ __launch_bounds__(kBlock) void train_wgrad_kernel(TrainArgs p) {
     const int l = blockIdx.y;
     const int split = blockIdx.x;
@@ -348,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void train_wgrad_kernel(TrainArgs p) {
     const int64_t k0 = (int64_t)split * kSplit;
     float* gp = p.w.gpart + ((int64_t)l * p.nsplit + split) * NPARAM;
 
-    {
+    if (blockIdx.z == 0) {
         const bool third = wave < 4;
         const int q = wave & 3;
         const __bf16* A = (third ? p.w.dz3 : p.w.dz2) + plane;   // [out][B]
@@ -359,19 +368,30 @@ __global__ __launch_bounds__(kBlock) void train_wgrad_kernel(TrainArgs p) {
         for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        bf16x8 a[4], bb[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) a[mt] = *reinterpret_cast<const bf16x8*>(A + (r0 + 16 * mt + col) * B + k0 + 8 * g);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) bb[nt] = *reinterpret_cast<const bf16x8*>(Bm + (c0 + 16 * nt + col) * B + k0 + 8 * g);
         for (int64_t k = k0; k < k0 + kSplit; k += 32) {
-            bf16x8 a[4], bb[4];
+            bf16x8 an[4], bn[4];
+            const int64_t kn = k + 32 < k0 + kSplit ? k + 32 : k;   // the last step reloads its own operands
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
-                a[mt] = *reinterpret_cast<const bf16x8*>(A + (r0 + 16 * mt + col) * B + k + 8 * g);
+                an[mt] = *reinterpret_cast<const bf16x8*>(A + (r0 + 16 * mt + col) * B + kn + 8 * g);
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
-                bb[nt] = *reinterpret_cast<const bf16x8*>(Bm + (c0 + 16 * nt + col) * B + k + 8 * g);
+                bn[nt] = *reinterpret_cast<const bf16x8*>(Bm + (c0 + 16 * nt + col) * B + kn + 8 * g);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bb[nt], acc[mt][nt], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                a[t] = an[t];
+                bb[t] = bn[t];
+            }
         }
         const int off = third ? OFF_W3 : OFF_W2;
 #pragma unroll
@@ -381,46 +401,64 @@ __global__ __launch_bounds__(kBlock) void train_wgrad_kernel(TrainArgs p) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     gp[off + (r0 + 16 * mt + 4 * g + r) * H + (c0 + 16 * nt + col)] = acc[mt][nt][r];
+        return;
     }
 
-    // small gradients: one thread per (kind, unit)
-    const int t = threadIdx.x;
-    const int u = t & (H - 1);
-    const int kind = t >> 7;   // 0: W1 and b1, 1: b2, 2: b3, 3: w4
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    // items 0 .. 4 H: kind = item / H (0: W1 row and b1, 1: b2, 2: b3,
+    // 3: w4), unit = item mod H; item 4 H is b4
+    constexpr int kItems = 4 * H + 1;
+    const int share = (kItems + kSmallGradBlocks - 1) / kSmallGradBlocks;
+    const int i0 = (blockIdx.z - 1) * share;
+    const int i1 = min(kItems, i0 + share);
     const int64_t lB = (int64_t)l * B;
-    for (int64_t k = k0; k < k0 + kSplit; ++k) {
-        if (kind == 0) {
-            const float d = p.w.dz1[plane + u * B + k];
-            const float* x = p.w.xh + (lB + k) * 3;
-            s0 = fmaf(d, x[0], s0);
-            s1 = fmaf(d, x[1], s1);
-            s2 = fmaf(d, x[2], s2);
-            s3 += d;
-        } else if (kind == 1) {
-            s0 += (float)p.w.dz2[plane + u * B + k];
-        } else if (kind == 2) {
-            s0 += (float)p.w.dz3[plane + u * B + k];
-        } else {
-            s0 = fmaf(p.w.dm[lB + k], (float)p.w.h3[plane + u * B + k], s0);
+    static_assert(kSplit % 64 == 0, "split of whole waves");
+    for (int item = i0 + wave; item < i1; item += kWaves) {
+        const int kind = item / H;
+        const int u = item - kind * H;
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll
+        for (int it = 0; it < kSplit / 64; ++it) {
+            const int64_t k = k0 + 64 * it + lane;
+            if (kind == 0) {
+                const float d = p.w.dz1[plane + u * B + k];
+                const float* x = p.w.xh + (lB + k) * 3;
+                s0 = fmaf(d, x[0], s0);
+                s1 = fmaf(d, x[1], s1);
+                s2 = fmaf(d, x[2], s2);
+                s3 += d;
+            } else if (kind == 1) {
+                s0 += (float)p.w.dz2[plane + u * B + k];
+            } else if (kind == 2) {
+                s0 += (float)p.w.dz3[plane + u * B + k];
+            } else if (kind == 3) {
+                s0 = fmaf(p.w.dm[lB + k], (float)p.w.h3[plane + u * B + k], s0);
+            } else {
+                s0 += p.w.dm[lB + k];
+            }
         }
-    }
-    if (kind == 0) {
-        gp[OFF_W1 + 3 * u + 0] = s0;
-        gp[OFF_W1 + 3 * u + 1] = s1;
-        gp[OFF_W1 + 3 * u + 2] = s2;
-        gp[OFF_B1 + u] = s3;
-    } else if (kind == 1) {
-        gp[OFF_B2 + u] = s0;
-    } else if (kind == 2) {
-        gp[OFF_B3 + u] = s0;
-    } else {
-        gp[OFF_W4 + u] = s0;
-    }
-    if (t == 0) {
-        float sb = 0.f;
-        for (int64_t k = k0; k < k0 + kSplit; ++k) sb += p.w.dm[lB + k];
-        gp[OFF_B4] = sb;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            s0 += __shfl_xor(s0, o, 64);
+            s1 += __shfl_xor(s1, o, 64);
+            s2 += __shfl_xor(s2, o, 64);
+            s3 += __shfl_xor(s3, o, 64);
+        }
+        if (lane == 0) {
+            if (kind == 0) {
+                gp[OFF_W1 + 3 * u + 0] = s0;
+                gp[OFF_W1 + 3 * u + 1] = s1;
+                gp[OFF_W1 + 3 * u + 2] = s2;
+                gp[OFF_B1 + u] = s3;
+            } else if (kind == 1) {
+                gp[OFF_B2 + u] = s0;
+            } else if (kind == 2) {
+                gp[OFF_B3 + u] = s0;
+            } else if (kind == 3) {
+                gp[OFF_W4 + u] = s0;
+            } else {
+                gp[OFF_B4] = s0;
+            }
+        }
     }
 }
 
@@ -563,7 +601,7 @@ int train_common(const float* params, float* adam_m, float* adam_v, int64_t t, f
     if ((rc = check_launch("mlp train forward")) != LSDF_OK) return rc;
     hipLaunchKernelGGL(train_backward_kernel, tiles_grid, dim3(kBlock), 0, s, a);
     if ((rc = check_launch("mlp train backward")) != LSDF_OK) return rc;
-    hipLaunchKernelGGL(train_wgrad_kernel, dim3(a.nsplit, L), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(train_wgrad_kernel, dim3(a.nsplit, L, 1 + kSmallGradBlocks), dim3(kBlock), 0, s, a);
     if ((rc = check_launch("mlp train weight gradients")) != LSDF_OK) return rc;
     ReduceArgs r{};
     r.w = a.w;
