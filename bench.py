@@ -195,7 +195,38 @@ def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 8):
         "train_epochs": epochs,
         "train_samples_per_link": n,
         "final_train_l1_mm": [round(1e3 * float(x), 2) for x in hist[-1]],
+        **learned_pair_stats(w, T, pts, params, cen, half, margin=0.05),
     }
+
+
+def learned_pair_stats(w, T, pts, params, cen, half, margin: float, sample: int = 1 << 20, seed: int = 7):
+    """On a seeded sample of (waypoint, point) pairs per link: the fraction
+    inside the network's domain, and among those the fraction whose network
+    value falls below the margin (the pairs that take the exact grid value)."""
+    import torch
+
+    from paper_2309_12543_amd import lsdf
+
+    gen = torch.Generator().manual_seed(seed)
+    ci = torch.randint(0, w.C, (sample,), generator=gen).to(pts.device)
+    ji = torch.randint(0, w.M, (sample,), generator=gen).to(pts.device)
+    x = pts[ji]
+    n_dom = n_fb = 0
+    for i in range(w.L):
+        R = T[ci, i, :, :3]
+        d = x - T[ci, i, :, 3]
+        lp = (R * d[:, :, None]).sum(dim=1)          # R^T (x - t)
+        c = torch.as_tensor(cen[i], dtype=torch.float32, device=pts.device)
+        h = torch.as_tensor(half[i], dtype=torch.float32, device=pts.device)
+        inside = ((lp - c).abs() <= h).all(dim=1)
+        lpi = lp[inside].contiguous()
+        n_dom += int(lpi.shape[0])
+        if lpi.shape[0]:
+            m = lsdf.mlp_eval(params[i].contiguous(), (cen[i:i + 1], half[i:i + 1]), lpi)
+            n_fb += int((m < margin).sum().item())
+    return {"pair_sample_per_link": sample,
+            "in_domain_pair_fraction": round(n_dom / (sample * w.L), 4),
+            "fallback_fraction_of_in_domain": round(n_fb / max(1, n_dom), 5)}
 
 
 def precision_variant(dev, steps: int, judge_waypoints: int = 16):
@@ -280,9 +311,12 @@ def batched_variant(dev, steps: int, warmup: int):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(steps):
-            one(True)
+            one(False)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t1) * 1e3 / steps
+        for _ in range(steps):       # instrumented pass: events around the query kernel
+            one(True)
+        torch.cuda.synchronize()
         kms = float(np.mean([a.elapsed_time(b) for a, b in kev]))
         res[name] = {"ms_per_step": round(ms, 4), "query_kernel_ms": round(kms, 4), "out": out}
     sg = StepGraph(w.robot.dh, w.robot.base_T, gs, w.C, w.M, w.K, tuning=best)
@@ -518,19 +552,22 @@ def main():
         a.record()
         b.record()
 
-    def step_separate(k=None):
+    # The timed steps carry no events: an event recorded between two kernels
+    # of the step adds a few µs to it.  Separate instrumented passes record
+    # events around the query call and around the query kernel alone.
+    def step_separate(k=None, instrument=False):
         # lsdf_fk_batch, then lsdf_query_min_distance
         lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T, out=T)
-        if k is not None:
+        if instrument and k is not None:
             call_ev[k][0].record()
             lsdf.set_kernel_events(*kern_ev[k])
         lsdf.query_min_distance(T, gs, pts, workspace=ws, out=(dist, link, None))
-        if k is not None:
+        if instrument and k is not None:
             call_ev[k][1].record()
 
-    def step_fused(k=None):
+    def step_fused(k=None, instrument=False):
         # lsdf_query_from_joints: the kinematics inside the query's first kernel
-        if k is not None:
+        if instrument and k is not None:
             lsdf.set_kernel_events(*kern_ev[args.steps + k])
         lsdf.query_from_joints(w.robot.dh, q, gs, pts, base_T=w.robot.base_T, link_T=T, workspace=ws,
                                out=(dist, link, None))
@@ -550,6 +587,9 @@ def main():
     d_sep, l_sep = dist.clone(), link.clone()
     ms_per_step = run(step_fused)
     fused_same = bool(torch.equal(dist.view(torch.int32), d_sep.view(torch.int32)) and torch.equal(link, l_sep))
+    log("instrumented passes (events around the query call and kernel)")
+    sep_ev_ms = run(lambda k=None: step_separate(k, instrument=True))
+    fused_ev_ms = run(lambda k=None: step_fused(k, instrument=True))
     call_ms = float(np.mean([a.elapsed_time(b) for a, b in call_ev]))
     kernel_ms_sep = float(np.mean([a.elapsed_time(b) for a, b in kern_ev[:args.steps]]))
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in kern_ev[args.steps:]]))
@@ -561,9 +601,28 @@ def main():
     sg = StepGraph(w.robot.dh, w.robot.base_T, gs, w.C, w.M, 1)
     sg.load(q, pts, torch.tensor([0, w.C], dtype=torch.int32, device=dev),
             torch.tensor([0, w.M], dtype=torch.int64, device=dev))
-    graph_ms = time_calls(sg.replay, args.steps, args.warmup)
+    graph_ms = run(lambda k=None: sg.replay())
     same = bool(torch.equal(sg.dist.view(torch.int32), d_sep.view(torch.int32)) and torch.equal(sg.link, l_sep))
     del sg
+
+    # warm grids, cold points: every step reads its own copy of the cloud,
+    # from a pool larger than the Infinity Cache (256 MB), so the points come
+    # from HBM while the grids stay cached
+    n_cold = max(args.steps + args.warmup, (300 << 20) // (w.M * 12) + 1)
+    cold = torch.empty((n_cold, w.M, 3), dtype=torch.float32, device=dev)
+    cold[:] = pts
+    ck = [0]
+
+    def step_cold():
+        lsdf.query_from_joints(w.robot.dh, q, gs, cold[ck[0] % n_cold], base_T=w.robot.base_T, link_T=T,
+                               workspace=ws, out=(dist, link, None))
+        ck[0] += 1
+
+    cold_ms = run(lambda k=None: step_cold())
+    cold_same = bool(torch.equal(dist.view(torch.int32), d_sep.view(torch.int32)))
+    del cold
+    call_q = np.percentile([a.elapsed_time(b) for a, b in call_ev], [5, 50, 95])
+    kern_q = np.percentile([a.elapsed_time(b) for a, b in kern_ev[args.steps:]], [5, 50, 95])
 
     Tn = T.cpu().numpy()
     tests, surv_pairs, inbox = culled_work(Tn, w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64), w.points)
@@ -588,8 +647,14 @@ def main():
                    "parallelism": "single GPU"},
         "step": "lsdf_query_from_joints: kinematics in the query's first kernel, then the query and finalize kernels",
         "separate_calls_ms_per_step": round(sep_ms, 5),
+        "instrumented_ms_per_step": {"separate_calls": round(sep_ev_ms, 5), "fused": round(fused_ev_ms, 5)},
         "separate_calls_equal_fused": fused_same,
         "query_call_ms": round(call_ms, 5),
+        "query_call_ms_p5_p50_p95": [round(float(v), 5) for v in call_q],
+        "query_kernel_ms_p5_p50_p95": [round(float(v), 5) for v in kern_q],
+        "cold_points_ms_per_step": round(cold_ms, 5),
+        "cold_points_cloud_copies": n_cold,
+        "cold_points_equal": cold_same,
         "query_kernel_ms": round(kernel_ms, 5),
         "query_kernel_ms_separate_calls": round(kernel_ms_sep, 5),
         "graph_replay_ms_per_step": round(graph_ms, 5),
