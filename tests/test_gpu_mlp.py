@@ -192,3 +192,32 @@ def test_query_mlp_no_fallback_matches_twin(B, orc, tiny, tiny_grids):
             ind = np.all(np.abs(X) <= 1.0, axis=1)
             want = orc.mlp_forward(P[i].astype(np.float64), X[ind], bf16=True).min() if ind.any() else np.inf
             assert abs(ld[c, i] - want) <= TOL_EVAL * max(1.0, abs(want)), (c, i, ld[c, i], want)
+
+
+def test_query_mlp_learned_scale_sampled(B, orc):
+    """The learned workload at full size (500 waypoints x 100,000 points x 7
+    links) in the launch configuration the benchmark times, margin -inf (every
+    in-domain pair takes the network value): sampled per-link minima against
+    the twin network over all of that link's in-domain points."""
+    w = synth.make_workload("learned")
+    cen, half = domains_of(w)
+    gs = B.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device="cuda")
+    T32 = orc.fk(w.robot.dh, w.q, w.robot.base_T).astype(np.float32)
+    pts = w.points.astype(np.float32)
+    P = params_f32(7, 6)
+    say(f"query_mlp learned scale C={w.C} M={w.M} margin=-inf")
+    d, l, ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half), dev(pts), margin=float("-inf"),
+                                        link_dist=True)
+    ld = ld.cpu().numpy().astype(np.float64)
+    assert np.isfinite(ld).mean() > 0.5
+    for c, i in [(0, 1), (123, 4), (377, 6), (499, 3)]:
+        R, t = T32[c, i, :, :3].astype(np.float64), T32[c, i, :, 3].astype(np.float64)
+        X = ((pts.astype(np.float64) - t) @ R - cen[i]) / half[i]
+        ind = np.all(np.abs(X) <= 1.0, axis=1)
+        want = orc.mlp_forward(P[i].astype(np.float64), X[ind], bf16=True).min() if ind.any() else np.inf
+        say(f"  c={c} link={i}: {ind.sum()} in-domain points, gpu {ld[c, i]:.6g} twin {want:.6g}")
+        assert abs(ld[c, i] - want) <= TOL_EVAL * max(1.0, abs(want)), (c, i, ld[c, i], want)
+    # per-waypoint results are the minima over links (lowest link on ties)
+    dn, ln = d.cpu().numpy().astype(np.float64), l.cpu().numpy()
+    want_l = np.where(np.isfinite(ld.min(axis=1)), ld.argmin(axis=1), -1)
+    assert np.array_equal(dn, ld.min(axis=1)) and np.array_equal(ln, want_l)
