@@ -97,24 +97,34 @@ def oracle_grids(w):
 
 def cpu_baseline(w, budget_s: float = 12.0):
     """The CPU oracle (double-precision kinematics + query) on the same
-    workload, repeated for about budget_s seconds."""
+    workload, repeated for about budget_s seconds on all the host's threads,
+    then three batches on one thread (median)."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    log(f"cpu baseline ({threads} threads)")
     grids = oracle_grids(w)
-    reps, t_total = 0, 0.0
-    while t_total < budget_s and reps < 200:
+
+    def batch():
         t0 = time.perf_counter()
         T = oracle.fk(w.robot.dh, w.q, w.robot.base_T)
         cl = oracle.query_f64(T, w.grid_lo, w.grid_hi, w.grid_n, grids, w.points)
         oracle.reduce(cl)
-        t_total += time.perf_counter() - t0
+        return time.perf_counter() - t0
+
+    threads = oracle.max_threads()
+    log(f"cpu baseline ({threads} threads)")
+    reps, t_total = 0, 0.0
+    while t_total < budget_s and reps < 200:
+        t_total += batch()
         reps += 1
     sec = t_total / reps
+    oracle.set_threads(1)
+    one = float(np.median([batch() for _ in range(3)]))
+    oracle.set_threads(threads)
     return {"value": round(w.C * w.M * w.L / sec / 1e9, 4), "unit": "G point-link queries/s",
             "ms_per_batch": round(sec * 1e3, 3), "cores": threads, "kind": "oracle",
             "sample": f"full {w.name} batch (C={w.C}, M={w.M}, L={w.L}) repeated {reps}x; "
-                      "double-precision kinematics + query, OpenMP over waypoints"}
+                      "double-precision kinematics + query, OpenMP over waypoints",
+            "single_thread": {"ms_per_batch": round(one * 1e3, 3),
+                              "value": round(w.C * w.M * w.L / one / 1e9, 4), "sample": "median of 3 full batches"}}
 
 
 def time_calls(fn, steps, warmup):

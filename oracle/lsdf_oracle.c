@@ -35,6 +35,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 #define ORC_EXPORT __attribute__((visibility("default")))
 
@@ -71,6 +72,10 @@ static double dist_point_segment(const double p[3], const double a[3], const dou
     double q[3] = {a[0] + t * ab[0] - p[0], a[1] + t * ab[1] - p[1], a[2] + t * ab[2] - p[2]};
     return v_norm(q);
 }
+
+/* Threads of the OpenMP loops (the timing harness measures one and all). */
+ORC_EXPORT void orc_set_threads(int32_t n) { omp_set_num_threads(n > 0 ? n : 1); }
+ORC_EXPORT int32_t orc_max_threads(void) { return (int32_t)omp_get_max_threads(); }
 
 ORC_EXPORT double orc_point_triangle_distance(const double* p, const double* a,
                                               const double* b, const double* c) {

@@ -40,6 +40,10 @@ def load():
     if not os.path.exists(LIB):
         build_oracle()
     lib = ct.CDLL(LIB)
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads.argtypes = [ct.c_int32]
+    lib.orc_max_threads.restype = ct.c_int32
+    lib.orc_max_threads.argtypes = []
     lib.orc_point_triangle_distance.restype = ct.c_double
     lib.orc_point_triangle_distance.argtypes = [_dp, _dp, _dp, _dp]
     lib.orc_winding_number.restype = ct.c_double
@@ -126,6 +130,16 @@ def winding_number(p, verts, tris, t0=0, t1=None) -> float:
     p, V, T = _c(p, np.float64), _c(verts, np.float64), _c(tris, np.int32)
     t1 = T.shape[0] if t1 is None else t1
     return float(lib.orc_winding_number(_ptr(p, _dp), _ptr(V, _dp), _ptr(T, _ip), t0, t1))
+
+
+def set_threads(n: int) -> None:
+    """Number of threads of the oracle's OpenMP loops."""
+    load().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(load().orc_max_threads())
 
 
 def mesh_sdf(points, verts, tris, comp_first=None) -> np.ndarray:
@@ -489,4 +503,5 @@ def mlp_unpack(params):
 
 __all__ = ["FRNN_HIDDEN", "frnn_forward", "frnn_loss_grad", "frnn_nparam", "frnn_target", "align", "robot_sdf_f64", "robot_sdf_query", "voxel_centres", "voxel_index", "build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
            "query_batched", "query_f32", "query_f32_each", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids",
-           "MLP_HIDDEN", "adam_step", "judge_min", "mlp_forward", "mlp_loss_grad", "mlp_nparam", "mlp_unpack"]
+           "MLP_HIDDEN", "adam_step", "judge_min", "mlp_forward", "mlp_loss_grad", "mlp_nparam", "mlp_unpack",
+           "max_threads", "set_threads"]
