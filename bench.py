@@ -239,6 +239,28 @@ def learned_pair_stats(w, T, pts, params, cen, half, margin: float, sample: int 
             "fallback_fraction_of_in_domain": round(n_fb / max(1, n_dom), 5)}
 
 
+def gather_roof(dev, iters: int = 64, reps: int = 5):
+    """Sustained rate of trilinear-style gathers (8 corners of a random cell)
+    from an FP32 grid that fits one XCD's L2 (64^3, 1 MB), one the size of
+    the seven link grids (121^3, 7.1 MB) and one only HBM holds (645^3,
+    1.07 GB): cells per second and the 32 B of corners per cell."""
+    import torch
+
+    from paper_2309_12543_amd import lsdf
+
+    threads = 256 * 8 * 256
+    res = {}
+    for name, n in (("l2_1mb", 64), ("grids_7mb", 121), ("hbm_1gb", 645)):
+        g = torch.rand(n ** 3, dtype=torch.float32, device=dev)
+        out = torch.empty(threads, dtype=torch.float32, device=dev)
+        ms = time_calls(lambda: lsdf.gather_roof(g, n, iters, threads, out=out), reps, 2)
+        cells = threads * iters
+        res[name] = {"n": n, "ms": round(ms, 4), "g_cells_per_s": round(cells / (ms / 1e3) / 1e9, 2),
+                     "corner_tb_per_s": round(32 * cells / (ms / 1e3) / 1e12, 3)}
+        del g, out
+    return res
+
+
 def precision_variant(dev, steps: int, judge_waypoints: int = 16):
     """128^3 grids stored as FP32, bfloat16 and binary16 on the 500 x 100,000
     x 7 workload: time per batch and the per-waypoint clearance error against
@@ -681,6 +703,11 @@ def main():
                               "inbox_pairs": inbox, "flop_per_test": FLOP_PER_TEST,
                               "flop_per_inbox_pair": FLOP_PER_INBOX_PAIR}},
     }
+    roof = gather_roof(dev)
+    rec["gather_roof"] = roof
+    rec["roofline"]["gather"] = {
+        "inbox_pair_corner_tb_per_s": round(BYTES_PER_INBOX_PAIR * inbox / (kernel_ms / 1e3) / 1e12, 4),
+        "roof_corner_tb_per_s_7mb": roof["grids_7mb"]["corner_tb_per_s"]}
     if args.learned_epochs > 0:
         rec["learned"] = learned_variant(dev, args.learned_epochs, args.learned_steps)
     if not args.no_precision:

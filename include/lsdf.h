@@ -416,6 +416,15 @@ int lsdf_sdf_labels(const float* verts, int32_t nv, const int32_t* tris, int32_t
                     int32_t ncomp, const lsdf_grid* desc, const void* grid_buf, const float* points, int64_t N,
                     float* out, void* stream);
 
+/* Measurement aid, not part of the query path: `threads` threads each take
+ * `iters` random cells of an n^3 FP32 grid (device, n^3 floats, x fastest,
+ * cells drawn by a counter-based hash of thread and iteration) and sum the
+ * cell's 8 corners, the gather of one trilinear sample; out (device
+ * [threads]) receives each thread's sum.  Timing a launch gives the gather
+ * rate a grid of that size sustains.  2 <= n <= 1024, iters >= 1,
+ * 1 <= threads <= 2^31. */
+int lsdf_gather_roof(const float* grid, int32_t n, int32_t iters, int64_t threads, float* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

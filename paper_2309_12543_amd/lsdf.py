@@ -154,6 +154,8 @@ def load_library():
     lib.lsdf_mlp_train_step.restype = ct.c_int
     lib.lsdf_mlp_train_step.argtypes = [vp, vp, vp, i64, ct.c_float, ct.c_float, ct.c_float, ct.c_float, dom, i32,
                                         vp, vp, i64, vp, i32, vp, vp, vp, sz, vp]
+    lib.lsdf_gather_roof.restype = ct.c_int
+    lib.lsdf_gather_roof.argtypes = [vp, i32, i32, i64, vp, vp]
     lib.lsdf_sdf_labels.restype = ct.c_int
     lib.lsdf_sdf_labels.argtypes = [vp, i32, vp, i32, ct.POINTER(ct.c_int32), i32, ct.POINTER(lsdf_grid), vp, vp,
                                     i64, vp, vp]
@@ -777,3 +779,17 @@ def sdf_labels(verts: torch.Tensor, tris: torch.Tensor, comp_first, grids: GridS
                                ct.pointer(grids.desc[index]), grids.buf.data_ptr(),
                                points.data_ptr() if N else None, N, out.data_ptr(), _stream_handle(stream, points.device)))
     return out
+
+
+def gather_roof(grid: torch.Tensor, n: int, iters: int, threads: int, out: torch.Tensor | None = None,
+                stream=None) -> torch.Tensor:
+    """Per-thread sums of `iters` random 8-corner cell gathers from an n^3
+    FP32 grid (lsdf_gather_roof, a measurement aid)."""
+    lib = load_library()
+    _require(grid, "grid", torch.float32, (n * n * n,))
+    if out is None:
+        out = torch.empty(threads, dtype=torch.float32, device=grid.device)
+    _require(out, "out", torch.float32, (threads,))
+    _check(lib.lsdf_gather_roof(grid.data_ptr(), n, iters, threads, out.data_ptr(), _stream_handle(stream, grid.device)))
+    return out
+

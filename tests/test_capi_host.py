@@ -293,3 +293,13 @@ def test_frnn_argument_errors(lib):
     assert lib.lsdf_robot_sdf_build_frnn(FAKE, 4, 2, g, FAKE, ct.byref(env), FAKE, 10, FAKE, FAKE, 1 << 20, None) \
         == B.LSDF_E_SHAPE
     assert b"does not hold" in lib.lsdf_last_error()
+
+
+def test_gather_roof_rejects_bad_arguments(lib):
+    vp = ct.c_void_p
+    dummy = vp(4096)
+    lib.lsdf_gather_roof.restype = ct.c_int
+    lib.lsdf_gather_roof.argtypes = [vp, ct.c_int32, ct.c_int32, ct.c_int64, vp, vp]
+    for n, it, th, g, o in [(1, 1, 1, dummy, dummy), (1025, 1, 1, dummy, dummy), (8, 0, 1, dummy, dummy),
+                            (8, 1, 0, dummy, dummy), (8, 1, 1, None, dummy), (8, 1, 1, dummy, None)]:
+        assert lib.lsdf_gather_roof(g, n, it, th, o, None) != 0
