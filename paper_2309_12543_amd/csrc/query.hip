@@ -68,7 +68,8 @@ constexpr float kFar = 1e30f;       // centred coordinate of unused lanes: never
 #define LSDF_QUERY_GATHER 4         // points whose gathers are in flight together
 #endif
 constexpr int kBlockPts = 8;        // points per culling sphere
-constexpr int kSphereBatch = 4;     // culling spheres tested together
+constexpr int kSphereBatch = 4;     // culling spheres tested together: the blocks of a quad
+constexpr int kQuadPts = kBlockPts * kSphereBatch;   // points per quad
 constexpr int kUnroll = LSDF_QUERY_UNROLL;
 constexpr int kGather = LSDF_QUERY_GATHER;
 static_assert(kUnroll % kGather == 0, "gather batch must divide the unroll");
@@ -99,7 +100,7 @@ struct TrajPlan {
     int64_t m_lo, m_hi;        // points [m_lo, m_hi) of the concatenated cloud
     int32_t c_lo, c_n;         // configurations [c_lo, c_lo + c_n)
     int32_t cgroups;           // ceil(c_n / 64)
-    int32_t chunks_per_group;  // ceil(quads of 4 blocks touched / chunk_quads)
+    int32_t chunks_per_group;  // ceil(quads touched / chunk_quads)
     int32_t pad[2];
 };
 static_assert(sizeof(TrajPlan) == 48, "plan entry layout");
@@ -128,7 +129,8 @@ struct PrepArgs {
     float* link_T_out;       // poses computed from q are stored here when not NULL
     const float* link_T;
     const float* points;
-    float4* spheres;         // [ceil(M / 8)]
+    float4* spheres;         // [4 ceil(M / 32)] one per 8-point block (the last few unused)
+    float4* qspheres;        // [ceil(M / 32)] one per quad of 4 blocks
     TrajPlan* plan;          // [K + 1]
     float* maps;             // [L][kMapFields][C]
     uint32_t* keys;          // [C][L], zeroed here
@@ -229,6 +231,7 @@ template <bool CUBIC, int DT>
 __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float* __restrict__ points,
                                                        const typename GridT<DT>::T* __restrict__ grid,
                                                        const float4* __restrict__ spheres,
+                                                       const float4* __restrict__ qspheres,
                                                        const TrajPlan* __restrict__ plan) {
     using E = GridT<DT>;
     const int lane = threadIdx.x & 63;
@@ -295,12 +298,14 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
         const int c = c_lo + cl;
         const LinkGrid& lg = p.link[i];
         const typename E::T* __restrict__ G = grid + lg.offset;
-        // the trajectory's 8-point blocks (aligned in the concatenated
-        // cloud) form quads of 4; chunk mc takes every cpg-th quad from quad
-        // mc, so that points near a link, which lie together in the cloud,
-        // spread over the chunks rather than piling onto a few waves
-        const int64_t blk0 = m_lo >> 3;
-        const int64_t nblk = ((m_hi + kBlockPts - 1) >> 3) - blk0;
+        // the trajectory's points lie in quads of 4 blocks of 8 (aligned in the
+        // concatenated cloud); chunk mc takes every cpg-th quad from the
+        // trajectory's quad mc, so that points near a link, which lie together
+        // in the cloud, spread over the chunks rather than piling onto a few
+        // waves
+        const int64_t blk0 = m_lo >> 3, blk1 = (m_hi + kBlockPts - 1) >> 3;   // the trajectory's blocks
+        const int64_t quad0 = m_lo / kQuadPts;
+        const int64_t nquad = (m_hi + kQuadPts - 1) / kQuadPts - quad0;
 
         // this lane's map v = M [x; y; z] + w (centred grid coordinates) and
         // its culling thresholds, from the table the first kernel built;
@@ -323,22 +328,35 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
         const int nxy = lg.n[0] * lg.n[1];
 
         float best = INFINITY;
-        for (int64_t qd = mc * kSphereBatch; qd < nblk; qd += (int64_t)cpg * kSphereBatch) {
-            // the spheres of the quad's blocks are loaded together (the
-            // sphere array has kSphereBatch - 1 spare entries past its end); a
-            // sphere bounds all 8 points of its block, so also the
-            // trajectory's share of a block it shares with its neighbour
-            const int64_t jb = (blk0 + qd) * kBlockPts;
+        for (int64_t qi = mc; qi < nquad; qi += cpg) {
+            // the quad's sphere first, its blocks' spheres only when some
+            // lane's box may reach the quad (all five loaded together); a
+            // sphere bounds all points of its quad or block, so also the
+            // trajectory's share of one it shares with its neighbour
+            const int64_t qg = quad0 + qi;
+            const float4 qs = qspheres[qg];
+            float4 sph[kSphereBatch];
+#pragma unroll
+            for (int u = 0; u < kSphereBatch; ++u) sph[u] = spheres[kSphereBatch * qg + u];
+            {
+                const float s0 = fmaf(m00, qs.x, fmaf(m01, qs.y, fmaf(m02, qs.z, w0)));
+                const float s1 = fmaf(m10, qs.x, fmaf(m11, qs.y, fmaf(m12, qs.z, w1)));
+                const float s2 = fmaf(m20, qs.x, fmaf(m21, qs.y, fmaf(m22, qs.z, w2)));
+                const bool near = (fabsf(s0) <= fmaf(nr0, qs.w, k0)) & (fabsf(s1) <= fmaf(nr1, qs.w, k1)) &
+                                  (fabsf(s2) <= fmaf(nr2, qs.w, k2));
+                if (!__ballot(near)) continue;
+            }
+            const int64_t jb = kQuadPts * qg;
             uint32_t near_mask = 0;
 #pragma unroll
             for (int u = 0; u < kSphereBatch; ++u) {
-                const float4 sph = spheres[blk0 + qd + u];
-                const float s0 = fmaf(m00, sph.x, fmaf(m01, sph.y, fmaf(m02, sph.z, w0)));
-                const float s1 = fmaf(m10, sph.x, fmaf(m11, sph.y, fmaf(m12, sph.z, w1)));
-                const float s2 = fmaf(m20, sph.x, fmaf(m21, sph.y, fmaf(m22, sph.z, w2)));
-                const bool near = (fabsf(s0) <= fmaf(nr0, sph.w, k0)) & (fabsf(s1) <= fmaf(nr1, sph.w, k1)) &
-                                  (fabsf(s2) <= fmaf(nr2, sph.w, k2));
-                if (__ballot(near) && qd + u < nblk) near_mask |= 1u << u;
+                const float s0 = fmaf(m00, sph[u].x, fmaf(m01, sph[u].y, fmaf(m02, sph[u].z, w0)));
+                const float s1 = fmaf(m10, sph[u].x, fmaf(m11, sph[u].y, fmaf(m12, sph[u].z, w1)));
+                const float s2 = fmaf(m20, sph[u].x, fmaf(m21, sph[u].y, fmaf(m22, sph[u].z, w2)));
+                const bool near = (fabsf(s0) <= fmaf(nr0, sph[u].w, k0)) & (fabsf(s1) <= fmaf(nr1, sph[u].w, k1)) &
+                                  (fabsf(s2) <= fmaf(nr2, sph[u].w, k2));
+                const int64_t blk = kSphereBatch * qg + u;
+                if (__ballot(near) && blk >= blk0 && blk < blk1) near_mask |= 1u << u;
             }
             while (near_mask) {   // wave-uniform: blocks some lane's box may reach
                 const int u = __builtin_ctz(near_mask);
@@ -351,17 +369,74 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
     }
 }
 
+// Culling spheres of block b (8 points from 8 b) and, for b = 4 q, of quad
+// q (blocks 4 q to 4 q + 3), from the thread of block b; the four threads of
+// a quad are adjacent lanes and combine their boxes and radii by shuffles.
+// A sphere's centre is the centre of its points' box and its radius the
+// largest distance to it, widened by a relative 1e-5, by 1e-4 of the sum of
+// the coordinates' magnitudes (which bounds FP32 rounding of the mapped
+// coordinates) and by 1e-6 m.  Past the end of the cloud the last point
+// repeats, which changes neither a box nor a radius.  Every lane of a quad
+// must call this together.
+__device__ __forceinline__ float4 widen(float cx, float cy, float cz, float r2) {
+    const float r = sqrtf(r2);
+    const float e = fabsf(cx) + fabsf(cy) + fabsf(cz) + 3.0f * r;
+    return make_float4(cx, cy, cz, fmaf(r, 1.00001f, fmaf(1e-4f, e, 1e-6f)));
+}
+
+__device__ __forceinline__ void block_and_quad_spheres(const float* __restrict__ points, int64_t b, int64_t M,
+                                                       float4* block_out, float4* quad_out) {
+    float x[kBlockPts], y[kBlockPts], z[kBlockPts];
+#pragma unroll
+    for (int k = 0; k < kBlockPts; ++k) {
+        const int64_t j = min(b * kBlockPts + k, M - 1);
+        x[k] = points[3 * j + 0];
+        y[k] = points[3 * j + 1];
+        z[k] = points[3 * j + 2];
+    }
+    float lo0 = x[0], lo1 = y[0], lo2 = z[0], hi0 = x[0], hi1 = y[0], hi2 = z[0];
+#pragma unroll
+    for (int k = 1; k < kBlockPts; ++k) {
+        lo0 = fminf(lo0, x[k]); hi0 = fmaxf(hi0, x[k]);
+        lo1 = fminf(lo1, y[k]); hi1 = fmaxf(hi1, y[k]);
+        lo2 = fminf(lo2, z[k]); hi2 = fmaxf(hi2, z[k]);
+    }
+    auto radius2 = [&](float cx, float cy, float cz) {
+        float r2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kBlockPts; ++k) {
+            const float dx = x[k] - cx, dy = y[k] - cy, dz = z[k] - cz;
+            r2 = fmaxf(r2, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        }
+        return r2;
+    };
+    {
+        const float cx = 0.5f * (lo0 + hi0), cy = 0.5f * (lo1 + hi1), cz = 0.5f * (lo2 + hi2);
+        const float4 sb = widen(cx, cy, cz, radius2(cx, cy, cz));
+        if (b * kBlockPts < M) *block_out = sb;
+    }
+#pragma unroll
+    for (int o = 1; o < kSphereBatch; o <<= 1) {
+        lo0 = fminf(lo0, __shfl_xor(lo0, o, 64)); hi0 = fmaxf(hi0, __shfl_xor(hi0, o, 64));
+        lo1 = fminf(lo1, __shfl_xor(lo1, o, 64)); hi1 = fmaxf(hi1, __shfl_xor(hi1, o, 64));
+        lo2 = fminf(lo2, __shfl_xor(lo2, o, 64)); hi2 = fmaxf(hi2, __shfl_xor(hi2, o, 64));
+    }
+    const float cx = 0.5f * (lo0 + hi0), cy = 0.5f * (lo1 + hi1), cz = 0.5f * (lo2 + hi2);
+    float r2 = radius2(cx, cy, cz);
+#pragma unroll
+    for (int o = 1; o < kSphereBatch; o <<= 1) r2 = fmaxf(r2, __shfl_xor(r2, o, 64));
+    if ((b & (kSphereBatch - 1)) == 0) *quad_out = widen(cx, cy, cz, r2);
+}
+
 // First kernel of a query.  Thread t < C L zeroes key t and writes the map
 // table entry of (link t / C, configuration t mod C), from the given pose or,
-// in the fused form, from the pose it computes from the joint angles.  Thread t < ceil(M / 8)
-// bounds block t of 8 consecutive points of the concatenated cloud by a
-// sphere: the centre of the block's box and a radius widened by a relative
-// 1e-5, by 1e-4 of the sum of the coordinates' magnitudes (which bounds FP32
-// rounding of the mapped coordinates) and by 1e-6 m.  Workgroup 0 also
-// builds the plan: each
-// trajectory's ranges clamped into [0, C) and [0, M) (so a bad offset table
-// gives wrong ranges, never an access out of bounds), its chunk count and
-// the exclusive prefix sum of the counts.
+// in the fused form, from the pose it computes from the joint angles.  Thread
+// t < ceil(M / 8) bounds block t of 8 consecutive points of the concatenated
+// cloud by a sphere, and thread t < ceil(M / 32) bounds quad t (blocks 4t to
+// 4t + 3) by another.  Workgroup 0 also builds the plan: each trajectory's
+// ranges clamped into [0, C) and [0, M) (so a bad offset table gives wrong
+// ranges, never an access out of bounds), its chunk count and the exclusive
+// prefix sum of the counts.
 __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (b < (int64_t)a.C * a.L) {
@@ -406,36 +481,9 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
 #pragma unroll
         for (int k = 0; k < kMapFields; ++k) out[(int64_t)k * a.C] = f[k];
     }
-    const int64_t j0 = b * kBlockPts;
-    if (j0 < a.M) {
-        // the block's points, loaded together; past the end of the cloud the
-        // last point repeats, which changes neither the box nor the radius
-        float x[kBlockPts], y[kBlockPts], z[kBlockPts];
-#pragma unroll
-        for (int k = 0; k < kBlockPts; ++k) {
-            const int64_t j = min(j0 + k, a.M - 1);
-            x[k] = a.points[3 * j + 0];
-            y[k] = a.points[3 * j + 1];
-            z[k] = a.points[3 * j + 2];
-        }
-        float lo0 = x[0], lo1 = y[0], lo2 = z[0], hi0 = x[0], hi1 = y[0], hi2 = z[0];
-#pragma unroll
-        for (int k = 1; k < kBlockPts; ++k) {
-            lo0 = fminf(lo0, x[k]); hi0 = fmaxf(hi0, x[k]);
-            lo1 = fminf(lo1, y[k]); hi1 = fmaxf(hi1, y[k]);
-            lo2 = fminf(lo2, z[k]); hi2 = fmaxf(hi2, z[k]);
-        }
-        const float cx = 0.5f * (lo0 + hi0), cy = 0.5f * (lo1 + hi1), cz = 0.5f * (lo2 + hi2);
-        float r2 = 0.0f;
-#pragma unroll
-        for (int k = 0; k < kBlockPts; ++k) {
-            const float dx = x[k] - cx, dy = y[k] - cy, dz = z[k] - cz;
-            r2 = fmaxf(r2, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        }
-        const float r = sqrtf(r2);
-        const float e = fabsf(cx) + fabsf(cy) + fabsf(cz) + 3.0f * r;
-        a.spheres[b] = make_float4(cx, cy, cz, fmaf(r, 1.00001f, fmaf(1e-4f, e, 1e-6f)));
-    }
+    // uniform over the four lanes of a quad (blocks 4 q .. 4 q + 3 are threads 4 q .. 4 q + 3)
+    if (b / kSphereBatch * kQuadPts < a.M)
+        block_and_quad_spheres(a.points, b, a.M, &a.spheres[b], &a.qspheres[b / kSphereBatch]);
     if (blockIdx.x != 0) return;
 
     __shared__ int64_t scan[256];
@@ -455,8 +503,8 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
             e.c_lo = c0;
             e.c_n = c1 - c0;
             e.cgroups = (e.c_n + 63) / 64;
-            const int64_t nb = m1 > m0 ? ((m1 + kBlockPts - 1) / kBlockPts) - m0 / kBlockPts : 0;
-            const int64_t nq = (nb + kSphereBatch - 1) / kSphereBatch;
+            // the quads (aligned in the concatenated cloud) that hold a point of [m0, m1)
+            const int64_t nq = m1 > m0 ? (m1 + kQuadPts - 1) / kQuadPts - m0 / kQuadPts : 0;
             e.chunks_per_group = (int32_t)((nq + a.chunk_quads - 1) / a.chunk_quads);
             n = (int64_t)a.L * e.cgroups * e.chunks_per_group;
         }
@@ -531,15 +579,14 @@ int lsdf::launch_zero_words(uint32_t* w, int64_t n, hipStream_t s) {
 namespace {
 
 size_t keys_bytes(int64_t C, int64_t L) { return ((size_t)(C * L) * 4 + 255) / 256 * 256; }
-// kSphereBatch - 1 spare spheres past the end: the query loads spheres in
-// batches and ignores those past a chunk's last block
-size_t sphere_bytes(int64_t M) {
-    return ((size_t)((M + kBlockPts - 1) / kBlockPts + kSphereBatch - 1) * 16 + 255) / 256 * 256;
-}
+// Block spheres for whole quads (the query loads a quad's four together and
+// ignores those past the cloud's last block), then the quad spheres.
+int64_t quad_count(int64_t M) { return (M + kQuadPts - 1) / kQuadPts; }
+size_t sphere_bytes(int64_t M) { return ((size_t)quad_count(M) * (kSphereBatch + 1) * 16 + 255) / 256 * 256; }
 size_t plan_bytes(int64_t K) { return ((size_t)(K + 1) * sizeof(TrajPlan) + 255) / 256 * 256; }
 size_t map_bytes(int64_t C, int64_t L) { return ((size_t)(C * L) * kMapFields * 4 + 255) / 256 * 256; }
 
-// Workspace: keys | spheres | plan | maps, each 256-byte aligned.
+// Workspace: keys | block and quad spheres | plan | maps, each 256-byte aligned.
 size_t workspace_bytes(int64_t K, int64_t C, int64_t L, int64_t M) {
     return keys_bytes(C, L) + sphere_bytes(M) + plan_bytes(K) + map_bytes(C, L);
 }
@@ -651,6 +698,7 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
     hipStream_t s = as_stream(stream);
     char* ws = static_cast<char*>(workspace);
     float4* spheres = reinterpret_cast<float4*>(ws + keys_bytes(C, L));
+    float4* qspheres = spheres + kSphereBatch * quad_count(M);
     TrajPlan* plan = reinterpret_cast<TrajPlan*>(ws + keys_bytes(C, L) + sphere_bytes(M));
     float* maps = reinterpret_cast<float*>(ws + keys_bytes(C, L) + sphere_bytes(M) + plan_bytes(K));
     p.maps = maps;
@@ -673,6 +721,7 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
         a.link_T = link_T;
         a.points = points;
         a.spheres = spheres;
+        a.qspheres = qspheres;
         a.plan = plan;
         a.maps = maps;
         a.keys = p.keys;
@@ -695,25 +744,26 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
         // given by C and M), no more waves than chunks
         int64_t blocks = (int64_t)cus * blocks_per_cu;
         if (!c_off) {
-            const int64_t nq = ((M + kBlockPts - 1) / kBlockPts + kSphereBatch - 1) / kSphereBatch;
+            const int64_t nq = quad_count(M);
             const int64_t chunks = (int64_t)L * ((C + 63) / 64) * ((nq + p.chunk_quads - 1) / p.chunk_quads);
             blocks = std::min<int64_t>(blocks, (chunks + kWavesPerBlock - 1) / kWavesPerBlock);
         }
         blocks = (blocks + kXcds - 1) / kXcds * kXcds;
         p.blocks_per_xcd = (int32_t)(blocks / kXcds);
         const float4* sph = spheres;
+        const float4* qsph = qspheres;
         const TrajPlan* pl = plan;
         const dim3 gd((unsigned)blocks), bd(kBlock);
         hipEvent_t ev0, ev1;
         take_kernel_events(&ev0, &ev1);
         if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return fail(LSDF_E_DEVICE, "%s: event record failed", who);
         switch (dtype * 2 + (cubic ? 1 : 0)) {
-            case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((query_kernel<true, LSDF_F32>), gd, bd, 0, s, p, points, static_cast<const float*>(grid_buf), sph, pl); break;
-            case LSDF_F32 * 2: hipLaunchKernelGGL((query_kernel<false, LSDF_F32>), gd, bd, 0, s, p, points, static_cast<const float*>(grid_buf), sph, pl); break;
-            case LSDF_BF16 * 2 + 1: hipLaunchKernelGGL((query_kernel<true, LSDF_BF16>), gd, bd, 0, s, p, points, static_cast<const uint16_t*>(grid_buf), sph, pl); break;
-            case LSDF_BF16 * 2: hipLaunchKernelGGL((query_kernel<false, LSDF_BF16>), gd, bd, 0, s, p, points, static_cast<const uint16_t*>(grid_buf), sph, pl); break;
-            case LSDF_F16 * 2 + 1: hipLaunchKernelGGL((query_kernel<true, LSDF_F16>), gd, bd, 0, s, p, points, static_cast<const _Float16*>(grid_buf), sph, pl); break;
-            default: hipLaunchKernelGGL((query_kernel<false, LSDF_F16>), gd, bd, 0, s, p, points, static_cast<const _Float16*>(grid_buf), sph, pl); break;
+            case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((query_kernel<true, LSDF_F32>), gd, bd, 0, s, p, points, static_cast<const float*>(grid_buf), sph, qsph, pl); break;
+            case LSDF_F32 * 2: hipLaunchKernelGGL((query_kernel<false, LSDF_F32>), gd, bd, 0, s, p, points, static_cast<const float*>(grid_buf), sph, qsph, pl); break;
+            case LSDF_BF16 * 2 + 1: hipLaunchKernelGGL((query_kernel<true, LSDF_BF16>), gd, bd, 0, s, p, points, static_cast<const uint16_t*>(grid_buf), sph, qsph, pl); break;
+            case LSDF_BF16 * 2: hipLaunchKernelGGL((query_kernel<false, LSDF_BF16>), gd, bd, 0, s, p, points, static_cast<const uint16_t*>(grid_buf), sph, qsph, pl); break;
+            case LSDF_F16 * 2 + 1: hipLaunchKernelGGL((query_kernel<true, LSDF_F16>), gd, bd, 0, s, p, points, static_cast<const _Float16*>(grid_buf), sph, qsph, pl); break;
+            default: hipLaunchKernelGGL((query_kernel<false, LSDF_F16>), gd, bd, 0, s, p, points, static_cast<const _Float16*>(grid_buf), sph, qsph, pl); break;
         }
         rc = check_launch(who);
         if (rc != LSDF_OK) return rc;
