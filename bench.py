@@ -474,12 +474,13 @@ def frnn_variant(dev, train_steps: int, test_rotations: int):
     lr0, lr1 = 1e-2, 1e-5
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    Rall = random_rotations_dev(64 * train_steps, gen, dev)      # every step's batch, drawn at once
     for t in range(1, train_steps + 1):
         lr = lr1 + 0.5 * (lr0 - lr1) * (1 + math.cos(math.pi * t / train_steps))
-        lsdf.frnn_train_step(P, m, random_rotations_dev(64, gen, dev), adam=(mm, vv), t=t, lr=lr, grad=grad,
-                             loss=loss)
+        lsdf.frnn_train_step(P, m, Rall[64 * (t - 1):64 * t], adam=(mm, vv), t=t, lr=lr, grad=grad, loss=loss)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
+    del Rall
     Rt = random_rotations_dev(test_rotations, gen, dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

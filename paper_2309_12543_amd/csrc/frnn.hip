@@ -95,10 +95,11 @@ __global__ __launch_bounds__(256) void frnn_hidden_kernel(TrainArgs a) {
 }
 
 __global__ __launch_bounds__(kRows) void frnn_output_kernel(TrainArgs a) {
+    static_assert(kRows == (kMaxB / 4) * (kH / 4), "one 4 x 4 tile of dh per thread");
     __shared__ float hs[kMaxB][kH];
     __shared__ float rs[kMaxB][9];
-    __shared__ float gs[kRows][kMaxB + 1];
-    __shared__ float ws[kRows][kH + 1];
+    __shared__ __align__(16) float gsT[kMaxB][kRows + 4];   // g[b][row]; the pad staggers 4 rows over the banks
+    __shared__ float4 ws4[kRows][kH / 4];       // W2 rows in 16 B chunks, chunk c stored at c ^ (row mod 8)
     __shared__ float ls[kRows];
     const int tid = threadIdx.x;
     const int B = a.B;
@@ -109,11 +110,24 @@ __global__ __launch_bounds__(kRows) void frnn_output_kernel(TrainArgs a) {
     float wrow[kH];
     const float* W2 = a.params + a.lay.w2;
 #pragma unroll
-    for (int u = 0; u < kH; ++u) {
-        wrow[u] = live ? W2[o * kH + u] : 0.0f;
-        ws[tid][u] = wrow[u];
-    }
+    for (int u = 0; u < kH; ++u) wrow[u] = live ? W2[o * kH + u] : 0.0f;
+#pragma unroll
+    for (int c = 0; c < kH / 4; ++c)
+        ws4[tid][c ^ (tid & 7)] = make_float4(wrow[4 * c], wrow[4 * c + 1], wrow[4 * c + 2], wrow[4 * c + 3]);
     const float bias = live ? a.params[a.lay.b2 + o] : 0.0f;
+    // this row's block voxel and component (the target is R^T P_j, component a)
+    int comp = 0;
+    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    if (live) {
+        const int64_t j = o / 3;
+        comp = (int)(o - 3 * j);
+        const int w = 2 * a.m;
+        const int jx = (int)(j % w), jy = (int)((j / w) % w), jz = (int)(j / ((int64_t)w * w));
+        const float inv = 1.0f / (float)a.m;
+        px = fmaf((float)jx + 0.5f, inv, -1.0f);
+        py = fmaf((float)jy + 0.5f, inv, -1.0f);
+        pz = fmaf((float)jz + 0.5f, inv, -1.0f);
+    }
     __syncthreads();
     const float scale = 1.0f / ((float)B * (float)a.lay.O);
     float dw[kH];
@@ -126,11 +140,13 @@ __global__ __launch_bounds__(kRows) void frnn_output_kernel(TrainArgs a) {
         for (int u = 0; u < kH; ++u) y = fmaf(wrow[u], hs[b][u], y);
         float g = 0.0f;
         if (live) {
-            const float e = y - frnn_target(rs[b], o, a.m);
+            const float* r = rs[b];
+            const float t = fmaf(r[comp], px, fmaf(r[3 + comp], py, r[6 + comp] * pz));
+            const float e = y - t;
             loss += fabsf(e);
             g = e > 0.0f ? scale : (e < 0.0f ? -scale : 0.0f);
         }
-        gs[tid][b] = g;
+        gsT[b][tid] = g;
 #pragma unroll
         for (int u = 0; u < kH; ++u) dw[u] = fmaf(g, hs[b][u], dw[u]);
         db += g;
@@ -143,13 +159,36 @@ __global__ __launch_bounds__(kRows) void frnn_output_kernel(TrainArgs a) {
     }
     ls[tid] = loss;
     __syncthreads();
-    // this workgroup's share of dh[b][u] = sum over its rows of g W2[o][u]
+    // this workgroup's share of dh[b][u] = sum over its rows of g W2[o][u],
+    // rows in order; thread t holds b = 4 (t / 8) + i, u = 4 (t mod 8) + k
+    const int bt = tid >> 3, ut = tid & 7;
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[i][k] = 0.0f;
+    for (int r0 = 0; r0 < kRows; r0 += 4) {
+        float4 g[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) g[i] = *reinterpret_cast<const float4*>(&gsT[4 * bt + i][r0]);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const float4 wv = ws4[r0 + rr][ut ^ ((r0 + rr) & 7)];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float gi = rr == 0 ? g[i].x : rr == 1 ? g[i].y : rr == 2 ? g[i].z : g[i].w;
+                acc[i][0] = fmaf(gi, wv.x, acc[i][0]);
+                acc[i][1] = fmaf(gi, wv.y, acc[i][1]);
+                acc[i][2] = fmaf(gi, wv.z, acc[i][2]);
+                acc[i][3] = fmaf(gi, wv.w, acc[i][3]);
+            }
+        }
+    }
     float* pd = a.part_dh + (int64_t)blockIdx.x * B * kH;
-    for (int p = tid; p < B * kH; p += kRows) {
-        const int b = p / kH, u = p - b * kH;
-        float s = 0.0f;
-        for (int r = 0; r < kRows; ++r) s = fmaf(gs[r][b], ws[r][u], s);
-        pd[p] = s;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int b = 4 * bt + i;
+        if (b < B) *reinterpret_cast<float4*>(&pd[b * kH + 4 * ut]) = make_float4(acc[i][0], acc[i][1], acc[i][2], acc[i][3]);
     }
     if (tid == 0) {
         float s = 0.0f;
