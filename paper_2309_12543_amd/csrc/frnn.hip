@@ -98,7 +98,9 @@ __global__ __launch_bounds__(kRows) void frnn_output_kernel(TrainArgs a) {
     static_assert(kRows == (kMaxB / 4) * (kH / 4), "one 4 x 4 tile of dh per thread");
     __shared__ float hs[kMaxB][kH];
     __shared__ float rs[kMaxB][9];
-    __shared__ __align__(16) float gsT[kMaxB][kRows + 4];   // g[b][row]; the pad staggers 4 rows over the banks
+    // sign of g[row][b] (g is +scale, -scale or 0), transposed: rows contiguous,
+    // the pad staggers the rotations over the banks
+    __shared__ __align__(16) int8_t sgT[kMaxB][kRows + 4];
     __shared__ float4 ws4[kRows][kH / 4];       // W2 rows in 16 B chunks, chunk c stored at c ^ (row mod 8)
     __shared__ float ls[kRows];
     const int tid = threadIdx.x;
@@ -139,14 +141,16 @@ __global__ __launch_bounds__(kRows) void frnn_output_kernel(TrainArgs a) {
 #pragma unroll
         for (int u = 0; u < kH; ++u) y = fmaf(wrow[u], hs[b][u], y);
         float g = 0.0f;
+        int8_t sg = 0;
         if (live) {
             const float* r = rs[b];
             const float t = fmaf(r[comp], px, fmaf(r[3 + comp], py, r[6 + comp] * pz));
             const float e = y - t;
             loss += fabsf(e);
+            sg = e > 0.0f ? 1 : (e < 0.0f ? -1 : 0);
             g = e > 0.0f ? scale : (e < 0.0f ? -scale : 0.0f);
         }
-        gsT[b][tid] = g;
+        sgT[b][tid] = sg;
 #pragma unroll
         for (int u = 0; u < kH; ++u) dw[u] = fmaf(g, hs[b][u], dw[u]);
         db += g;
@@ -168,15 +172,16 @@ __global__ __launch_bounds__(kRows) void frnn_output_kernel(TrainArgs a) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[i][k] = 0.0f;
     for (int r0 = 0; r0 < kRows; r0 += 4) {
-        float4 g[4];
+        uint32_t sg4[4];   // the signs of rows r0 .. r0 + 3, one byte each
 #pragma unroll
-        for (int i = 0; i < 4; ++i) g[i] = *reinterpret_cast<const float4*>(&gsT[4 * bt + i][r0]);
+        for (int i = 0; i < 4; ++i) sg4[i] = *reinterpret_cast<const uint32_t*>(&sgT[4 * bt + i][r0]);
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
             const float4 wv = ws4[r0 + rr][ut ^ ((r0 + rr) & 7)];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float gi = rr == 0 ? g[i].x : rr == 1 ? g[i].y : rr == 2 ? g[i].z : g[i].w;
+                // g itself, rebuilt exactly from its sign
+                const float gi = (float)(int8_t)(sg4[i] >> (8 * rr)) * scale;
                 acc[i][0] = fmaf(gi, wv.x, acc[i][0]);
                 acc[i][1] = fmaf(gi, wv.y, acc[i][1]);
                 acc[i][2] = fmaf(gi, wv.z, acc[i][2]);
