@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kBlock) void mlp_eval_kernel(EvalArgs p) {
             for (int a = 0; a < 3; ++a) xh[nt][a] = (p.points[3 * j + a] - p.d.cen[a]) * p.d.inv[a];
         }
         float m[NT];
-        forward_tile<false>(sW2, sW3, &sp, xh, m, ForwardTrace{});
+        forward_tile<NT, false>(sW2, sW3, &sp, xh, m, ForwardTrace{});
         if (lane < 16) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) 
         }
         if (!__ballot(any)) continue;
         float m[NT];
-        forward_tile<false>(sW2, sW3, &sp, xh, m, ForwardTrace{});
+        forward_tile<NT, false>(sW2, sW3, &sp, xh, m, ForwardTrace{});
         if (lane < 16) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
@@ -198,7 +198,7 @@ struct TrainBufs {
     __bf16* dz3;
     float* xh;      // [L][B][3]
     float* dm;      // [L][B]
-    float* loss;    // [L][B / TILE]
+    float* loss;    // [L][B / TILE_TRAIN]
     float* gpart;   // [L][nsplit][NPARAM]
 };
 
@@ -229,11 +229,11 @@ __global__ __launch_bounds__(kBlock) void train_forward_kernel(TrainArgs p) {
     const int tt = blockIdx.x * kWaves + wave;          // tile of this wave
     const int64_t B = p.B;
     const int64_t lB = (int64_t)l * B;
-    float xh[NT][3];
-    int64_t idx[NT];
+    float xh[NT_TRAIN][3];
+    int64_t idx[NT_TRAIN];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int64_t s = (int64_t)tt * TILE + 16 * nt + (lane & 15);
+    for (int nt = 0; nt < NT_TRAIN; ++nt) {
+        const int64_t s = (int64_t)tt * TILE_TRAIN + 16 * nt + (lane & 15);
         int64_t k = p.bidx ? (int64_t)p.bidx[lB + s] : s;
         k = min(max(k, (int64_t)0), p.N - 1);          // a bad index reads a valid sample
         idx[nt] = (int64_t)l * p.N + k;
@@ -247,21 +247,21 @@ __global__ __launch_bounds__(kBlock) void train_forward_kernel(TrainArgs p) {
     }
     const int64_t plane = (int64_t)l * H * B;
     ForwardTrace tr{p.w.z1 + plane, p.w.z2 + plane, p.w.z3 + plane, p.w.h1 + plane, p.w.h2 + plane, p.w.h3 + plane,
-                    B, (int64_t)tt * TILE};
-    float m[NT];
-    forward_tile<true>(sW2, sW3, &sp, xh, m, tr);
+                    B, (int64_t)tt * TILE_TRAIN};
+    float m[NT_TRAIN];
+    forward_tile<NT_TRAIN, true>(sW2, sW3, &sp, xh, m, tr);
     float absr = 0.0f;
     if (lane < 16) {
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int64_t s = (int64_t)tt * TILE + 16 * nt + lane;
+        for (int nt = 0; nt < NT_TRAIN; ++nt) {
+            const int64_t s = (int64_t)tt * TILE_TRAIN + 16 * nt + lane;
             const float r = m[nt] - p.labels[idx[nt]];
             p.w.dm[lB + s] = (r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f)) / (float)B;
             absr += fabsf(r);
         }
     }
     absr = wave_sum(absr);
-    if (lane == 0) p.w.loss[(int64_t)l * (B / TILE) + tt] = absr;
+    if (lane == 0) p.w.loss[(int64_t)l * (B / TILE_TRAIN) + tt] = absr;
 }
 
 __global__ __launch_bounds__(kBlock) void train_backward_kernel(TrainArgs p) {
@@ -282,17 +282,17 @@ __global__ __launch_bounds__(kBlock) void train_backward_kernel(TrainArgs p) {
     const int64_t B = p.B;
     const int64_t lB = (int64_t)l * B;
     const int64_t plane = (int64_t)l * H * B;
-    const int64_t c0 = (int64_t)tt * TILE;
+    const int64_t c0 = (int64_t)tt * TILE_TRAIN;
 
     // dz3 = dm * w4 * SiLU'(z3), rounded: B operand of dh2 = W3^T dz3
-    bf16x8 b[4][NT];
+    bf16x8 b[4][NT_TRAIN];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int u = perm_unit(s, 8 * g + e);
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
+            for (int nt = 0; nt < NT_TRAIN; ++nt) {
                 const int64_t c = c0 + 16 * nt + col;
                 const float d = p.w.dm[lB + c] * sw4[u] * silu_grad(p.w.z3[plane + u * B + c]);
                 const __bf16 db = (__bf16)d;
@@ -303,24 +303,24 @@ __global__ __launch_bounds__(kBlock) void train_backward_kernel(TrainArgs p) {
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
         const __bf16* sW = layer == 0 ? sW3t : sW2t;
-        f32x4 acc[8][NT];
+        f32x4 acc[8][NT_TRAIN];
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int nt = 0; nt < NT_TRAIN; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const bf16x8 a = lds_a(sW, mt, s, lane);
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
+                for (int nt = 0; nt < NT_TRAIN; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s][nt], acc[mt][nt], 0, 0, 0);
             }
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
+            for (int nt = 0; nt < NT_TRAIN; ++nt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int u = 16 * mt + 4 * g + r;
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(256) void train_reduce_kernel(ReduceArgs p) {
         }
     }
     if (p.loss_out && k < p.L) {
-        const int tiles = p.B / TILE;
+        const int tiles = p.B / TILE_TRAIN;
         float s = 0.f;
         for (int t = 0; t < tiles; ++t) s += p.w.loss[k * tiles + t];
         p.loss_out[k] = s / (float)p.B;
@@ -552,7 +552,7 @@ size_t train_layout(int32_t L, int32_t B, char* base, TrainBufs* w) {
     t.dz3 = (__bf16*)take(h_plane);
     t.xh = (float*)take((size_t)L * B * 3 * sizeof(float));
     t.dm = (float*)take((size_t)L * B * sizeof(float));
-    t.loss = (float*)take((size_t)L * (B / TILE) * sizeof(float));
+    t.loss = (float*)take((size_t)L * (B / TILE_TRAIN) * sizeof(float));
     t.gpart = (float*)take((size_t)L * nsplit * NPARAM * sizeof(float));
     if (w) *w = t;
     return off;
@@ -596,7 +596,7 @@ int train_common(const float* params, float* adam_m, float* adam_v, int64_t t, f
     a.B = B;
     a.nsplit = B / kSplit;
     hipStream_t s = as_stream(stream);
-    const dim3 tiles_grid(B / (TILE * kWaves), L);
+    const dim3 tiles_grid(B / (TILE_TRAIN * kWaves), L);
     hipLaunchKernelGGL(train_forward_kernel, tiles_grid, dim3(kBlock), 0, s, a);
     if ((rc = check_launch("mlp train forward")) != LSDF_OK) return rc;
     hipLaunchKernelGGL(train_backward_kernel, tiles_grid, dim3(kBlock), 0, s, a);

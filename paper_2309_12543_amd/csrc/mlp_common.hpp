@@ -37,8 +37,13 @@ constexpr int OFF_B4 = OFF_W4 + H;
 constexpr int NPARAM = OFF_B4 + 1;
 static_assert(NPARAM == LSDF_MLP_PARAMS, "parameter layout");
 
-constexpr int NT = 2;                   // 16-pair column tiles per wave tile
+constexpr int NT = 2;                   // 16-pair column tiles per wave tile (evaluation, query)
 constexpr int TILE = 16 * NT;           // pairs per wave tile
+// Training takes one column tile per wave: twice the waves for the same
+// batch, which hides more latency (the evaluation keeps two, which reuse
+// each weight tile read from LDS twice)
+constexpr int NT_TRAIN = 1;
+constexpr int TILE_TRAIN = 16 * NT_TRAIN;
 constexpr int WTILE_ELEMS = H * H;      // bf16 elements of one staged 128x128 layer
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
@@ -116,12 +121,12 @@ struct ForwardTrace {
     int64_t col0;
 };
 
-// Forward pass of one wave tile (TILE pairs).  xh[nt] is this lane's input
+// Forward pass of one wave tile (16 NT_ pairs).  xh[nt] is this lane's input
 // for pair 16 nt + lane % 16 (all four lane groups hold the same pairs).
 // Returns the output for pair 16 nt + lane % 16 in m[nt] (every lane).
-template <bool TRACE>
+template <int NT_, bool TRACE>
 __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const SmallParams* sp,
-                                    const float (&xh)[NT][3], float (&m)[NT], const ForwardTrace& tr) {
+                                    const float (&xh)[NT_][3], float (&m)[NT_], const ForwardTrace& tr) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4;
     const int col = lane & 15;
@@ -130,14 +135,14 @@ __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const 
     asm volatile("" ::: "memory");
 
     // input layer (FP32 VALU) straight into layer 2's B operands
-    bf16x8 b[4][NT];
+    bf16x8 b[4][NT_];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int u = perm_unit(s, 8 * g + e);
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
+            for (int nt = 0; nt < NT_; ++nt) {
                 const float z = fmaf(sp->w1[u][0], xh[nt][0],
                                      fmaf(sp->w1[u][1], xh[nt][1], fmaf(sp->w1[u][2], xh[nt][2], sp->b1[u])));
                 const __bf16 h = (__bf16)silu(z);
@@ -156,18 +161,18 @@ __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const 
     for (int layer = 0; layer < 2; ++layer) {
         const __bf16* sW = layer == 0 ? sW2 : sW3;
         const float* bias = layer == 0 ? sp->b2 : sp->b3;
-        f32x4 acc[8][NT];
+        f32x4 acc[8][NT_];
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int nt = 0; nt < NT_; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const bf16x8 a = lds_a(sW, mt, s, lane);
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
+                for (int nt = 0; nt < NT_; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s][nt], acc[mt][nt], 0, 0, 0);
             }
         }
@@ -176,7 +181,7 @@ __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const 
 #pragma unroll
             for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
+                for (int nt = 0; nt < NT_; ++nt)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int u = 16 * mt + 4 * g + r;
@@ -192,7 +197,7 @@ __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const 
         } else {
             // bias + SiLU, rounded, and this lane's part of w4 . h3
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
+            for (int nt = 0; nt < NT_; ++nt) {
                 float part = 0.0f;
 #pragma unroll
                 for (int mt = 0; mt < 8; ++mt)
