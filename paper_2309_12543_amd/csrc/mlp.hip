@@ -16,6 +16,11 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kSplit = 512;                 // samples per weight-gradient split
 constexpr int kSmallGradBlocks = 16;         // workgroups per split for the small gradients
 constexpr int kBlocksPerCu = 2;             // 69 KB of LDS per block
+// The clearance query: 12 waves share one copy of the staged weights, the 3
+// waves per SIMD that its register budget (168 VGPRs) allows; one workgroup
+// per CU
+constexpr int kQueryBlock = 768;
+constexpr int kQueryWaves = kQueryBlock / 64;
 
 struct Domain {
     float cen[3];
@@ -98,10 +103,9 @@ struct QueryMlpArgs {
 };
 
 template <bool CUBIC, int DT>
-// The register budget of 3 waves per SIMD (168 VGPRs) schedules the tile
-// loop better than the default 2 (248): 67 against 74 ms on the learned
-// workload, same bits.
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void query_mlp_kernel(QueryMlpArgs p) {
+// The register budget of 3 waves per SIMD (168 VGPRs) also schedules the tile
+// loop better than the default 2 (248).
+__global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) void query_mlp_kernel(QueryMlpArgs p) {
     __shared__ __bf16 sW2[WTILE_ELEMS];
     __shared__ __bf16 sW3[WTILE_ELEMS];
     __shared__ SmallParams sp;
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3))) 
         if (lane == 0 && w < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(w));
         best = INFINITY;
     };
-    for (int64_t t = t0 + wave; t < t1; t += kWaves) {
+    for (int64_t t = t0 + wave; t < t1; t += kQueryWaves) {
         const int c = (int)(t / p.tiles_per_c);
         const int64_t j0 = (t - (int64_t)c * p.tiles_per_c) * TILE;
         if (c != cur) {
@@ -696,20 +700,21 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
     if (a.tiles_per_link > 0) {
         const int cus = device_cus();
         if (cus <= 0) return fail(LSDF_E_DEVICE, "query_mlp: cannot read the device's compute-unit count");
+        // one round of workgroups: as many per link as leave no CU with two
         const int64_t per_link = std::max<int64_t>(
-            1, std::min<int64_t>(((int64_t)cus * kBlocksPerCu + L - 1) / L, (a.tiles_per_link + kWaves - 1) / kWaves));
+            1, std::min<int64_t>((int64_t)cus / L, (a.tiles_per_link + kQueryWaves - 1) / kQueryWaves));
         const dim3 grid((unsigned)per_link, L);
         if ((rc = launch_zero_words(a.keys, (int64_t)C * L, s)) != LSDF_OK) return rc;
         hipEvent_t ev0, ev1;
         take_kernel_events(&ev0, &ev1);
         if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return fail(LSDF_E_DEVICE, "query_mlp: event record failed");
         switch (dtype * 2 + (cubic ? 1 : 0)) {
-            case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((query_mlp_kernel<true, LSDF_F32>), grid, dim3(kBlock), 0, s, a); break;
-            case LSDF_F32 * 2: hipLaunchKernelGGL((query_mlp_kernel<false, LSDF_F32>), grid, dim3(kBlock), 0, s, a); break;
-            case LSDF_BF16 * 2 + 1: hipLaunchKernelGGL((query_mlp_kernel<true, LSDF_BF16>), grid, dim3(kBlock), 0, s, a); break;
-            case LSDF_BF16 * 2: hipLaunchKernelGGL((query_mlp_kernel<false, LSDF_BF16>), grid, dim3(kBlock), 0, s, a); break;
-            case LSDF_F16 * 2 + 1: hipLaunchKernelGGL((query_mlp_kernel<true, LSDF_F16>), grid, dim3(kBlock), 0, s, a); break;
-            default: hipLaunchKernelGGL((query_mlp_kernel<false, LSDF_F16>), grid, dim3(kBlock), 0, s, a); break;
+            case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((query_mlp_kernel<true, LSDF_F32>), grid, dim3(kQueryBlock), 0, s, a); break;
+            case LSDF_F32 * 2: hipLaunchKernelGGL((query_mlp_kernel<false, LSDF_F32>), grid, dim3(kQueryBlock), 0, s, a); break;
+            case LSDF_BF16 * 2 + 1: hipLaunchKernelGGL((query_mlp_kernel<true, LSDF_BF16>), grid, dim3(kQueryBlock), 0, s, a); break;
+            case LSDF_BF16 * 2: hipLaunchKernelGGL((query_mlp_kernel<false, LSDF_BF16>), grid, dim3(kQueryBlock), 0, s, a); break;
+            case LSDF_F16 * 2 + 1: hipLaunchKernelGGL((query_mlp_kernel<true, LSDF_F16>), grid, dim3(kQueryBlock), 0, s, a); break;
+            default: hipLaunchKernelGGL((query_mlp_kernel<false, LSDF_F16>), grid, dim3(kQueryBlock), 0, s, a); break;
         }
         if ((rc = check_launch("query_min_distance_mlp")) != LSDF_OK) return rc;
         if (ev1 && hipEventRecord(ev1, s) != hipSuccess) return fail(LSDF_E_DEVICE, "query_mlp: event record failed");
