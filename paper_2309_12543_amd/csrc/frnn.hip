@@ -33,6 +33,7 @@ constexpr int kH = LSDF_FRNN_HIDDEN;
 constexpr int kRows = 128;          // output rows per workgroup
 constexpr int kMaxB = 64;           // rotations per training step
 constexpr int kTile = 64;           // rotations per tile in the max-error kernel
+constexpr int kReduceThreads = 1024;   // the single workgroup of the last reduction
 constexpr int kSlices = 64;         // first level of the partial-sum reduction
 
 struct Layout {
@@ -208,35 +209,67 @@ __global__ __launch_bounds__(256) void frnn_slice_kernel(TrainArgs a) {
     const int sl = blockIdx.y;
     const int p = blockIdx.x * 256 + threadIdx.x;
     const int BH = a.B * kH;
+    // the sums run in the fixed order; their loads are issued kBatch at a time
+    constexpr int kBatch = 8;
     if (p < BH) {
         float s = 0.0f;
-        for (int blk = sl; blk < a.blocks; blk += kSlices) s += a.part_dh[(int64_t)blk * BH + p];
+        for (int blk0 = sl; blk0 < a.blocks; blk0 += kBatch * kSlices) {
+            float v[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int blk = blk0 + k * kSlices;
+                v[k] = blk < a.blocks ? a.part_dh[(int64_t)blk * BH + p] : 0.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k)
+                if (blk0 + k * kSlices < a.blocks) s += v[k];
+        }
         a.part2_dh[(int64_t)sl * BH + p] = s;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         float s = 0.0f;
-        for (int blk = sl; blk < a.blocks; blk += kSlices) s += a.part_loss[blk];
+        for (int blk0 = sl; blk0 < a.blocks; blk0 += kBatch * kSlices) {
+            float v[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int blk = blk0 + k * kSlices;
+                v[k] = blk < a.blocks ? a.part_loss[blk] : 0.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k)
+                if (blk0 + k * kSlices < a.blocks) s += v[k];
+        }
         a.part2_loss[sl] = s;
     }
 }
 
 // One workgroup: sums the slices, then the first layer's gradient through
 // the ReLU.
-__global__ __launch_bounds__(256) void frnn_reduce_kernel(TrainArgs a) {
+__global__ __launch_bounds__(kReduceThreads) void frnn_reduce_kernel(TrainArgs a) {
     __shared__ float dz[kMaxB][kH];
+    __shared__ float rs[kMaxB * 9];
     const int tid = threadIdx.x;
     const int B = a.B;
-    for (int p = tid; p < B * kH; p += 256) {
+    for (int k = tid; k < B * 9; k += kReduceThreads) rs[k] = a.R[k];
+    // the slices are summed in order, with 16 loads in flight per thread
+    for (int p = tid; p < B * kH; p += kReduceThreads) {
         float s = 0.0f;
-        for (int sl = 0; sl < kSlices; ++sl) s += a.part2_dh[(int64_t)sl * B * kH + p];
+#pragma unroll
+        for (int sl0 = 0; sl0 < kSlices; sl0 += 16) {
+            float v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = a.part2_dh[(int64_t)(sl0 + k) * B * kH + p];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) s += v[k];
+        }
         dz[p / kH][p % kH] = a.z[p] > 0.0f ? s : 0.0f;
     }
     __syncthreads();
-    for (int p = tid; p < kH * 10; p += 256) {
+    for (int p = tid; p < kH * 10; p += kReduceThreads) {
         if (p < kH * 9) {
             const int u = p / 9, k = p - u * 9;
             float s = 0.0f;
-            for (int b = 0; b < B; ++b) s = fmaf(dz[b][u], a.R[b * 9 + k], s);
+            for (int b = 0; b < B; ++b) s = fmaf(dz[b][u], rs[b * 9 + k], s);
             a.grad[a.lay.w1 + p] = s;
         } else {
             const int u = p - kH * 9;
@@ -246,8 +279,12 @@ __global__ __launch_bounds__(256) void frnn_reduce_kernel(TrainArgs a) {
         }
     }
     if (tid == 0 && a.loss_out) {
+        float v[kSlices];
+#pragma unroll
+        for (int sl = 0; sl < kSlices; ++sl) v[sl] = a.part2_loss[sl];
         float s = 0.0f;
-        for (int sl = 0; sl < kSlices; ++sl) s += a.part2_loss[sl];
+#pragma unroll
+        for (int sl = 0; sl < kSlices; ++sl) s += v[sl];
         a.loss_out[0] = s / ((float)B * (float)a.lay.O);
     }
 }
@@ -404,7 +441,7 @@ LSDF_API int lsdf_frnn_train_step(float* params, float* adam_m, float* adam_v, i
     if ((rc = check_launch("frnn_train_step (output)")) != LSDF_OK) return rc;
     hipLaunchKernelGGL(frnn_slice_kernel, dim3((B * kH + 255) / 256, kSlices), dim3(256), 0, s, a);
     if ((rc = check_launch("frnn_train_step (slices)")) != LSDF_OK) return rc;
-    hipLaunchKernelGGL(frnn_reduce_kernel, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(frnn_reduce_kernel, dim3(1), dim3(kReduceThreads), 0, s, a);
     if ((rc = check_launch("frnn_train_step (reduce)")) != LSDF_OK) return rc;
     if (!adam_m) return LSDF_OK;   // gradient only
     AdamArgs d{params, adam_m, adam_v, grad, a.lay.n, lr, beta1, beta2, eps,
