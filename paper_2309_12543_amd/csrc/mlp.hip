@@ -491,8 +491,17 @@ __global__ __launch_bounds__(256) void train_reduce_kernel(ReduceArgs p) {
     if (k < (int64_t)p.L * NPARAM) {
         const int l = (int)(k / NPARAM);
         const int pk = (int)(k - (int64_t)l * NPARAM);
+        // the split partials in order, their loads issued 8 at a time
         float gsum = 0.f;
-        for (int s = 0; s < p.nsplit; ++s) gsum += p.w.gpart[((int64_t)l * p.nsplit + s) * NPARAM + pk];
+        for (int s0 = 0; s0 < p.nsplit; s0 += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] = s0 + u < p.nsplit ? p.w.gpart[((int64_t)l * p.nsplit + s0 + u) * NPARAM + pk] : 0.f;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (s0 + u < p.nsplit) gsum += v[u];
+        }
         if (p.grad_out) p.grad_out[k] = gsum;
         if (p.adam) {
             const float mk = p.beta1 * p.m[k] + (1.0f - p.beta1) * gsum;
@@ -502,11 +511,15 @@ __global__ __launch_bounds__(256) void train_reduce_kernel(ReduceArgs p) {
             p.params[k] -= p.lr * (mk / p.c1) / (sqrtf(vk / p.c2) + p.eps);
         }
     }
-    if (p.loss_out && k < p.L) {
+    // mean loss per link: wave l sums link l's tiles (lanes stride them, then a butterfly)
+    if (p.loss_out && k < (int64_t)p.L * 64) {
+        const int l = (int)(k >> 6), lane = (int)(k & 63);
         const int tiles = p.B / TILE_TRAIN;
         float s = 0.f;
-        for (int t = 0; t < tiles; ++t) s += p.w.loss[k * tiles + t];
-        p.loss_out[k] = s / (float)p.B;
+        for (int t = lane; t < tiles; t += 64) s += p.w.loss[(int64_t)l * tiles + t];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) p.loss_out[l] = s / (float)p.B;
     }
 }
 
