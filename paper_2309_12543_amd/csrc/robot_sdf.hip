@@ -267,18 +267,26 @@ __global__ __launch_bounds__(kBlock) void runtime_zero_kernel(RuntimeArgs a) {
 
 __global__ __launch_bounds__(kBlock) void voxelise_kernel(RuntimeArgs a) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= a.M) return;
-    int64_t q[3];
+    bool inside = j < a.M;
+    int64_t q[3] = {0, 0, 0};
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        const double u = floor(((double)a.points[3 * j + ax] - a.lo[ax]) / a.r);
-        if (!(u >= 0.0 && u < (double)a.n[ax])) return;   // outside the environment
-        q[ax] = (int64_t)u;
+        const double u = inside ? floor(((double)a.points[3 * j + ax] - a.lo[ax]) / a.r) : -1.0;
+        inside = inside && u >= 0.0 && u < (double)a.n[ax];   // points outside the environment are dropped
+        q[ax] = inside ? (int64_t)u : 0;
     }
     const int64_t v = (q[2] * a.n[1] + q[1]) * (int64_t)a.n[0] + q[0];
     const uint32_t bit = 1u << (v & 31);
-    const uint32_t old = atomicOr(&a.bitmap[v >> 5], bit);
-    if (!(old & bit)) a.list[atomicAdd(a.count, 1u)] = (uint32_t)v;   // first point of this voxel
+    const bool first = inside && !(atomicOr(&a.bitmap[v >> 5], bit) & bit);   // first point of this voxel
+    // the wave's new voxels take consecutive list slots: one counter atomic per wave
+    const uint64_t mask = __ballot(first);
+    if (mask == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(mask);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(a.count, (uint32_t)__builtin_popcountll(mask));
+    base = __shfl(base, leader, 64);
+    if (first) a.list[base + (uint32_t)__builtin_popcountll(mask & ((1ull << lane) - 1))] = (uint32_t)v;
 }
 
 // One workgroup per configuration: the minimum of its Robot SDF over the
