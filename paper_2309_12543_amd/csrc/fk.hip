@@ -22,14 +22,16 @@ __global__ __launch_bounds__(256) void fk_kernel(FkArgs p) {
     float* out = p.out + (int64_t)c * (dof + 1) * 12;
 #pragma unroll
     for (int k = 0; k < 12; ++k) out[k] = T[k];
-    const float* q = p.q + (int64_t)c * dof;
-    for (int j = 0; j < dof; ++j) {
-        float st, ct;
-        sincosf(q[j] + p.dh.off[j], &st, &ct);
-        lsdf::compose_dh(T, ct, st, p.dh.ca[j], p.dh.sa[j], p.dh.a[j], p.dh.d[j]);
-        float* o = out + 12 * (j + 1);
+    float st[LSDF_MAX_DOF], ct[LSDF_MAX_DOF];
+    lsdf::joint_sincos(p.dh, p.q + (int64_t)c * dof, st, ct);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) o[k] = T[k];
+    for (int j = 0; j < LSDF_MAX_DOF; ++j) {
+        if (j < dof) {
+            lsdf::compose_dh(T, ct[j], st[j], p.dh.ca[j], p.dh.sa[j], p.dh.a[j], p.dh.d[j]);
+            float* o = out + 12 * (j + 1);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) o[k] = T[k];
+        }
     }
 }
 

@@ -36,16 +36,30 @@ __device__ inline void compose_dh(float (&T)[12], float ct, float st, float ca, 
     for (int k = 0; k < 12; ++k) T[k] = r[k];
 }
 
+// Sine and cosine of every joint angle q[j] + offset_j, j < dof.  They do
+// not depend on one another or on the chain, so all the loads and all the
+// evaluations are issued together rather than one joint at a time.
+__device__ inline void joint_sincos(const DhTable& t, const float* q, float (&st)[LSDF_MAX_DOF],
+                                    float (&ct)[LSDF_MAX_DOF]) {
+    float qv[LSDF_MAX_DOF];
+#pragma unroll
+    for (int j = 0; j < LSDF_MAX_DOF; ++j)
+        if (j < t.dof) qv[j] = q[j];
+#pragma unroll
+    for (int j = 0; j < LSDF_MAX_DOF; ++j)
+        if (j < t.dof) sincosf(qv[j] + t.off[j], &st[j], &ct[j]);
+}
+
 // Pose of frame `link` (0 = base) at joint angles q[0..dof): the base
 // composed with joints 0 .. link-1, in the order the kinematics kernel uses.
 __device__ inline void chain_pose(const DhTable& t, const float* q, int link, float (&T)[12]) {
+    float st[LSDF_MAX_DOF], ct[LSDF_MAX_DOF];
+    joint_sincos(t, q, st, ct);
 #pragma unroll
     for (int k = 0; k < 12; ++k) T[k] = t.base[k];
-    for (int j = 0; j < link; ++j) {
-        float st, ct;
-        sincosf(q[j] + t.off[j], &st, &ct);
-        compose_dh(T, ct, st, t.ca[j], t.sa[j], t.a[j], t.d[j]);
-    }
+#pragma unroll
+    for (int j = 0; j < LSDF_MAX_DOF; ++j)
+        if (j < link) compose_dh(T, ct[j], st[j], t.ca[j], t.sa[j], t.a[j], t.d[j]);
 }
 
 }  // namespace lsdf

@@ -137,6 +137,7 @@ struct PrepArgs {
     const int32_t* c_off;    // device [K + 1] or NULL (one trajectory of all C)
     const int64_t* m_off;    // device [K + 1] or NULL (one trajectory of all M)
     int64_t M;
+    int64_t sphere_base;     // first thread of the sphere job: C L rounded up to the wave size
     int32_t C;
     int32_t K;
     int32_t L;
@@ -428,64 +429,8 @@ __device__ __forceinline__ void block_and_quad_spheres(const float* __restrict__
     if ((b & (kSphereBatch - 1)) == 0) *quad_out = widen(cx, cy, cz, r2);
 }
 
-// First kernel of a query.  Thread t < C L zeroes key t and writes the map
-// table entry of (link t / C, configuration t mod C), from the given pose or,
-// in the fused form, from the pose it computes from the joint angles.  Thread
-// t < ceil(M / 8) bounds block t of 8 consecutive points of the concatenated
-// cloud by a sphere, and thread t < ceil(M / 32) bounds quad t (blocks 4t to
-// 4t + 3) by another.  Workgroup 0 also builds the plan: each trajectory's
-// ranges clamped into [0, C) and [0, M) (so a bad offset table gives wrong
-// ranges, never an access out of bounds), its chunk count and the exclusive
-// prefix sum of the counts.
-__global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
-    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (b < (int64_t)a.C * a.L) {
-        a.keys[b] = 0u;
-        // map of link i at configuration c: row a of R^T scaled by invh_a,
-        // offset -invh_a (R^T t)_a + cen_a (the inverse pose of Eq. 4 with
-        // the grid scaling folded in); then the culling thresholds: the
-        // row norms (x (1 + 1e-6)) and half_a plus a bound on FP32 rounding
-        const int i = (int)(b / a.C);
-        const int64_t c = b - (int64_t)i * a.C;
-        const LinkGrid& lg = a.link[i];
-        float Tq[12];
-        const float* T = a.link_T + (c * a.L + i) * 12;
-        if (a.q) {
-            // the pose from the joint angles, with the kinematics kernel's
-            // arithmetic (same bits as lsdf_fk_batch)
-            lsdf::chain_pose(a.dh, a.q + c * a.dh.dof, i, Tq);
-            if (a.link_T_out) {
-                float* o = a.link_T_out + (c * a.L + i) * 12;
-#pragma unroll
-                for (int k = 0; k < 12; ++k) o[k] = Tq[k];
-            }
-            T = Tq;
-        }
-        const float r00 = T[0], r01 = T[1], r02 = T[2], t0 = T[3];
-        const float r10 = T[4], r11 = T[5], r12 = T[6], t1 = T[7];
-        const float r20 = T[8], r21 = T[9], r22 = T[10], t2 = T[11];
-        float f[kMapFields];
-        f[0] = lg.invh[0] * r00; f[1] = lg.invh[0] * r10; f[2] = lg.invh[0] * r20;
-        f[3] = lg.invh[1] * r01; f[4] = lg.invh[1] * r11; f[5] = lg.invh[1] * r21;
-        f[6] = lg.invh[2] * r02; f[7] = lg.invh[2] * r12; f[8] = lg.invh[2] * r22;
-        f[9] = fmaf(-lg.invh[0], fmaf(r00, t0, fmaf(r10, t1, r20 * t2)), lg.cen[0]);
-        f[10] = fmaf(-lg.invh[1], fmaf(r01, t0, fmaf(r11, t1, r21 * t2)), lg.cen[1]);
-        f[11] = fmaf(-lg.invh[2], fmaf(r02, t0, fmaf(r12, t1, r22 * t2)), lg.cen[2]);
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            const float* m = f + 3 * ax;
-            f[12 + ax] = sqrtf(fmaf(m[0], m[0], fmaf(m[1], m[1], m[2] * m[2]))) * 1.000001f;
-            f[15 + ax] = lg.half[ax] + fmaf(1e-4f, fabsf(f[9 + ax]), 1e-3f);
-        }
-        float* out = a.maps + (int64_t)i * kMapFields * a.C + c;
-#pragma unroll
-        for (int k = 0; k < kMapFields; ++k) out[(int64_t)k * a.C] = f[k];
-    }
-    // uniform over the four lanes of a quad (blocks 4 q .. 4 q + 3 are threads 4 q .. 4 q + 3)
-    if (b / kSphereBatch * kQuadPts < a.M)
-        block_and_quad_spheres(a.points, b, a.M, &a.spheres[b], &a.qspheres[b / kSphereBatch]);
-    if (blockIdx.x != 0) return;
-
+// The plan of the batched queries (in one workgroup of 256 threads).
+__device__ __forceinline__ void build_plan(const PrepArgs& a) {
     __shared__ int64_t scan[256];
     const int t = threadIdx.x;
     int64_t carry = 0;
@@ -527,6 +472,76 @@ __global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
         TrajPlan e{};
         e.chunk_start = carry;
         a.plan[a.K] = e;
+    }
+}
+
+// First kernel of a query, three independent jobs on separate threads so
+// that their latencies overlap.  Thread t < C L zeroes key t and writes the
+// map table entry of (link t / C, configuration t mod C), from the given pose
+// or, in the fused form, from the pose it computes from the joint angles.
+// Thread sphere_base + s bounds block s of 8 consecutive points of the
+// concatenated cloud by a sphere, and with its quad's three other lanes quad
+// s / 4 (blocks s - s mod 4 to s - s mod 4 + 3) by another (sphere_base is
+// a multiple of the wave size, so every wave holds whole quads).  The last
+// workgroup builds the plan: each trajectory's ranges clamped into [0, C)
+// and [0, M) (so a bad offset table gives wrong ranges, never an access out
+// of bounds), its chunk count and the exclusive prefix sum of the counts.
+__global__ __launch_bounds__(256) void prep_kernel(PrepArgs a) {
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x == gridDim.x - 1) {
+        build_plan(a);
+        return;
+    }
+    if (b >= a.sphere_base) {
+        const int64_t sb = b - a.sphere_base;
+        // uniform over the four lanes of a quad
+        if (sb / kSphereBatch * kQuadPts < a.M)
+            block_and_quad_spheres(a.points, sb, a.M, &a.spheres[sb], &a.qspheres[sb / kSphereBatch]);
+        return;
+    }
+    if (b < (int64_t)a.C * a.L) {
+        a.keys[b] = 0u;
+        // map of link i at configuration c: row a of R^T scaled by invh_a,
+        // offset -invh_a (R^T t)_a + cen_a (the inverse pose of Eq. 4 with
+        // the grid scaling folded in); then the culling thresholds: the
+        // row norms (x (1 + 1e-6)) and half_a plus a bound on FP32 rounding
+        const int i = (int)(b / a.C);
+        const int64_t c = b - (int64_t)i * a.C;
+        const LinkGrid& lg = a.link[i];
+        float T[12];
+        if (a.q) {
+            // the pose from the joint angles, with the kinematics kernel's
+            // arithmetic (same bits as lsdf_fk_batch)
+            lsdf::chain_pose(a.dh, a.q + c * a.dh.dof, i, T);
+            if (a.link_T_out) {
+                float* o = a.link_T_out + (c * a.L + i) * 12;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) o[k] = T[k];
+            }
+        } else {
+            const float* src = a.link_T + (c * a.L + i) * 12;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) T[k] = src[k];
+        }
+        const float r00 = T[0], r01 = T[1], r02 = T[2], t0 = T[3];
+        const float r10 = T[4], r11 = T[5], r12 = T[6], t1 = T[7];
+        const float r20 = T[8], r21 = T[9], r22 = T[10], t2 = T[11];
+        float f[kMapFields];
+        f[0] = lg.invh[0] * r00; f[1] = lg.invh[0] * r10; f[2] = lg.invh[0] * r20;
+        f[3] = lg.invh[1] * r01; f[4] = lg.invh[1] * r11; f[5] = lg.invh[1] * r21;
+        f[6] = lg.invh[2] * r02; f[7] = lg.invh[2] * r12; f[8] = lg.invh[2] * r22;
+        f[9] = fmaf(-lg.invh[0], fmaf(r00, t0, fmaf(r10, t1, r20 * t2)), lg.cen[0]);
+        f[10] = fmaf(-lg.invh[1], fmaf(r01, t0, fmaf(r11, t1, r21 * t2)), lg.cen[1]);
+        f[11] = fmaf(-lg.invh[2], fmaf(r02, t0, fmaf(r12, t1, r22 * t2)), lg.cen[2]);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const float* m = f + 3 * ax;
+            f[12 + ax] = sqrtf(fmaf(m[0], m[0], fmaf(m[1], m[1], m[2] * m[2]))) * 1.000001f;
+            f[15 + ax] = lg.half[ax] + fmaf(1e-4f, fabsf(f[9 + ax]), 1e-3f);
+        }
+        float* out = a.maps + (int64_t)i * kMapFields * a.C + c;
+#pragma unroll
+        for (int k = 0; k < kMapFields; ++k) out[(int64_t)k * a.C] = f[k];
     }
 }
 
@@ -732,9 +747,11 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
         a.K = K;
         a.L = L;
         a.chunk_quads = p.chunk_quads;
-        const int64_t nsph = (M + kBlockPts - 1) / kBlockPts;
-        const int64_t threads = std::max<int64_t>(nsph, (int64_t)C * L);
-        hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
+        // map threads, then (from a wave boundary) one thread per block of
+        // every quad, then the plan's workgroup
+        a.sphere_base = ((int64_t)C * L + 63) / 64 * 64;
+        const int64_t threads = a.sphere_base + kSphereBatch * quad_count(M);
+        hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((threads + 255) / 256 + 1)), dim3(256), 0, s, a);
         rc = check_launch(who);
         if (rc != LSDF_OK) return rc;
     }
