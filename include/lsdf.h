@@ -178,9 +178,9 @@ typedef struct {
     int32_t chunk_points;   /* points per work chunk: a multiple of 8 in
                                [8, 8192], rounded up to a multiple of 32
                                (a chunk takes every n-th run of 32 points of
-                               its trajectory's cloud); 0 = default (about
-                               two chunks per wave of the grid for C and M,
-                               32 to 1024 points) */
+                               its trajectory's cloud); 0 = default (at
+                               most about one chunk per wave of the grid
+                               for C and M, 32 to 1024 points) */
     int32_t blocks_per_cu;  /* workgroups of the persistent grid per compute
                                unit, in [1, 16]; 0 = default (as many as fit
                                on a CU at once) */

@@ -77,9 +77,10 @@ static_assert(kUnroll == kBlockPts, "blocks of 8 points");
 
 // Default tiling: as many workgroups per CU as can be resident at once (so
 // that no wave of the persistent grid waits for another to finish; 8 if
-// the runtime cannot say), chunks dealt over the whole grid, about two
-// chunks per wave of the grid for the call's sizes (with offset arrays, the
-// capacities C and M), a power of two between 4 and 128 blocks of 8 points.
+// the runtime cannot say), chunks dealt over the whole grid, at most about
+// one chunk per wave of the grid for the call's sizes (with offset arrays,
+// the capacities C and M): the smallest power of two of blocks of 8 points
+// between 4 and 128 that gives no more chunks than waves.
 constexpr int kDefaultChunkPoints = 1024;
 constexpr int kDefaultBlocksPerCu = 8;
 constexpr int kDefaultSchedule = LSDF_SCHED_INTERLEAVED;
@@ -87,7 +88,7 @@ constexpr int kDefaultSchedule = LSDF_SCHED_INTERLEAVED;
 int default_chunk_blocks(int64_t C, int64_t L, int64_t M, int64_t waves) {
     const int64_t units = L * ((C + 63) / 64) * ((M + kBlockPts - 1) / kBlockPts);
     int64_t cb = 4;
-    while (cb < 128 && 2 * cb * 2 * waves <= units) cb *= 2;
+    while (cb < 128 && cb * waves <= units) cb *= 2;
     return (int)cb;
 }
 constexpr int kMaxChunkPoints = 8192;
@@ -104,6 +105,20 @@ struct TrajPlan {
     int32_t pad[2];
 };
 static_assert(sizeof(TrajPlan) == 48, "plan entry layout");
+
+// A surviving block handed from the wave that found it to whichever wave of
+// the workgroup is free once every wave has tested its own chunks.
+struct Deferred {
+    uint64_t mask;             // lanes (configurations c0 + lane) whose box may reach the block
+    int64_t blk;               // block of 8 points in the concatenated cloud
+    int64_t m_lo, m_hi;        // the trajectory's points
+    int32_t c0;                // configuration of lane 0
+    int32_t link;
+};
+#ifndef LSDF_QUERY_DEFER
+#define LSDF_QUERY_DEFER 128       // surviving blocks a workgroup may pass between its waves
+#endif
+constexpr int kDeferCap = LSDF_QUERY_DEFER;
 
 struct QueryArgs {
     LinkGrid link[LSDF_MAX_LINKS];
@@ -228,33 +243,44 @@ __device__ __forceinline__ void block_min(const float* __restrict__ points, int6
     }
 }
 
-template <bool CUBIC, int DT>
-__global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float* __restrict__ points,
-                                                       const typename GridT<DT>::T* __restrict__ grid,
-                                                       const float4* __restrict__ spheres,
-                                                       const float4* __restrict__ qspheres,
-                                                       const TrajPlan* __restrict__ plan) {
-    using E = GridT<DT>;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t total = plan[p.K].chunk_start;
-    int64_t q_first, q_end, q_step;
-    if (p.schedule == LSDF_SCHED_XCD_SLICES) {
-        // each XCD (blocks b = x mod 8) takes a contiguous slice of chunks
-        // and deals it round-robin to its waves
-        const int xcd = blockIdx.x % kXcds;
-        const int slot = blockIdx.x / kXcds;
-        q_first = total * xcd / kXcds + slot * kWavesPerBlock + wave;
-        q_end = total * (xcd + 1) / kXcds;
-        q_step = (int64_t)p.blocks_per_xcd * kWavesPerBlock;
-    } else {
-        // every wave of the grid takes every W-th chunk
-        q_first = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-        q_end = total;
-        q_step = (int64_t)gridDim.x * kWavesPerBlock;
-    }
-    if (q_first >= q_end) return;
+// A 64-bit value that every lane holds alike, moved to scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
+// The 12 map entries of (link i, configuration c) from the table the first
+// kernel built; a lane with valid = false gets a map that sends every point
+// far outside the box.
+struct Map {
+    float m00, m01, m02, w0, m10, m11, m12, w1, m20, m21, m22, w2;
+};
+__device__ __forceinline__ void load_map(const QueryArgs& p, int i, int c, bool valid, Map& m) {
+    m = Map{0.f, 0.f, 0.f, kFar, 0.f, 0.f, 0.f, kFar, 0.f, 0.f, 0.f, kFar};
+    if (valid) {
+        const float* mp = p.maps + (int64_t)i * kMapFields * p.C + c;
+        const int64_t C = p.C;
+        m.m00 = mp[0 * C]; m.m01 = mp[1 * C]; m.m02 = mp[2 * C];
+        m.m10 = mp[3 * C]; m.m11 = mp[4 * C]; m.m12 = mp[5 * C];
+        m.m20 = mp[6 * C]; m.m21 = mp[7 * C]; m.m22 = mp[8 * C];
+        m.w0 = mp[9 * C]; m.w1 = mp[10 * C]; m.w2 = mp[11 * C];
+    }
+}
+
+// The first pass of a wave: the chunks q_first, q_first + q_step, ... below
+// q_end.  A chunk's quads are tested against every lane's box, then their
+// blocks; a block some lane's box may reach is appended to the workgroup's
+// list s_def while it has room (its points are tested after the workgroup's
+// barrier, by whichever wave is free) and tested here once the list is full.
+template <bool CUBIC, int DT>
+__device__ __forceinline__ void test_chunks(const QueryArgs& p, const float* __restrict__ points,
+                                            const typename GridT<DT>::T* __restrict__ grid,
+                                            const float4* __restrict__ spheres,
+                                            const float4* __restrict__ qspheres,
+                                            const TrajPlan* __restrict__ plan, int64_t q_first, int64_t q_end,
+                                            int64_t q_step, int lane, Deferred* s_def, int* ndef) {
+    using E = GridT<DT>;
     // trajectory of the first chunk: the last entry whose start is <= q
     int k = 0;
     {
@@ -349,6 +375,7 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
             }
             const int64_t jb = kQuadPts * qg;
             uint32_t near_mask = 0;
+            uint64_t lanes[kSphereBatch];
 #pragma unroll
             for (int u = 0; u < kSphereBatch; ++u) {
                 const float s0 = fmaf(m00, sph[u].x, fmaf(m01, sph[u].y, fmaf(m02, sph[u].z, w0)));
@@ -357,16 +384,84 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
                 const bool near = (fabsf(s0) <= fmaf(nr0, sph[u].w, k0)) & (fabsf(s1) <= fmaf(nr1, sph[u].w, k1)) &
                                   (fabsf(s2) <= fmaf(nr2, sph[u].w, k2));
                 const int64_t blk = kSphereBatch * qg + u;
-                if (__ballot(near) && blk >= blk0 && blk < blk1) near_mask |= 1u << u;
+                lanes[u] = __ballot(near);
+                if (lanes[u] && blk >= blk0 && blk < blk1) near_mask |= 1u << u;
             }
-            while (near_mask) {   // wave-uniform: blocks some lane's box may reach
+            // the blocks some lane's box may reach: handed to the workgroup
+            // while it has room, else tested here
+            int slot = kDeferCap;
+            if (near_mask && lane == 0 && *ndef < kDeferCap) slot = atomicAdd(ndef, __builtin_popcount(near_mask));
+            slot = __builtin_amdgcn_readfirstlane(slot);
+            while (near_mask) {   // wave-uniform
                 const int u = __builtin_ctz(near_mask);
                 near_mask &= near_mask - 1;
-                block_min<CUBIC, DT>(points, jb + u * kBlockPts, m_lo, m_hi, lg, G, nx, nxy, m00, m01, m02, w0, m10,
-                                     m11, m12, w1, m20, m21, m22, w2, best);
+                if (slot < kDeferCap) {
+                    if (lane == 0) s_def[slot] = Deferred{lanes[u], kSphereBatch * qg + u, m_lo, m_hi, c_lo + cb * 64, i};
+                    ++slot;
+                } else {
+                    block_min<CUBIC, DT>(points, jb + u * kBlockPts, m_lo, m_hi, lg, G, nx, nxy, m00, m01, m02, w0,
+                                         m10, m11, m12, w1, m20, m21, m22, w2, best);
+                }
             }
         }
         if (cl < c_n && best < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(best));
+    }
+}
+
+
+template <bool CUBIC, int DT>
+__global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float* __restrict__ points,
+                                                       const typename GridT<DT>::T* __restrict__ grid,
+                                                       const float4* __restrict__ spheres,
+                                                       const float4* __restrict__ qspheres,
+                                                       const TrajPlan* __restrict__ plan) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t total = plan[p.K].chunk_start;
+    int64_t q_first, q_end, q_step;
+    if (p.schedule == LSDF_SCHED_XCD_SLICES) {
+        // each XCD (blocks b = x mod 8) takes a contiguous slice of chunks
+        // and deals it round-robin to its waves
+        const int xcd = blockIdx.x % kXcds;
+        const int slot = blockIdx.x / kXcds;
+        q_first = total * xcd / kXcds + (int64_t)wave * p.blocks_per_xcd + slot;
+        q_end = total * (xcd + 1) / kXcds;
+        q_step = (int64_t)p.blocks_per_xcd * kWavesPerBlock;
+    } else {
+        // every wave of the grid takes every W-th chunk
+        q_first = (int64_t)wave * gridDim.x + blockIdx.x;
+        q_end = total;
+        q_step = (int64_t)gridDim.x * kWavesPerBlock;
+    }
+    // (the waves of one workgroup start a grid's width apart, on different
+    // links or configuration groups, so that their loads differ and the
+    // deferred blocks even them out)
+    __shared__ Deferred s_def[kDeferCap];
+    __shared__ int s_ndef;
+    if (threadIdx.x == 0) s_ndef = 0;
+    __syncthreads();
+    if (q_first < q_end)
+        test_chunks<CUBIC, DT>(p, points, grid, spheres, qspheres, plan, q_first, q_end, q_step, lane, s_def, &s_ndef);
+    __syncthreads();
+
+    // the deferred blocks, dealt round-robin to the workgroup's waves
+    const int nd = min(s_ndef, kDeferCap);
+    for (int it = wave; it < nd; it += kWavesPerBlock) {
+        const uint64_t mask = (uint64_t)uniform64((int64_t)s_def[it].mask);
+        const int64_t blk = uniform64(s_def[it].blk);
+        const int64_t m_lo = uniform64(s_def[it].m_lo), m_hi = uniform64(s_def[it].m_hi);
+        const int c0 = __builtin_amdgcn_readfirstlane(s_def[it].c0);
+        const int i = __builtin_amdgcn_readfirstlane(s_def[it].link);
+        const bool mine = (mask >> lane) & 1u;
+        const int c = c0 + lane;
+        const LinkGrid& lg = p.link[i];
+        Map mp;
+        load_map(p, i, c, mine, mp);
+        float best = INFINITY;
+        block_min<CUBIC, DT>(points, blk * kBlockPts, m_lo, m_hi, lg, grid + lg.offset, lg.n[0], lg.n[0] * lg.n[1],
+                             mp.m00, mp.m01, mp.m02, mp.w0, mp.m10, mp.m11, mp.m12, mp.w1, mp.m20, mp.m21, mp.m22,
+                             mp.w2, best);
+        if (mine && best < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(best));
     }
 }
 
@@ -918,3 +1013,4 @@ LSDF_API int lsdf_query_autotune(int32_t K, const int32_t* traj_c_offset, const 
     if (best_ms) *best_ms = best_t;
     return LSDF_OK;
 }
+
