@@ -321,7 +321,7 @@ def batched_variant(dev, steps: int, warmup: int):
     mo = torch.as_tensor(w.m_off, dtype=torch.int64, device=dev)
     T = lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T)
     ws = torch.zeros(lsdf.query_batched_workspace_size(w.K, w.C, w.L, w.M), dtype=torch.uint8, device=dev)
-    best, best_ms, _ = lsdf.query_autotune(T, gs, pts, co, mo, reps=3, workspace=ws)
+    best, best_ms, _ = lsdf.query_autotune(T, gs, pts, co, mo, reps=5, workspace=ws)
     log(f"batched variant: autotuner picked {best} ({best_ms:.3f} ms per call)")
     res = {}
     for name, tun in (("default", None), ("tuned", best)):

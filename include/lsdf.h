@@ -224,8 +224,9 @@ int lsdf_query_from_joints(const lsdf_dh* dh, int32_t dof, const float* base_T, 
  * Runs lsdf_query_min_distance_batched once untimed and `reps` times timed
  * (HIP events on `stream`) per candidate, and returns the candidate with
  * the lowest mean time in *best (and that time in ms in *best_ms, which may
- * be NULL).  candidates = NULL uses a built-in list (chunk_points 32 to
- * 4096, 5 and 8 workgroups per CU, both schedules).  1 <= reps <= 1000.
+ * be NULL).  candidates = NULL uses a built-in list (the default tiling
+ * first, then chunk_points 64 to 4096 on the resident grid, 4 workgroups per
+ * CU, and per-XCD slices).  1 <= reps <= 1000.
  * It SYNCHRONISES the stream (not capturable); out_dist / out_link hold the
  * problem's results when it returns LSDF_OK. */
 int lsdf_query_autotune(int32_t K, const int32_t* traj_c_offset, const int64_t* traj_m_offset,

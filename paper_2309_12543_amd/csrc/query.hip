@@ -956,13 +956,16 @@ LSDF_API int lsdf_query_autotune(int32_t K, const int32_t* traj_c_offset, const 
     if (!traj_c_offset || !traj_m_offset) return fail(LSDF_E_INVALID_ARG, "query_autotune: NULL offset array");
     if (!best) return fail(LSDF_E_INVALID_ARG, "query_autotune: best is NULL");
     if (reps < 1 || reps > 1000) return fail(LSDF_E_INVALID_ARG, "query_autotune: reps = %d out of [1, 1000]", (int)reps);
+    // the default tiling first (so the pick is never a tiling measured
+    // slower than it), then chunk sizes over the resident grid, a smaller
+    // grid, and the per-XCD slices
     static const lsdf_query_tuning kGrid[] = {
-        {32, 8, LSDF_SCHED_INTERLEAVED, 0},   {64, 8, LSDF_SCHED_INTERLEAVED, 0},
-        {128, 8, LSDF_SCHED_INTERLEAVED, 0},  {256, 8, LSDF_SCHED_INTERLEAVED, 0},
-        {1024, 8, LSDF_SCHED_INTERLEAVED, 0}, {32, 5, LSDF_SCHED_INTERLEAVED, 0},
-        {64, 5, LSDF_SCHED_INTERLEAVED, 0},   {32, 8, LSDF_SCHED_XCD_SLICES, 0},
-        {64, 8, LSDF_SCHED_XCD_SLICES, 0},    {256, 8, LSDF_SCHED_XCD_SLICES, 0},
-        {1024, 8, LSDF_SCHED_XCD_SLICES, 0},  {4096, 8, LSDF_SCHED_XCD_SLICES, 0},
+        {0, 0, LSDF_SCHED_DEFAULT, 0},        {64, 0, LSDF_SCHED_INTERLEAVED, 0},
+        {128, 0, LSDF_SCHED_INTERLEAVED, 0},  {256, 0, LSDF_SCHED_INTERLEAVED, 0},
+        {512, 0, LSDF_SCHED_INTERLEAVED, 0},  {1024, 0, LSDF_SCHED_INTERLEAVED, 0},
+        {2048, 0, LSDF_SCHED_INTERLEAVED, 0}, {4096, 0, LSDF_SCHED_INTERLEAVED, 0},
+        {256, 4, LSDF_SCHED_INTERLEAVED, 0},  {1024, 4, LSDF_SCHED_INTERLEAVED, 0},
+        {256, 0, LSDF_SCHED_XCD_SLICES, 0},   {1024, 0, LSDF_SCHED_XCD_SLICES, 0},
     };
     if (!candidates) {
         candidates = kGrid;
