@@ -216,6 +216,32 @@ def test_query_culling_is_exact_on_faces_and_nonrigid_poses(B, orc, tiny, tiny_g
     assert np.isfinite(gpu[2]).mean() > 0.5
 
 
+@pytest.mark.parametrize("chunk_points,blocks_per_cu", [(8192, 1), (256, 0), (32, 2)])
+def test_query_bit_exact_when_block_lists_fill(B, orc, tiny, tiny_grids, chunk_points, blocks_per_cu):
+    """A cloud packed inside the links' boxes makes nearly every block reach
+    some lane's box, so each workgroup's list of surviving blocks fills (it
+    holds 128) and the waves test the rest of their blocks themselves: both
+    paths must give the twin's bits, at every tiling."""
+    rng = np.random.default_rng(71)
+    C = min(64, len(tiny.q))
+    T32 = orc.fk(tiny.robot.dh, tiny.q[:C], tiny.robot.base_T).astype(np.float32)
+    pts = []
+    for _ in range(8192):
+        c, i = rng.integers(0, C), rng.integers(0, tiny.L)
+        l = rng.uniform(tiny.grid_lo[i], tiny.grid_hi[i])
+        pts.append(T32[c, i, :, :3].astype(np.float64) @ l + T32[c, i, :, 3])
+    pts = np.array(pts, dtype=np.float32)
+    gs = upload_grids(B, tiny, tiny_grids)
+    say(f"full lists: chunk_points={chunk_points} blocks_per_cu={blocks_per_cu} C={C} M={len(pts)}")
+    d, l, ld = B.query_min_distance_batched(
+        to_dev(T32), gs, to_dev(pts), to_dev([0, C], torch.int32), to_dev([0, len(pts)], torch.int64),
+        link_dist=True, tuning=B.make_tuning(chunk_points, blocks_per_cu, 2))
+    torch.cuda.synchronize()
+    gpu = d.cpu().numpy(), l.cpu().numpy(), ld.cpu().numpy()
+    assert_bit_exact(gpu, twin(orc, tiny, T32, tiny_grids, pts))
+    assert np.isfinite(gpu[2]).mean() > 0.9
+
+
 @pytest.mark.parametrize("dt", ["bf16", "f16"])
 def test_query_bit_exact_half_storage(B, orc, tiny, tiny_grids, paper, paper_grids, dt):
     """16-bit grids: the kernel widens each corner exactly to FP32, so the
