@@ -424,18 +424,20 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
         // and deals it round-robin to its waves
         const int xcd = blockIdx.x % kXcds;
         const int slot = blockIdx.x / kXcds;
-        q_first = total * xcd / kXcds + (int64_t)wave * p.blocks_per_xcd + slot;
+        q_first = total * xcd / kXcds + (int64_t)wave * p.blocks_per_xcd +
+                  ((wave & 1) ? p.blocks_per_xcd - 1 - slot : slot);
         q_end = total * (xcd + 1) / kXcds;
         q_step = (int64_t)p.blocks_per_xcd * kWavesPerBlock;
     } else {
         // every wave of the grid takes every W-th chunk
-        q_first = (int64_t)wave * gridDim.x + blockIdx.x;
+        q_first = (int64_t)wave * gridDim.x + ((wave & 1) ? gridDim.x - 1 - blockIdx.x : blockIdx.x);
         q_end = total;
         q_step = (int64_t)gridDim.x * kWavesPerBlock;
     }
     // (the waves of one workgroup start a grid's width apart, on different
     // links or configuration groups, so that their loads differ and the
-    // deferred blocks even them out)
+    // deferred blocks even them out; odd waves count the workgroups from the
+    // other end, which pairs a workgroup's early chunks with late ones)
     __shared__ Deferred s_def[kDeferCap];
     __shared__ int s_ndef;
     if (threadIdx.x == 0) s_ndef = 0;
