@@ -409,6 +409,16 @@ __device__ __forceinline__ void test_chunks(const QueryArgs& p, const float* __r
 }
 
 
+// Slot of workgroup b (of n) for its wave w: waves 2 and 3 shift by half
+// the grid and odd waves count from the other end, so that a workgroup's
+// four chunks come from four different parts of the chunk order (early and
+// late links, early and late configuration groups).  A bijection of [0, n)
+// for each w.
+__device__ __forceinline__ int mix_slot(int b, int n, int w) {
+    int s = (w & 2) ? (b + n / 2) % n : b;
+    return (w & 1) ? n - 1 - s : s;
+}
+
 template <bool CUBIC, int DT>
 __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float* __restrict__ points,
                                                        const typename GridT<DT>::T* __restrict__ grid,
@@ -424,20 +434,19 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
         // and deals it round-robin to its waves
         const int xcd = blockIdx.x % kXcds;
         const int slot = blockIdx.x / kXcds;
-        q_first = total * xcd / kXcds + (int64_t)wave * p.blocks_per_xcd +
-                  ((wave & 1) ? p.blocks_per_xcd - 1 - slot : slot);
+        q_first = total * xcd / kXcds + (int64_t)wave * p.blocks_per_xcd + mix_slot(slot, p.blocks_per_xcd, wave);
         q_end = total * (xcd + 1) / kXcds;
         q_step = (int64_t)p.blocks_per_xcd * kWavesPerBlock;
     } else {
         // every wave of the grid takes every W-th chunk
-        q_first = (int64_t)wave * gridDim.x + ((wave & 1) ? gridDim.x - 1 - blockIdx.x : blockIdx.x);
+        q_first = (int64_t)wave * gridDim.x + mix_slot((int)blockIdx.x, (int)gridDim.x, wave);
         q_end = total;
         q_step = (int64_t)gridDim.x * kWavesPerBlock;
     }
     // (the waves of one workgroup start a grid's width apart, on different
     // links or configuration groups, so that their loads differ and the
-    // deferred blocks even them out; odd waves count the workgroups from the
-    // other end, which pairs a workgroup's early chunks with late ones)
+    // deferred blocks even them out; mix_slot shuffles which workgroup each
+    // wave index lands in)
     __shared__ Deferred s_def[kDeferCap];
     __shared__ int s_ndef;
     if (threadIdx.x == 0) s_ndef = 0;
