@@ -13,10 +13,14 @@
 //     their box gather 8 corners and interpolate, with the loads of a batch
 //     of points issued together so that one wait covers them all;
 //   * points are culled 8 at a time: a first small kernel bounds every block
-//     of 8 consecutive points by a sphere, and a wave skips a block when no
-//     lane's box can hold any of its points (the sphere centre is mapped with
-//     the lane's own map; the test widens the box by the radius times the
-//     map's row norms plus a bound on FP32 rounding, so the skip is exact);
+//     of 8 consecutive points by a sphere (and every quad of 4 blocks by
+//     another), and a wave skips a quad or block when no lane's box can hold
+//     any of its points (the sphere centre is mapped with the lane's own map;
+//     the test widens the box by the radius times the map's row norms plus a
+//     bound on FP32 rounding, so the skip is exact);
+//   * a block that survives is recorded in a list in the workgroup's LDS;
+//     after a barrier the workgroup's waves share out the recorded blocks,
+//     so that a wave that drew many does not hold up the kernel alone;
 //   * a call may hold many trajectories, each a range of configurations
 //     checked against its own range of points (a re-planned path against
 //     its latest cloud); a plain query is the one-trajectory case.  The
@@ -29,11 +33,12 @@
 //     map and culling thresholds into a field-major table (one coalesced
 //     load per field per chunk) and zeroes the keys;
 //   * the iteration space (trajectory, link, 64-configuration group, point)
-//     is cut into chunks of a tunable number of 8-point blocks, dealt to the
-//     waves round-robin, either over the whole grid or inside per-XCD slices
+//     is cut into chunks of a tunable number of 8-point blocks (a chunk takes
+//     every n-th quad of its trajectory's cloud), dealt to the waves
+//     round-robin, either over the whole grid or inside per-XCD slices
 //     (blocks b = x mod 8 take a contiguous slice, which keeps an XCD on one
-//     or two links' grids in its L2); round-robin spreads dense regions of
-//     a cloud over many waves;
+//     or two links' grids in its L2); the four waves of a workgroup take
+//     chunks from four different parts of the order;
 //   * per-pair minima merge across waves with one unsigned atomic max on a
 //     complemented order-preserving key; a last small kernel turns the keys
 //     into the outputs (the kernel boundary orders it after every atomic,
