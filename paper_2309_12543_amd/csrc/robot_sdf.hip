@@ -265,7 +265,19 @@ __global__ __launch_bounds__(kBlock) void runtime_zero_kernel(RuntimeArgs a) {
     if (t == 0) *a.count = 0u;
 }
 
+// Voxels a workgroup's points fall in are first made unique in an LDS hash
+// set (open addressing, twice as many slots as points, so every insertion
+// ends within the table), and only one point per distinct voxel sets the
+// voxel's bit with a device atomic: points of one obstacle lie together in
+// the cloud, and their atomics on the same few bitmap words would otherwise
+// run one after another.
+constexpr int kHashSlots = 2 * kBlock;
+constexpr uint32_t kHashEmpty = 0xffffffffu;
+
 __global__ __launch_bounds__(kBlock) void voxelise_kernel(RuntimeArgs a) {
+    __shared__ uint32_t s_key[kHashSlots];
+    for (int k = threadIdx.x; k < kHashSlots; k += kBlock) s_key[k] = kHashEmpty;
+    __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     bool inside = j < a.M;
     int64_t q[3] = {0, 0, 0};
@@ -276,8 +288,23 @@ __global__ __launch_bounds__(kBlock) void voxelise_kernel(RuntimeArgs a) {
         q[ax] = inside ? (int64_t)u : 0;
     }
     const int64_t v = (q[2] * a.n[1] + q[1]) * (int64_t)a.n[0] + q[0];
+    // this point stands for its voxel in the workgroup when it inserts the
+    // voxel into the set first (voxel 2^32 - 1, the empty key, always does)
+    bool rep = inside && (uint32_t)v == kHashEmpty;
+    if (inside && !rep) {
+        uint32_t h = ((uint32_t)v * 2654435761u) % (uint32_t)kHashSlots;
+        for (int probe = 0; probe < kHashSlots; ++probe) {
+            const uint32_t prev = atomicCAS(&s_key[h], kHashEmpty, (uint32_t)v);
+            if (prev == kHashEmpty) {
+                rep = true;
+                break;
+            }
+            if (prev == (uint32_t)v) break;
+            h = (h + 1u) % (uint32_t)kHashSlots;
+        }
+    }
     const uint32_t bit = 1u << (v & 31);
-    const bool first = inside && !(atomicOr(&a.bitmap[v >> 5], bit) & bit);   // first point of this voxel
+    const bool first = rep && !(atomicOr(&a.bitmap[v >> 5], bit) & bit);   // first point of this voxel
     // the wave's new voxels take consecutive list slots: one counter atomic per wave
     const uint64_t mask = __ballot(first);
     if (mask == 0) return;
