@@ -299,6 +299,43 @@ ORC_EXPORT void orc_query_f64(const double* T, int32_t C, int32_t L, const doubl
     }
 }
 
+/* Every pair of the double query, for explaining a disagreement pair by pair
+ * (the per-link minimum hides which point set it).  For configuration c,
+ * link i and point j, at index e = (c L + i) M + j:
+ *   u[3 e + a] = the grid coordinate (R^T (x_j - t) - lo)_a / h_a, in or out
+ *                of [0, n_a - 1];
+ *   v[e]       = the trilinear interpolant at u clamped into the box (equal
+ *                to the query's value when u is inside; a finite value
+ *                for every pair).
+ * Same arithmetic as orc_query_f64 (definition of Sec. III-A). */
+ORC_EXPORT void orc_query_f64_each(const double* T, int32_t C, int32_t L, const double* lo, const double* hi,
+                                   const int32_t* n, const double* grids, const int64_t* offs, const double* P,
+                                   int64_t M, double* u_out, double* v_out) {
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+    for (int32_t c = 0; c < C; ++c) {
+        for (int32_t i = 0; i < L; ++i) {
+            const double* Ti = T + ((int64_t)c * L + i) * 12;
+            const double* lo_i = lo + 3 * i;
+            const double* hi_i = hi + 3 * i;
+            const int32_t* n_i = n + 3 * i;
+            double h[3];
+            for (int a = 0; a < 3; ++a) h[a] = (hi_i[a] - lo_i[a]) / (double)(n_i[a] - 1);
+            const int64_t e0 = ((int64_t)c * L + i) * M;
+            for (int64_t j = 0; j < M; ++j) {
+                double d[3] = {P[3 * j] - Ti[3], P[3 * j + 1] - Ti[7], P[3 * j + 2] - Ti[11]};
+                double u[3], uc[3];
+                for (int a = 0; a < 3; ++a) {
+                    double l = Ti[0 + a] * d[0] + Ti[4 + a] * d[1] + Ti[8 + a] * d[2];
+                    u[a] = (l - lo_i[a]) / h[a];
+                    uc[a] = u[a] < 0.0 ? 0.0 : (u[a] > (double)(n_i[a] - 1) ? (double)(n_i[a] - 1) : u[a]);
+                    u_out[3 * (e0 + j) + a] = u[a];
+                }
+                v_out[e0 + j] = orc_trilinear_f64(grids + offs[i], n_i, uc);
+            }
+        }
+    }
+}
+
 /* Exact (grid-free) per-link minima: the mesh SDF of link i at every point
  * expressed in link i's frame, over all points (no box).  Brute force, for
  * tiny inputs. */
@@ -663,6 +700,64 @@ ORC_EXPORT void orc_judge_min(const double* T, int32_t C, int32_t L, const doubl
             out[(int64_t)c * L + i] = best;
         }
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Clearance with the learned surrogate and its margin fallback (the build's */
+/* extension; the safety-margin rule, read as strict).  Per pair (c, i, j):  */
+/*   l = R^T (x - t) in double from the FP32 pose; the pair counts only if    */
+/*   l lies in link i's network domain, |(l_a - dom_c_a) / dom_h_a| <= 1;    */
+/*   m = the network of link i at the normalised point (mlp_forward_one,      */
+/*       bfloat16 rounding points when bf16 != 0);                           */
+/*   if m < margin and the single-precision twin places the point in the     */
+/*   grid box, the pair's value is the twin's grid value, else it is m (a     */
+/*   point outside the box keeps m: the grid has no value there).             */
+/* out[c][i] = the minimum over counted pairs (+inf if none).  each_m and     */
+/* each_g (optional, [C][L][M]) receive m (evaluated for every pair, in the  */
+/* domain or not) and the twin's grid value (+inf outside the box).          */
+/* ------------------------------------------------------------------------ */
+ORC_EXPORT void orc_query_mlp(const float* T, int32_t C, int32_t L, const float* lo, const float* hi,
+                              const int32_t* n, const float* grids, const int64_t* offs, const float* P,
+                              int64_t M, const double* params, const double* dom_c, const double* dom_h,
+                              double margin, int32_t bf16, double* out, double* each_m, double* each_g) {
+    float* gl = (float*)malloc(sizeof(float) * (size_t)L);
+    float* ge = (float*)malloc(sizeof(float) * (size_t)L * (size_t)(M > 0 ? M : 1));
+    for (int32_t c = 0; c < C; ++c) {
+        const float* Tc = T + (int64_t)c * L * 12;
+        query_f32_impl(Tc, 1, L, lo, hi, n, grids, offs, P, M, gl, ge);
+        for (int32_t i = 0; i < L; ++i) {
+            const float* Ti = Tc + (int64_t)i * 12;
+            const double* Pi = params + (int64_t)i * ORC_NPARAM;
+            const int64_t row = (int64_t)c * L + i;
+            double best = INFINITY;
+#pragma omp parallel for schedule(static) reduction(min : best)
+            for (int64_t j = 0; j < M; ++j) {
+                double d[3] = {(double)P[3 * j] - Ti[3], (double)P[3 * j + 1] - Ti[7], (double)P[3 * j + 2] - Ti[11]};
+                double xh[3];
+                int indom = 1;
+                for (int a = 0; a < 3; ++a) {
+                    double l = (double)Ti[0 + a] * d[0] + (double)Ti[4 + a] * d[1] + (double)Ti[8 + a] * d[2];
+                    xh[a] = (l - dom_c[3 * i + a]) / dom_h[3 * i + a];
+                    if (fabs(xh[a]) > 1.0) indom = 0;
+                }
+                const double g = (double)ge[(int64_t)i * M + j];
+                double m = INFINITY;
+                if (indom || each_m) {
+                    double z1[ORC_H], h1[ORC_H], z2[ORC_H], h2[ORC_H], z3[ORC_H], h3[ORC_H];
+                    m = mlp_forward_one(Pi, xh, bf16, z1, h1, z2, h2, z3, h3);
+                }
+                if (indom) {
+                    double v = (m < margin && g < INFINITY) ? g : m;
+                    if (v < best) best = v;
+                }
+                if (each_m) each_m[row * M + j] = m;
+                if (each_g) each_g[row * M + j] = g;
+            }
+            out[row] = best;
+        }
+    }
+    free(ge);
+    free(gl);
 }
 
 /* ------------------------------------------------------------------------ */

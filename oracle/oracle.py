@@ -61,6 +61,9 @@ def load():
     lib.orc_query_f64.restype = None
     lib.orc_query_f64.argtypes = [_dp, ct.c_int32, ct.c_int32, _dp, _dp, _ip, _dp, _lp, _dp,
                                   ct.c_int64, _dp]
+    lib.orc_query_f64_each.restype = None
+    lib.orc_query_f64_each.argtypes = [_dp, ct.c_int32, ct.c_int32, _dp, _dp, _ip, _dp, _lp, _dp, ct.c_int64,
+                                       _dp, _dp]
     lib.orc_query_f32.restype = None
     lib.orc_query_f32.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _fp, _ip, _fp, _lp, _fp,
                                   ct.c_int64, _fp]
@@ -83,6 +86,9 @@ def load():
     lib.orc_judge_min.restype = None
     lib.orc_judge_min.argtypes = [_dp, ct.c_int32, ct.c_int32, _dp, _dp, _ip, _dp, _lp, ct.POINTER(_dp),
                                   ct.POINTER(_ip), ct.POINTER(_ip), _ip, _dp, _dp, _dp, _dp, _dp, ct.c_int64, _dp]
+    lib.orc_query_mlp.restype = None
+    lib.orc_query_mlp.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _fp, _ip, _fp, _lp, _fp, ct.c_int64, _dp, _dp,
+                                  _dp, ct.c_double, ct.c_int32, _dp, _dp, _dp]
     lib.orc_query_f32_each.restype = None
     lib.orc_query_f32_each.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _fp, _ip, _fp, _lp, _fp, ct.c_int64, _fp,
                                        _fp]
@@ -213,6 +219,24 @@ def query_f64(T, lo, hi, n, grids, points) -> np.ndarray:
     lib.orc_query_f64(_ptr(T, _dp), C, L, _ptr(lo, _dp), _ptr(hi, _dp), _ptr(n, _ip),
                       _ptr(buf, _dp), _ptr(offs, _lp), _ptr(P, _dp), P.shape[0], _ptr(out, _dp))
     return out
+
+
+def query_f64_each(T, lo, hi, n, grids, points):
+    """Every pair of the double query: grid coordinates u [C][L][M][3] (in
+    or out of the box) and the trilinear value at u clamped into the box
+    [C][L][M] (finite for every pair)."""
+    lib = load()
+    T = _c(T, np.float64)
+    C, L = T.shape[0], T.shape[1]
+    lo, hi, n = _c(lo, np.float64), _c(hi, np.float64), _c(n, np.int32)
+    buf, offs = _pack(grids, np.float64)
+    P = _c(points, np.float64).reshape(-1, 3)
+    M = P.shape[0]
+    u = np.empty((C, L, M, 3), dtype=np.float64)
+    v = np.empty((C, L, M), dtype=np.float64)
+    lib.orc_query_f64_each(_ptr(T, _dp), C, L, _ptr(lo, _dp), _ptr(hi, _dp), _ptr(n, _ip), _ptr(buf, _dp),
+                           _ptr(offs, _lp), _ptr(P, _dp), M, _ptr(u, _dp), _ptr(v, _dp))
+    return u, v
 
 
 def query_f32(T, lo, hi, n, grids, points) -> np.ndarray:
@@ -414,6 +438,33 @@ def judge_min(T, lo, hi, n, grids, meshes, dom_c, dom_h, points) -> np.ndarray:
     return out
 
 
+def query_mlp(T, lo, hi, n, grids, points, params, dom_c, dom_h, margin, bf16=True, each=False):
+    """Per-link minima [C][L] of the learned clearance with its margin
+    fallback: network value per in-domain pair, replaced by the single-
+    precision twin's grid value when it is below the margin and the point is
+    in the grid box.  With each=True also returns the per-pair network values
+    (evaluated for every pair, in the domain or not) and twin grid values
+    (+inf outside the box), [C][L][M]."""
+    lib = load()
+    T = _c(T, np.float32)
+    C, L = T.shape[0], T.shape[1]
+    lo, hi, n = _c(lo, np.float32), _c(hi, np.float32), _c(n, np.int32)
+    buf, offs = _pack(grids, np.float32)
+    P = _c(points, np.float32).reshape(-1, 3)
+    M = P.shape[0]
+    prm = _c(params, np.float64).reshape(L, -1)
+    dc, dh = _c(dom_c, np.float64).reshape(L, 3), _c(dom_h, np.float64).reshape(L, 3)
+    out = np.empty((C, L), dtype=np.float64)
+    em = np.empty((C, L, M), dtype=np.float64) if each else None
+    eg = np.empty((C, L, M), dtype=np.float64) if each else None
+    null = ct.POINTER(ct.c_double)()
+    lib.orc_query_mlp(_ptr(T, _fp), C, L, _ptr(lo, _fp), _ptr(hi, _fp), _ptr(n, _ip), _ptr(buf, _fp),
+                      _ptr(offs, _lp), _ptr(P, _fp), M, _ptr(prm, _dp), _ptr(dc, _dp), _ptr(dh, _dp),
+                      float(margin), int(bool(bf16)), _ptr(out, _dp),
+                      _ptr(em, _dp) if each else null, _ptr(eg, _dp) if each else null)
+    return (out, em, eg) if each else out
+
+
 def reduce(cl):
     """Per configuration: (min over links, lowest argmin link or -1)."""
     lib = load()
@@ -502,6 +553,6 @@ def mlp_unpack(params):
 
 
 __all__ = ["FRNN_HIDDEN", "frnn_forward", "frnn_loss_grad", "frnn_nparam", "frnn_target", "align", "robot_sdf_f64", "robot_sdf_query", "voxel_centres", "voxel_index", "build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
-           "query_batched", "query_f32", "query_f32_each", "query_f64", "reduce", "trilinear_f64", "winding_number", "workload_grids",
+           "query_batched", "query_f32", "query_f32_each", "query_f64", "query_f64_each", "query_mlp", "reduce", "trilinear_f64", "winding_number", "workload_grids",
            "MLP_HIDDEN", "adam_step", "judge_min", "mlp_forward", "mlp_loss_grad", "mlp_nparam", "mlp_unpack",
            "max_threads", "set_threads"]

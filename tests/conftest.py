@@ -29,3 +29,14 @@ def tiny():
 @pytest.fixture(scope="session")
 def tiny_grids(orc, tiny):
     return orc.workload_grids(tiny)
+
+
+@pytest.fixture(scope="session")
+def paper():
+    import synth
+    return synth.make_workload("paper")
+
+
+@pytest.fixture(scope="session")
+def paper_grids(orc, paper):
+    return orc.workload_grids(paper)

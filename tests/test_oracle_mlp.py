@@ -5,7 +5,9 @@ SiLU), its L1 loss gradient and its Adam step.
   and SiLU layers in float64 (an independent library implementation);
 * gradient: equal to PyTorch autograd of the L1 loss in float64, and to
   central finite differences;
-* bfloat16 rounding: equal to PyTorch's float32 -> bfloat16 conversion;
+* bfloat16 rounding: equal to PyTorch's float32 -> bfloat16 conversion, in
+  the forward pass and at the two backward rounding points (the deltas of
+  layers 3 and 2), against PyTorch autograd in float64 with the same casts;
 * Adam: the first two steps against their closed forms.
 """
 import numpy as np
@@ -97,6 +99,76 @@ def test_bf16_rounding_matches_torch(orc):
     assert abs(got - orc.mlp_forward(P, np.zeros((1, 3)))[0]) > 1e-6     # rounding did happen
 
 
+class _RoundValue(torch.autograd.Function):
+    """Value rounded to bfloat16 (float64 -> float32 -> bfloat16, torch's own
+    round-to-nearest-even), gradient passed through unchanged."""
+    @staticmethod
+    def forward(ctx, x):
+        return x.float().bfloat16().double()
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+class _RoundGrad(torch.autograd.Function):
+    """Value unchanged, gradient rounded to bfloat16 on its way back."""
+    @staticmethod
+    def forward(ctx, x):
+        return x.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        return g.float().bfloat16().double()
+
+
+def _torch_bf16_grad(orc, P, X, Y, round_d3=True, round_d2=True, round_d1=False):
+    """L1 loss gradient of the network by PyTorch autograd in float64, with
+    the weights and the activations h1..h3 rounded to bfloat16 in the forward
+    pass and the gradients at the pre-activations z3, z2 (optionally z1)
+    rounded in the backward pass."""
+    rv, rg = _RoundValue.apply, _RoundGrad.apply
+    ts = [torch.tensor(a, requires_grad=True) for a in orc.mlp_unpack(P)]
+    W1, b1, W2, b2, W3, b3, w4, b4 = ts
+    x = torch.tensor(X)
+    z1 = x @ rv(W1).T + b1
+    if round_d1:
+        z1 = rg(z1)
+    h1 = rv(torch.nn.functional.silu(z1))
+    z2 = h1 @ rv(W2).T + b2
+    if round_d2:
+        z2 = rg(z2)
+    h2 = rv(torch.nn.functional.silu(z2))
+    z3 = h2 @ rv(W3).T + b3
+    if round_d3:
+        z3 = rg(z3)
+    h3 = rv(torch.nn.functional.silu(z3))
+    m = h3 @ rv(w4) + b4
+    loss = torch.nn.functional.l1_loss(m, torch.tensor(Y))
+    loss.backward()
+    return loss.item(), np.concatenate([t.grad.numpy().ravel() for t in ts])
+
+
+def test_bf16_backward_rounding_matches_torch(orc):
+    """The bfloat16 twin's gradient (the GPU kernels' rounding points: weights
+    and activations in the forward pass, the deltas of layers 3 and 2 before
+    they are multiplied) against PyTorch autograd in float64 with the same
+    casts placed independently.  Moving, dropping or adding one backward
+    rounding point changes the gradient far beyond the agreement found."""
+    P = rand_params(orc, 9, scale=2.0)
+    rng = np.random.default_rng(10)
+    X = rng.uniform(-1, 1, size=(48, 3))
+    Y = orc.mlp_forward(P, X, bf16=True) + rng.choice([-0.5, 0.5], size=48)
+    loss, g = orc.mlp_loss_grad(P, X, Y, bf16=True)
+    tl, tg = _torch_bf16_grad(orc, P, X, Y)
+    scale = np.abs(tg).max()
+    assert loss == pytest.approx(tl, abs=1e-13)
+    assert np.max(np.abs(g - tg)) <= 1e-12 * scale
+    for variant in ({"round_d3": False}, {"round_d2": False}, {"round_d1": True}):
+        _, vg = _torch_bf16_grad(orc, P, X, Y, **variant)
+        assert np.max(np.abs(g - vg)) > 1e-6 * scale, variant
+
+
 def test_adam_first_two_steps_closed_form(orc):
     rng = np.random.default_rng(8)
     n = 50
@@ -112,3 +184,69 @@ def test_adam_first_two_steps_closed_form(orc):
     mh = (b1 * (1 - b1) * g1 + (1 - b1) * g2) / (1 - b1 ** 2)
     vh = (b2 * (1 - b2) * g1 ** 2 + (1 - b2) * g2 ** 2) / (1 - b2 ** 2)
     assert np.allclose(P, P1 - lr * mh / (np.sqrt(vh) + eps), rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# learned clearance with the margin fallback (orc_query_mlp)
+# ---------------------------------------------------------------------------
+
+def _mlp_setup(orc, tiny, C=4):
+    import synth
+    T32 = orc.fk(tiny.robot.dh, tiny.q[:C], tiny.robot.base_T).astype(np.float32)
+    dc, dh = synth.mlp_domain(tiny.grid_lo.astype(np.float64), tiny.grid_hi.astype(np.float64))
+    pts = tiny.points[:600].astype(np.float32)
+    return T32, dc, dh, pts
+
+
+def _in_domain(T32, dc, dh, pts):
+    """[C][L][M] domain membership and normalised inputs, numpy double."""
+    T = T32.astype(np.float64)
+    loc = np.einsum("jb,clba->clja", pts.astype(np.float64), T[..., :3]) \
+        - np.einsum("clb,clba->cla", T[..., 3], T[..., :3])[:, :, None, :]
+    X = (loc - dc[None, :, None, :]) / dh[None, :, None, :]
+    return np.all(np.abs(X) <= 1.0, axis=-1), X
+
+
+def test_query_mlp_without_fallback_is_network_min(orc, tiny):
+    """margin = -inf: every in-domain pair takes the network's value, so the
+    per-link minimum is the bfloat16 twin network's minimum over the points
+    in that link's domain (domain test and inputs formed here in numpy)."""
+    T32, dc, dh, pts = _mlp_setup(orc, tiny)
+    P = np.stack([rand_params(orc, 20 + i) for i in range(tiny.L)])
+    g32 = [g.astype(np.float32) for g in orc.workload_grids(tiny)]
+    got = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P, dc, dh, -np.inf)
+    ind, X = _in_domain(T32, dc, dh, pts)
+    for c in range(T32.shape[0]):
+        for i in range(tiny.L):
+            want = orc.mlp_forward(P[i], X[c, i][ind[c, i]], bf16=True).min() if ind[c, i].any() else np.inf
+            assert got[c, i] == pytest.approx(want, abs=1e-12), (c, i)
+    assert np.isfinite(got).mean() > 0.5
+
+
+@pytest.mark.parametrize("k", [0.01, 0.05, 0.2])
+def test_query_mlp_fallback_rule_with_constant_network(orc, tiny, tiny_grids, k):
+    """A network that outputs the constant k (every weight zero, b4 = k)
+    at margin 0.05.  Below the margin (k = 0.01) an in-box pair takes the
+    single-precision twin's grid value and a pair outside the box keeps k;
+    at the margin itself (k = 0.05, the test is strict) and above it every
+    in-domain pair keeps k."""
+    T32, dc, dh, pts = _mlp_setup(orc, tiny)
+    P = np.zeros((tiny.L, orc.mlp_nparam()))
+    P[:, -1] = k
+    g32 = [g.astype(np.float32) for g in tiny_grids]
+    got = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P, dc, dh, 0.05)
+    ind, _ = _in_domain(T32, dc, dh, pts)
+    each = orc.query_f32_each(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts).astype(np.float64)
+    inbox = np.isfinite(each)
+    assert np.all(ind[inbox])                    # the grid box lies inside the domain
+    for c in range(T32.shape[0]):
+        for i in range(tiny.L):
+            if k < 0.05:
+                grid_part = each[c, i][inbox[c, i]].min() if inbox[c, i].any() else np.inf
+                far_part = k if (ind[c, i] & ~inbox[c, i]).any() else np.inf
+                want = min(grid_part, far_part)
+            else:
+                want = k if ind[c, i].any() else np.inf
+            assert got[c, i] == want, (c, i, got[c, i], want)
+    if k < 0.05:
+        assert (inbox.any(-1) & (got < k)).any()     # some minima come from the grid

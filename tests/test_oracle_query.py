@@ -302,3 +302,45 @@ def test_batched_is_per_configuration_min_over_covering_trajectories(orc, tiny, 
         want = orc.query_f32(T[c:c + 1], tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts[idx])[0]
         assert np.array_equal(got[c].astype(np.float32).view(np.uint32), want.view(np.uint32)), c
     assert covered >= 20 and np.isfinite(got).any()
+
+
+def test_twin_within_rounding_bound_of_double_per_pair(orc, paper, paper_grids):
+    """The single-precision twin against the double definition of Sec. III-A,
+    pair by pair on the paper workload (20 of its 500 configurations, every
+    link and point), with the same FP32 poses and FP32 grids on both sides so
+    that only the arithmetic differs.  Every pair the twin keeps lies within
+    the rounding bound of its operation order (tests/r10_bound.py) of the
+    double value; a pair kept by one side only lies within the coordinate
+    bound of a box face.  A transposed rotation in the twin's input moves the
+    values far outside that bound, so the bound has teeth."""
+    import r10_bound as rb
+    w = paper
+    sel = np.arange(0, w.C, 25)
+    T32 = orc.fk(w.robot.dh, w.q[sel], w.robot.base_T).astype(np.float32)
+    T64 = T32.astype(np.float64)
+    g32 = [g.astype(np.float32) for g in paper_grids]
+    g64 = [g.astype(np.float64) for g in g32]
+    lo, hi = w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64)
+    pts = w.points.astype(np.float32)
+    v32 = orc.query_f32_each(T32, w.grid_lo, w.grid_hi, w.grid_n, g32, pts).astype(np.float64)
+    u64, v64 = orc.query_f64_each(T64, lo, hi, w.grid_n, g64, pts.astype(np.float64))
+    du = rb.coord_bound(T64, lo, hi, w.grid_n, pts)
+    slack = rb.face_slack(u64, w.grid_n)
+    in64 = (slack >= 0).all(-1)
+    in32 = np.isfinite(v32)
+    assert in32.sum() > 10000, in32.sum()
+    diff = in64 != in32
+    near_face = (slack >= -du).all(-1) & (slack <= du).any(-1)
+    assert np.all(near_face[diff]), np.argwhere(diff & ~near_face)[:5]
+    vb = rb.value_bound(du, g64)
+    err = np.abs(v32 - v64)
+    assert np.all(err[in32] <= vb[in32]), np.max(err[in32] / vb[in32])
+    print(f"[oracle] {in32.sum()} kept pairs, {diff.sum()} kept by one side only; max |twin - double| "
+          f"{err[in32].max():.3g} m, bound up to {vb[in32].max():.3g} m, max ratio {np.max(err[in32] / vb[in32]):.3g}")
+    # teeth: the twin fed R instead of R^T
+    Tt = T32[:1].copy()
+    Tt[..., :3] = np.swapaxes(Tt[..., :3], -1, -2)
+    vt = orc.query_f32_each(Tt, w.grid_lo, w.grid_hi, w.grid_n, g32, pts).astype(np.float64)[0]
+    both = np.isfinite(vt) & in64[0]
+    moved = (np.abs(vt - v64[0]) > vb[0]) | (np.isfinite(vt) != in64[0])
+    assert moved.sum() > 0.5 * max(1, (np.isfinite(vt) | in64[0]).sum()), (moved.sum(), both.sum())
