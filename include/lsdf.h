@@ -280,7 +280,12 @@ int lsdf_robot_sdf_query_workspace_size(const lsdf_env* env, int64_t M, size_t* 
  * holding at least one of the points (voxel of x: floor((x - lo) / r),
  * in double; points outside the environment are ignored); +inf when no
  * point is inside.  workspace: device, 256-byte aligned, at least
- * lsdf_robot_sdf_query_workspace_size(env, M) bytes; contents ignored. */
+ * lsdf_robot_sdf_query_workspace_size(env, M) bytes; contents ignored.
+ * When the call's work has completed, the workspace holds the distinct
+ * occupied voxels for inspection: with V = n[0] n[1] n[2] and
+ * K = 256 * ceil(4 * ceil(V / 32) / 256), their count as a uint32 at byte
+ * K, and their flat indices (uint32, in no particular order) from byte
+ * K + 256 on. */
 int lsdf_robot_sdf_query(const float* robot_sdf, int32_t C, const lsdf_env* env,
                          const float* points, int64_t M, float* out_dist,
                          void* workspace, size_t ws_bytes, void* stream);
@@ -377,12 +382,16 @@ int lsdf_mlp_eval(const float* params, const lsdf_mlp_domain* domain, const floa
                   float* out, void* stream);
 
 /* Clearance with the learned surrogate: as lsdf_query_min_distance, but the
- * value of pair (c, i, j) is m = the network of link i at the point (if the
- * point lies in link i's domain; +inf otherwise), replaced by the grid value
- * (+inf outside the grid box) when m < margin.  Same workspace as
- * lsdf_query_min_distance (lsdf_query_workspace_size).  margin may be +inf
- * (every pair takes the grid value) or -inf (none does).  A pair that takes
- * the grid value gets exactly the bits lsdf_query_min_distance would give. */
+ * value of pair (c, i, j) is m = the network of link i at the point if the
+ * point lies in link i's domain (the pair is skipped otherwise), replaced by
+ * the grid value when m < margin (strict) and the point lies in link i's grid
+ * box.  A point outside the box keeps m whatever its value, since the grid
+ * has no value there (when the box pads the link's bounding box by at least
+ * the margin, such an m below the margin underestimates the distance).  Same
+ * workspace as lsdf_query_min_distance
+ * (lsdf_query_workspace_size).  margin may be +inf (every in-box pair takes
+ * the grid value) or -inf (none does).  A pair that takes the grid value gets
+ * exactly the bits lsdf_query_min_distance would give it. */
 int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t L, const lsdf_grid* grids,
                                 const void* grid_buf, const float* mlp_params, const lsdf_mlp_domain* domains,
                                 float margin, const float* points, int64_t M, float* out_dist, int32_t* out_link,

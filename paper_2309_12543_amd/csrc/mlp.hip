@@ -176,8 +176,14 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 if (!indom[nt]) continue;
-                const float v = m[nt] < p.margin ? sample_or_inf<CUBIC, DT>(G, lg, gm, px[nt][0], px[nt][1], px[nt][2])
-                                                 : m[nt];
+                // below the margin the grid's value replaces the estimate; a
+                // point outside the grid box keeps the estimate, since the
+                // grid has no value there
+                float v = m[nt];
+                if (m[nt] < p.margin) {
+                    const float g = sample_or_inf<CUBIC, DT>(G, lg, gm, px[nt][0], px[nt][1], px[nt][2]);
+                    if (g < INFINITY) v = g;
+                }
                 best = fminf(best, v);
             }
         }

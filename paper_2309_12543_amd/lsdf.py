@@ -497,9 +497,11 @@ def robot_sdf_build(link_T: torch.Tensor, grids: GridSet, env: lsdf_env, out: to
 
 
 def robot_sdf_query(robot_sdf: torch.Tensor, env: lsdf_env, points: torch.Tensor, out: torch.Tensor | None = None,
-                    stream=None) -> torch.Tensor:
+                    stream=None, workspace: torch.Tensor | None = None) -> torch.Tensor:
     """Per configuration, the minimum of its Robot SDF over the voxels the
-    points occupy (lsdf_robot_sdf_query)."""
+    points occupy (lsdf_robot_sdf_query).  ``workspace`` (uint8, optional)
+    is the call's workspace; afterwards it holds the distinct occupied voxels
+    as the header describes."""
     lib = load_library()
     _require(robot_sdf, "robot_sdf", torch.float32)
     C, dev = int(robot_sdf.shape[0]), robot_sdf.device
@@ -514,7 +516,11 @@ def robot_sdf_query(robot_sdf: torch.Tensor, env: lsdf_env, points: torch.Tensor
     _require(out, "out_dist", torch.float32, (C,))
     n = ct.c_size_t(0)
     _check(lib.lsdf_robot_sdf_query_workspace_size(ct.byref(env), M, ct.byref(n)))
-    ws = _cached_workspace(int(n.value), dev)
+    if workspace is None:
+        ws = _cached_workspace(int(n.value), dev)
+    else:
+        _require(workspace, "workspace", torch.uint8)
+        ws = workspace
     _check(lib.lsdf_robot_sdf_query(robot_sdf.data_ptr(), C, ct.byref(env), points.data_ptr() if M > 0 else None, M,
                                     out.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream, dev)))
     return out

@@ -42,7 +42,7 @@ def coord_bound(T, lo, hi, n, points):
     cen = np.abs(-lo * invh - 0.5 * (n - 1.0))                # [L][3]
     absR = np.abs(T[..., :3])                                 # [C][L][b][a]
     at = np.einsum("clba,clb->cla", absR, np.abs(T[..., 3]))  # sum_b |R_ba| |t_b|
-    ax = np.einsum("jb,clba->clja", P, absR)                  # sum_b |R_ba| |x_b|
+    ax = P @ absR                                             # sum_b |x_b| |R_ba|, [C][L][M][3]
     S = invh[None, :, None, :] * (ax + at[:, :, None, :] + np.abs(lo)[None, :, None, :]) \
         + (cen + (n - 1.0))[None, :, None, :]
     return K_MAP * U32 * S

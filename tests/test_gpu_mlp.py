@@ -3,7 +3,9 @@ the C ABI: network evaluation and L1-loss gradients against the oracle's
 bfloat16 twin (same rounding points, double accumulation) and its pure
 double network, the Adam step against the oracle's, labels against the
 oracle's grid and mesh distances, and the learned clearance query against
-the plain query (every pair falling back) and against the twin network."""
+the oracle's rule (orc_query_mlp): constant networks bit for bit, a finite
+margin pair by pair and per link at tiny and full size, and the network
+alone (no pair falling back) against the twin network."""
 import numpy as np
 import pytest
 import torch
@@ -148,25 +150,243 @@ def test_sdf_labels_match_oracle(B, orc, tiny, tiny_grids):
     assert np.abs(lab[out] - ref[out]).max() < 2e-6
 
 
-def test_query_mlp_all_fallback_equals_plain(B, orc, tiny, tiny_grids):
-    """With an infinite margin every pair takes the grid value: the learned
-    query must give the plain query's bits."""
-    cen, half = domains_of(tiny)
-    gs = B.GridSet(tiny.grid_lo, tiny.grid_hi, tiny.grid_n, device="cuda")
-    for k, g in enumerate(tiny_grids):
+def _poses(orc, w, sel):
+    return orc.fk(w.robot.dh, w.q[sel], w.robot.base_T).astype(np.float32)
+
+
+def _domain_bands(T32, cen, half, pts, eps=1e-5):
+    """[C][L][M] membership of each pair in its link's network domain, decided
+    in double from the FP32 poses with a band of +-eps (normalised units)
+    around the boundary: (surely inside, possibly inside).  The kernel and the
+    oracle form the normalised point in different precisions, so a pair in
+    the band may fall on either side."""
+    T = T32.astype(np.float64)
+    loc = np.einsum("jb,clba->clja", pts.astype(np.float64), T[..., :3]) \
+        - np.einsum("clb,clba->cla", T[..., 3], T[..., :3])[:, :, None, :]
+    r = np.abs((loc - cen.astype(np.float64)[None, :, None, :]) / half.astype(np.float64)[None, :, None, :]).max(-1)
+    return r <= 1.0 - eps, r <= 1.0 + eps
+
+
+def _grid_set(B, w, grids):
+    gs = B.GridSet(w.grid_lo, w.grid_hi, w.grid_n, device="cuda")
+    for k, g in enumerate(grids):
         gs.set_grid(k, g.astype(np.float32))
-    T = dev(orc.fk(tiny.robot.dh, tiny.q, tiny.robot.base_T).astype(np.float32))
-    pts = dev(tiny.points.astype(np.float32))
-    P = dev(params_f32(7, 3))
-    say("query_mlp margin=+inf vs plain")
-    d0, l0, ld0 = B.query_min_distance(T, gs, pts, link_dist=True)
-    # a workspace full of 0xFF: the learned query clears its keys first
-    ws = torch.full((B.query_workspace_size(tiny.C, 7, tiny.M),), 0xFF, dtype=torch.uint8, device="cuda")
-    d1, l1, ld1 = B.query_min_distance_mlp(T, gs, P, (cen, half), pts, margin=float("inf"), link_dist=True,
-                                           workspace=ws)
-    torch.cuda.synchronize()
-    assert torch.equal(ld0.view(torch.int32), ld1.view(torch.int32))
-    assert torch.equal(d0.view(torch.int32), d1.view(torch.int32)) and torch.equal(l0, l1)
+    return gs
+
+
+@pytest.mark.parametrize("k,margin", [(0.01, 0.05), (0.05, 0.05), (0.2, 0.05), (10.0, float("inf"))])
+def test_query_mlp_constant_network_matches_oracle(B, orc, tiny, tiny_grids, k, margin):
+    """A network whose output is the constant k (every weight zero, b4 = k)
+    gives the same value on the GPU and in the oracle, so the learned query's
+    per-link minima must equal the oracle's (orc_query_mlp) bit for bit: below
+    the margin an in-box pair takes the grid value and a pair outside the box
+    keeps k; at the margin (strict test) and above it every in-domain pair
+    keeps k.  With margin +inf and k above every grid value the result is the
+    plain query's wherever that is finite.  The workspace starts full of 0xFF:
+    the query clears its keys itself."""
+    sel = np.arange(0, tiny.C, 5)
+    T32 = _poses(orc, tiny, sel)
+    cen, half = domains_of(tiny)
+    pts = tiny.points.astype(np.float32)
+    g32 = [g.astype(np.float32) for g in tiny_grids]
+    gs = _grid_set(B, tiny, tiny_grids)
+    P = np.zeros((tiny.L, B.LSDF_MLP_PARAMS), np.float32)
+    P[:, -1] = k
+    C = len(sel)
+    ws = torch.full((B.query_workspace_size(C, tiny.L, tiny.M),), 0xFF, dtype=torch.uint8, device="cuda")
+    say(f"query_mlp constant network k={k} margin={margin} C={C} M={tiny.M}")
+    d, l, ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half), dev(pts), margin=margin,
+                                        link_dist=True, workspace=ws)
+    ld = ld.cpu().numpy().astype(np.float64)
+    want = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P.astype(np.float64), cen, half,
+                         margin)
+    # (c, i) whose result a pair in the domain's boundary band could change
+    sure, maybe = _domain_bands(T32, cen, half, pts)
+    inbox = np.isfinite(orc.query_f32_each(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts))
+    keeps_k = ~inbox if k < margin else np.ones_like(inbox)
+    amb = (sure & keeps_k).any(-1) != (maybe & keeps_k).any(-1)
+    ok = ~amb
+    say(f"  {ok.sum()} of {ok.size} link minima compared bit for bit ({amb.sum()} with a boundary pair deciding)")
+    assert amb.sum() <= 2
+    assert np.array_equal(ld[ok].astype(np.float32).view(np.uint32), want[ok].astype(np.float32).view(np.uint32))
+    assert np.array_equal(ld[ok], want[ok])
+    if k < margin < np.inf:
+        assert (inbox.any(-1) & (want < k)).any() and (want == np.float32(k)).any()   # both kinds of pair decide
+    dn, ln = d.cpu().numpy().astype(np.float64), l.cpu().numpy()
+    want_l = np.where(np.isfinite(ld.min(axis=1)), ld.argmin(axis=1), -1)
+    assert np.array_equal(dn, ld.min(axis=1)) and np.array_equal(ln, want_l)
+    if np.isinf(margin):
+        plain = B.query_min_distance(dev(T32), gs, dev(pts), link_dist=True)[2].cpu().numpy()
+        fin = np.isfinite(plain)
+        assert fin.sum() > 50
+        assert np.array_equal(ld[fin].astype(np.float32).view(np.uint32), plain[fin].view(np.uint32))
+
+
+def _shift_to_margin(orc, w, T32, pts, P, cen, half, margin, q=0.4, s=1.0):
+    """Scale each link's output weights w4 by s and shift its output bias so
+    that the margin sits at quantile q of the twin network's values over the
+    pairs in that link's domain.  Returns the FP32 parameters (what the GPU
+    is given; the oracle reads the same values) and the per-pair tolerance
+    function: a GPU-twin difference comes from bfloat16 rounding flips inside
+    the network, so it scales with the output's distance from its bias."""
+    P = P.copy()
+    P[:, -129:-1] *= np.float32(s)
+    _, em, _ = orc.query_mlp(T32, w.grid_lo, w.grid_hi, w.grid_n, [np.zeros(tuple(n[::-1]), np.float32)
+                                                                    for n in w.grid_n],
+                             pts, P.astype(np.float64), cen, half, -np.inf, each=True)
+    sure, _ = _domain_bands(T32, cen, half, pts)
+    for i in range(w.L):
+        P[i, -1] += np.float32(margin - np.quantile(em[:, i][sure[:, i]], q))
+    P = P.astype(np.float32)
+    b4 = P[:, -1].astype(np.float64)
+
+    def tol(em):
+        return TOL_EVAL * np.maximum(s, np.abs(em - b4.reshape((1, -1) + (1,) * (em.ndim - 2))))
+    return P, tol
+
+
+def _pair_intervals(em, eg, sure, maybe, margin, tol):
+    """Per pair, the interval [lo, hi] of values the learned query may give:
+    the oracle decides with the twin network's m, the GPU with its own m
+    (within tol of the twin's), so a decision is fixed only where m is more
+    than tol from the margin and the pair is clear of the domain's boundary
+    band.  A pair that takes the grid value gives the twin's grid bits."""
+    below = em < margin - tol
+    near = np.abs(em - margin) <= tol
+    inbox = np.isfinite(eg)
+    lo = np.where(below & inbox, eg, em - tol)
+    hi = np.where(below & inbox, eg, em + tol)
+    lo = np.where(near & inbox, np.minimum(eg, em - tol), lo)
+    hi = np.where(near & inbox, np.maximum(eg, em + tol), hi)
+    lo = np.where(maybe, lo, np.inf)
+    hi = np.where(sure, hi, np.inf)
+    return lo, hi
+
+
+def test_query_mlp_finite_margin_pairs_match_oracle(B, orc, tiny, tiny_grids):
+    """Margin 5 cm with a random network whose outputs are shifted to put the
+    margin inside their range, pair by pair: each GPU call takes one point,
+    so its per-link values are the values of single pairs.  Every pair whose
+    decision is fixed (network value more than TOL_EVAL from the margin,
+    clear of the domain boundary) must follow the oracle's rule: below the
+    margin and in the box, the twin's grid value bit for bit; below the
+    margin outside the box, the network value; above the margin, the network
+    value.  The network is not a distance field, so a wrong decision moves a
+    value far beyond the tolerance."""
+    sel = np.arange(0, tiny.C, 5)
+    T32 = _poses(orc, tiny, sel)
+    cen, half = domains_of(tiny)
+    g32 = [g.astype(np.float32) for g in tiny_grids]
+    # the 100 points in the most grid boxes over these poses, and 60 others
+    nbox = np.isfinite(orc.query_f32_each(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32,
+                                          tiny.points.astype(np.float32))).sum(axis=(0, 1))
+    order = np.argsort(-nbox, kind="stable")
+    pts = tiny.points[np.concatenate([order[:100], order[-60:]])].astype(np.float32)
+    gs = _grid_set(B, tiny, tiny_grids)
+    margin = 0.05
+    P, tolf = _shift_to_margin(orc, tiny, T32, pts, params_f32(7, 7), cen, half, margin)
+    _, em, eg = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P.astype(np.float64), cen, half,
+                              margin, each=True)
+    sure, maybe = _domain_bands(T32, cen, half, pts)
+    C, L, M = em.shape
+    Tg, Pg = dev(T32), dev(P)
+    ws = B.query_workspace(C, L, 1, "cuda")
+    say(f"query_mlp margin={margin}: {M} single-point calls, C={C}")
+    got = np.empty((C, L, M))
+    for j in range(M):
+        got[:, :, j] = B.query_min_distance_mlp(Tg, gs, Pg, (cen, half), dev(pts[j:j + 1]), margin=margin,
+                                                link_dist=True, workspace=ws)[2].cpu().numpy()
+    tol = tolf(em)
+    fixed = sure & (np.abs(em - margin) > tol)
+    inbox = np.isfinite(eg)
+    grid_pairs = fixed & (em < margin) & inbox
+    far_pairs = fixed & (em < margin) & ~inbox
+    net_pairs = fixed & (em >= margin)
+    say(f"  pairs: {grid_pairs.sum()} take the grid, {far_pairs.sum()} below the margin outside the box keep m, "
+        f"{net_pairs.sum()} above the margin; {(sure & ~fixed).sum()} within the tolerance of the margin")
+    assert grid_pairs.sum() > 100 and far_pairs.sum() > 100 and net_pairs.sum() > 100
+    assert np.array_equal(got[grid_pairs].astype(np.float32).view(np.uint32),
+                          eg[grid_pairs].astype(np.float32).view(np.uint32))
+    assert np.all(np.abs(got[far_pairs] - em[far_pairs]) <= tol[far_pairs])
+    assert np.all(np.abs(got[net_pairs] - em[net_pairs]) <= tol[net_pairs])
+    assert np.all(np.isinf(got[~maybe]))                     # outside the domain: no value
+    # the rule has teeth: the grid value is far from m for most grid pairs
+    assert (np.abs(eg[grid_pairs] - em[grid_pairs]) > tol[grid_pairs]).mean() > 0.9
+    lo, hi = _pair_intervals(em, eg, sure, maybe, margin, tol)
+    assert np.all((got >= lo) & (got <= hi))
+
+
+def _check_minima(ld, lo, hi, where):
+    """Per-link minima against the intervals of their pairs: the minimum of
+    the learned values lies between the minima of the lower and upper ends;
+    where the two coincide (a grid pair decides) it is that value exactly."""
+    mlo, mhi = lo.min(-1), hi.min(-1)
+    exact = mlo == mhi
+    assert np.all((ld >= mlo) & (ld <= mhi)), (where, np.argwhere(~((ld >= mlo) & (ld <= mhi)))[:5])
+    assert np.array_equal(ld[exact], mlo[exact])
+    return int(exact.sum())
+
+
+def test_query_mlp_finite_margin_minima_match_oracle(B, orc, tiny, tiny_grids):
+    """Margin 5 cm, every point of the tiny workload in one call, with a
+    random network whose output is scaled to vary a few centimetres around
+    the margin: some per-link minima are decided by a grid value (then they
+    are that value exactly), others by a network value, and every one must
+    lie within the oracle's per-pair intervals."""
+    sel = np.arange(0, tiny.C, 5)
+    T32 = _poses(orc, tiny, sel)
+    cen, half = domains_of(tiny)
+    pts = tiny.points.astype(np.float32)
+    g32 = [g.astype(np.float32) for g in tiny_grids]
+    gs = _grid_set(B, tiny, tiny_grids)
+    margin = 0.05
+    P, tolf = _shift_to_margin(orc, tiny, T32, pts[:300], params_f32(7, 8), cen, half, margin, q=0.5, s=0.05)
+    _, em, eg = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P.astype(np.float64), cen, half,
+                              margin, each=True)
+    sure, maybe = _domain_bands(T32, cen, half, pts)
+    say(f"query_mlp margin={margin} C={len(sel)} M={tiny.M}")
+    ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half), dev(pts), margin=margin,
+                                  link_dist=True)[2].cpu().numpy().astype(np.float64)
+    tol = tolf(em)
+    lo, hi = _pair_intervals(em, eg, sure, maybe, margin, tol)
+    n_exact = _check_minima(ld, lo, hi, "tiny")
+    n_net = int((np.isfinite(hi.min(-1)) & (lo.min(-1) < hi.min(-1))).sum())
+    say(f"  {n_exact} of {ld.size} minima decided by a grid pair (exact), {n_net} by network values")
+    assert n_exact > 0 and n_net > 0
+
+
+def test_query_mlp_finite_margin_learned_scale_sampled(B, orc):
+    """The learned workload at full size (500 waypoints x 100,000 points x 7
+    links) at margin 5 cm in the benchmark's launch configuration, with a
+    random network scaled to vary a few centimetres around the margin:
+    sampled per-link minima against the oracle's per-pair intervals over all
+    100,000 points of that link."""
+    w = synth.make_workload("learned")
+    cen, half = domains_of(w)
+    g32 = [g.astype(np.float32) for g in orc.workload_grids(w)]
+    gs = _grid_set(B, w, g32)                    # the oracle's grids on both sides
+    T32 = orc.fk(w.robot.dh, w.q, w.robot.base_T).astype(np.float32)
+    pts = w.points.astype(np.float32)
+    margin = 0.05
+    s = 0.05
+    P, _ = _shift_to_margin(orc, w, T32[::100], pts[::50], params_f32(7, 9), cen, half, margin, q=0.5, s=s)
+    say(f"query_mlp learned scale C={w.C} M={w.M} margin={margin}")
+    ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half), dev(pts), margin=margin,
+                                  link_dist=True)[2].cpu().numpy().astype(np.float64)
+    n_exact = 0
+    for c, i in [(0, 1), (123, 4), (250, 0), (377, 6), (499, 3)]:
+        Tci = T32[c:c + 1, i:i + 1]
+        _, em, eg = orc.query_mlp(Tci, w.grid_lo[i:i + 1], w.grid_hi[i:i + 1], w.grid_n[i:i + 1], [g32[i]], pts,
+                                  P[i:i + 1].astype(np.float64), cen[i:i + 1], half[i:i + 1], margin, each=True)
+        sure, maybe = _domain_bands(Tci, cen[i:i + 1], half[i:i + 1], pts)
+        tol = TOL_EVAL * np.maximum(s, np.abs(em - np.float64(P[i, -1])))
+        lo, hi = _pair_intervals(em, eg, sure, maybe, margin, tol)
+        below = (em < margin) & sure
+        say(f"  c={c} link={i}: {sure.sum()} in-domain pairs, {(below & np.isfinite(eg)).sum()} take the grid, "
+            f"{(below & ~np.isfinite(eg)).sum()} below the margin outside the box; gpu {ld[c, i]:.6g}, "
+            f"interval [{lo.min():.6g}, {hi.min():.6g}]")
+        n_exact += _check_minima(ld[c:c + 1, i:i + 1], lo, hi, (c, i))
+    assert n_exact >= 1
 
 
 def test_query_mlp_no_fallback_matches_twin(B, orc, tiny, tiny_grids):

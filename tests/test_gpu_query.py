@@ -7,7 +7,10 @@ query_min_distance) against the CPU oracle, through the C ABI.
 * fk_batch: within 5e-6 of the oracle's double-precision kinematics;
 * build_link_sdf: within 2e-6 m of the oracle's double-precision grid;
 * end to end (GPU kinematics, GPU grids, GPU query) against the all-double
-  oracle: within 1e-5 m, argmin equal outside near-ties.
+  oracle: every per-link minimum within 1e-5 m of the double one, except
+  where a pair proven to lie within the two sides' coordinate difference of
+  a box face decides it (then between the double minima with and without
+  such pairs); argmin equal outside near-ties.
 """
 import numpy as np
 import pytest
@@ -18,7 +21,6 @@ import synth
 pytestmark = pytest.mark.gpu
 
 TOL_E2E = 1e-5        # metres, FP32 end to end vs the double oracle
-TIE = 2e-5            # link minima closer than this count as a tie
 
 
 def say(*a):
@@ -325,13 +327,51 @@ def test_build_link_sdf_matches_oracle(B, orc, tiny, tiny_grids):
         assert err.max() < 2e-6, (i, err.max())
 
 
-def face_min(grid):
-    return min(grid[0].min(), grid[-1].min(), grid[:, 0].min(), grid[:, -1].min(), grid[:, :, 0].min(),
-               grid[:, :, -1].min())
+def _double_intervals(orc, w, grids64, T32, T64, chunk=25):
+    """Per (c, i), the interval the FP32 path's per-link minimum must lie in,
+    from the double oracle's per-pair dump.  A pair can be in link i's grid
+    box on one side and out of it on the other only when its double grid
+    coordinates lie within the two sides' coordinate difference of a box
+    face.  That difference is bounded per pair by the pose part (the FP32
+    poses the GPU computed against the double ones, the link-frame points
+    compared exactly in double) plus the rounding bound of the
+    single-precision map (r10_bound).  Pairs clear of every face by more
+    than that are surely in or surely out; the interval runs from the
+    minimum over pairs possibly in the box to the minimum over pairs surely
+    in it, each widened by TOL_E2E."""
+    import r10_bound as rb
+    lo64, hi64 = w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64)
+    invh = (w.grid_n - 1.0) / (hi64 - lo64)
+    P = w.points.astype(np.float64)
+    C = T64.shape[0]
+    lo = np.empty((C, w.L))
+    hi = np.empty((C, w.L))
+    for c0 in range(0, C, chunk):
+        cs = slice(c0, min(C, c0 + chunk))
+        u, v = orc.query_f64_each(T64[cs], lo64, hi64, w.grid_n, grids64, P)
+        T3 = T32[cs].astype(np.float64)
+        T6 = T64[cs]
+        l32 = P @ T3[..., :3] - T3[..., 3][:, :, None, :] @ T3[..., :3]      # R^T (x - t), [c][L][M][3]
+        l64 = P @ T6[..., :3] - T6[..., 3][:, :, None, :] @ T6[..., :3]
+        du = np.abs(l32 - l64) * invh[None, :, None, :] + rb.coord_bound(T3, lo64, hi64, w.grid_n, P)
+        slack = rb.face_slack(u, w.grid_n)
+        surely = (slack > du).all(-1)
+        maybe = (slack >= -du).all(-1)
+        lo[cs] = np.where(maybe, v, np.inf).min(-1) - TOL_E2E
+        hi[cs] = np.where(surely, v, np.inf).min(-1) + TOL_E2E
+    return lo, hi
 
 
 @pytest.mark.parametrize("name", ["tiny", "paper"])
 def test_end_to_end_vs_double_oracle(B, orc, name, tiny_grids, paper_grids):
+    """The whole path on the GPU (FP32 kinematics, GPU-built grids, FP32
+    query) against the all-double oracle.  Every per-link minimum, at any
+    distance, must lie in the interval the oracle's per-pair dump gives it
+    (_double_intervals): the only slack beyond TOL_E2E is for pairs proven
+    to lie within the two sides' coordinate difference of a box face, and
+    the test reports how many minima such pairs widened.  Per waypoint the
+    clearance lies between the links' interval ends and the argmin is a link
+    whose interval can hold the minimum (the only one, outside near-ties)."""
     w = synth.make_workload(name)
     grids64 = tiny_grids if name == "tiny" else paper_grids
     say("end-to-end", name, "C=%d M=%d" % (w.C, w.M))
@@ -340,27 +380,28 @@ def test_end_to_end_vs_double_oracle(B, orc, name, tiny_grids, paper_grids):
     d, l, ld = B.query_min_distance(T, gs, to_dev(w.points), link_dist=True)
     torch.cuda.synchronize()
     d, l, ld = d.cpu().numpy().astype(np.float64), l.cpu().numpy(), ld.cpu().numpy().astype(np.float64)
+    T32 = T.cpu().numpy()
     T64 = orc.fk(w.robot.dh, w.q, w.robot.base_T)
+    lo, hi = _double_intervals(orc, w, grids64, T32, T64)
     cl = orc.query_f64(T64, w.grid_lo, w.grid_hi, w.grid_n, grids64, w.points)
-    rd, rl = orc.reduce(cl)
-    # A point lying within rounding of a box face can be in the box in one
-    # precision and out of it in the other (out-of-box counts as +inf).  Such
-    # a point's value is at least the smallest value on that box's faces, so
-    # a disagreement is only allowed above that band.
-    band = np.array([face_min(g) for g in grids64]) - TOL_E2E
-    same = (ld == cl) | (np.abs(ld - cl) <= TOL_E2E)
-    boundary = np.minimum(ld, cl) >= band[None, :]
-    assert np.all(same | boundary), np.argwhere(~(same | boundary))[:5]
-    dsame = (d == rd) | (np.abs(d - rd) <= TOL_E2E)
-    assert np.all(dsame | (np.minimum(d, rd) >= band.min()))
-    fin = np.isfinite(rd) & dsame
-    say("end-to-end max |d - d_oracle| = %.3g m over %d waypoints, %d outside the band rule" %
-        (np.max(np.abs(d[fin] - rd[fin])) if fin.any() else 0.0, fin.sum(), (~dsame).sum()))
-    # argmin: exact unless the oracle's two best links are within TIE
-    srt = np.sort(cl, axis=1)
-    clear = (srt[:, 1] - srt[:, 0] > TIE) & dsame & np.isfinite(rd)
-    assert np.array_equal(l[clear], rl[clear])
-    amb = dsame & np.isfinite(rd) & ~clear
-    for c in np.flatnonzero(amb):
-        assert cl[c, l[c]] <= rd[c] + TIE
+    bad = ~((ld >= lo) & (ld <= hi))
+    assert not bad.any(), [(c, i, ld[c, i], lo[c, i], hi[c, i]) for c, i in np.argwhere(bad)[:5]]
+    fin = np.isfinite(cl) & np.isfinite(ld)
+    widened = np.isfinite(hi) & (hi - np.where(np.isfinite(lo), lo, hi) > 2 * TOL_E2E + 1e-12) | (np.isinf(hi) & np.isfinite(lo))
+    differ = (np.isfinite(cl) != np.isfinite(ld)) | (fin & (np.abs(np.where(fin, ld - cl, 0.0)) > TOL_E2E))
+    err = np.abs(ld[fin] - cl[fin])
+    say(f"end-to-end: {ld.size} link minima, {np.isfinite(ld).sum()} finite; max |gpu - double| = "
+        f"{err.max() if err.size else 0.0:.3g} m; {widened.sum()} intervals widened by near-face pairs, "
+        f"{differ.sum()} minima differ from the double one by more than {TOL_E2E} (all inside their intervals)")
+    assert differ.sum() <= widened.sum()
+    assert widened.sum() <= max(2, 0.01 * ld.size)
+    # per waypoint
+    assert np.array_equal(d, ld.min(axis=1))
+    assert np.all((d >= lo.min(axis=1)) & (d <= hi.min(axis=1)))
+    cand = lo <= hi.min(axis=1, keepdims=True)                   # links that can hold the minimum
+    fin_c = np.isfinite(d)
+    assert np.all(cand[fin_c, l[fin_c]])
+    single = fin_c & (cand.sum(axis=1) == 1)
+    assert np.array_equal(l[single], np.argmax(cand[single], axis=1))
+    say(f"  argmin: {single.sum()} waypoints with one possible link (equal), {(fin_c & ~single).sum()} near-ties")
     assert np.all((l == -1) == ~np.isfinite(d))

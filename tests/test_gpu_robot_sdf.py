@@ -10,6 +10,7 @@ through the C ABI: lsdf_robot_sdf_build and lsdf_robot_sdf_query.
 * at the paper's size (500 configurations, a 4 m environment of 3.125 cm
   voxels, 64^3 grids), sampled voxels and configurations match the twin.
 """
+import ctypes as ct
 import math
 
 import numpy as np
@@ -110,6 +111,61 @@ def test_robot_sdf_query_bit_exact_small(B, orc, tiny, tiny_grids):
     assert torch.isinf(B.robot_sdf_query(rs, env, far)).all()
     empty = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
     assert torch.isinf(B.robot_sdf_query(rs, env, empty)).all()
+
+
+def _occupied(orc, pts, lo, r, n):
+    flat = np.array([orc.voxel_index(p.astype(np.float64), lo, r, n) for p in pts])
+    return np.unique(flat[flat >= 0])
+
+
+def _voxel_list(B, env, ws):
+    """Count and sorted list of the distinct occupied voxels the runtime left
+    in its workspace (the layout lsdf.h documents)."""
+    V = int(env.n[0]) * int(env.n[1]) * int(env.n[2])
+    K = 256 * ((4 * ((V + 31) // 32) + 255) // 256)
+    raw = ws.cpu().numpy()
+    cnt = int(raw[K:K + 4].view(np.uint32)[0])
+    return cnt, np.sort(raw[K + 256:K + 256 + 4 * cnt].view(np.uint32).astype(np.int64))
+
+
+@pytest.mark.parametrize("cloud", ["clustered", "paper"])
+def test_robot_sdf_query_voxel_set_exact(B, orc, tiny, cloud):
+    """The runtime's set of distinct occupied voxels, checked whole: its
+    count and its list (read from the workspace) equal the oracle's voxels,
+    so no voxel is dropped, repeated or invented.  Independently of the
+    list, a synthetic Robot SDF gives each configuration one finite voxel
+    (value c for configuration c, +inf elsewhere): the query returns c
+    exactly when that voxel is occupied, for every occupied voxel and for
+    as many unoccupied ones."""
+    lo, r, n = LO_SMALL, R_SMALL, N_SMALL
+    env = B.make_env(lo, r, n)
+    V = int(np.prod(n))
+    rng = np.random.default_rng(92)
+    if cloud == "clustered":
+        T32 = orc.fk(tiny.robot.dh, tiny.q[[5]], tiny.robot.base_T).astype(np.float32)
+        origins = T32[0, :, :, 3].astype(np.float64)
+        pts = np.concatenate([origins[rng.integers(0, len(origins), 3000)] + rng.normal(0, 0.05, size=(3000, 3)),
+                              rng.uniform(-3, 3, size=(200, 3))]).astype(np.float32)
+    else:
+        pts = synth.make_workload("paper").points.astype(np.float32)
+    occ = _occupied(orc, pts, lo, r, n)
+    free = np.setdiff1d(np.arange(V), occ)
+    probe = np.concatenate([occ, rng.choice(free, size=min(len(free), len(occ)), replace=False)])
+    C = len(probe)
+    rs = torch.full((C, V), float("inf"), dtype=torch.float32, device="cuda")
+    rs[torch.arange(C, device="cuda"), torch.as_tensor(probe, device="cuda")] = torch.arange(
+        C, dtype=torch.float32, device="cuda")
+    need = ct.c_size_t(0)
+    assert B.load_library().lsdf_robot_sdf_query_workspace_size(ct.byref(env), len(pts), ct.byref(need)) == 0
+    ws = torch.full((int(need.value),), 0xAB, dtype=torch.uint8, device="cuda")
+    say(f"robot_sdf_query voxel set: {cloud} cloud M={len(pts)}, {len(occ)} occupied voxels, C={C}")
+    d = B.robot_sdf_query(rs.reshape(C, n[2], n[1], n[0]), env, to_dev(pts), workspace=ws).cpu().numpy()
+    cnt, lst = _voxel_list(B, env, ws)
+    assert cnt == len(occ)
+    assert np.array_equal(lst, occ)
+    want = np.where(np.arange(C) < len(occ), np.arange(C, dtype=np.float32), np.float32(np.inf))
+    assert np.array_equal(d.view(np.uint32), want.view(np.uint32))
+    del rs
 
 
 def test_robot_sdf_paper_scale_sampled(B, orc):
