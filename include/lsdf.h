@@ -140,7 +140,9 @@ int lsdf_fk_batch(const lsdf_dh* dh, int32_t dof, const float* base_T,
  * configuration the world-to-grid map is formed once as one affine matrix,
  * the form of Eq. 4; the lerp is fma(f, b, fma(-f, a, a))), so results are
  * reproducible bit for bit. */
-int lsdf_query_workspace_size(int32_t C, int32_t L, int64_t M, size_t* bytes);
+/* Workspace bytes of a query of C configurations, L links and M points
+ * with the given flags (the same flags the query will get; must be 0). */
+int lsdf_query_workspace_size(int32_t C, int32_t L, int64_t M, uint32_t flags, size_t* bytes);
 
 int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L,
                             const lsdf_grid* grids, const void* grid_buf,

@@ -692,7 +692,7 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
     if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
         return fail(LSDF_E_INVALID_ARG, "query_mlp: workspace is not 256-byte aligned");
     size_t need = 0;
-    int rc = lsdf_query_workspace_size(C, L, M, &need);
+    int rc = lsdf_query_workspace_size(C, L, M, flags, &need);
     if (rc != LSDF_OK) return rc;
     if (ws_bytes < need) return fail(LSDF_E_SHAPE, "query_mlp: workspace has %zu bytes, needs %zu", ws_bytes, need);
     QueryMlpArgs a{};

@@ -904,7 +904,9 @@ int run_query(const char* who, int32_t K, const int32_t* c_off, const int64_t* m
 
 }  // namespace
 
-LSDF_API int lsdf_query_workspace_size(int32_t C, int32_t L, int64_t M, size_t* bytes) {
+LSDF_API int lsdf_query_workspace_size(int32_t C, int32_t L, int64_t M, uint32_t flags, size_t* bytes) {
+    lsdf::clear_error();
+    if (flags != 0) return lsdf::fail(LSDF_E_UNSUPPORTED, "query_workspace_size: unsupported flags 0x%x", flags);
     return lsdf_query_batched_workspace_size(1, C, L, M, bytes);
 }
 

@@ -97,7 +97,7 @@ def load_library():
     lib.lsdf_fk_batch.restype = ct.c_int
     lib.lsdf_fk_batch.argtypes = [ct.POINTER(lsdf_dh), i32, ct.POINTER(ct.c_float), vp, i32, vp, vp]
     lib.lsdf_query_workspace_size.restype = ct.c_int
-    lib.lsdf_query_workspace_size.argtypes = [i32, i32, i64, ct.POINTER(sz)]
+    lib.lsdf_query_workspace_size.argtypes = [i32, i32, i64, ct.c_uint32, ct.POINTER(sz)]
     lib.lsdf_query_min_distance.restype = ct.c_int
     lib.lsdf_query_min_distance.argtypes = [vp, i32, i32, ct.POINTER(lsdf_grid), vp, vp, i64, vp, vp, vp,
                                             u32, vp, sz, vp]
@@ -278,7 +278,7 @@ def set_kernel_events(before=None, after=None):
 
 def query_workspace_size(C: int, L: int, M: int) -> int:
     n = ct.c_size_t(0)
-    _check(load_library().lsdf_query_workspace_size(C, L, M, ct.byref(n)))
+    _check(load_library().lsdf_query_workspace_size(C, L, M, 0, ct.byref(n)))
     return int(n.value)
 
 

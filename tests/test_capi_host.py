@@ -92,10 +92,11 @@ def test_query_argument_errors(lib):
 
 def test_workspace_size(lib):
     n = ct.c_size_t(0)
-    assert lib.lsdf_query_workspace_size(500, 7, 20000, ct.byref(n)) == 0
+    assert lib.lsdf_query_workspace_size(500, 7, 20000, 0, ct.byref(n)) == 0
     assert n.value >= 500 * 7 * 4 and n.value % 256 == 0
-    assert lib.lsdf_query_workspace_size(500, 0, 20000, ct.byref(n)) != 0
-    assert lib.lsdf_query_workspace_size(500, 7, 20000, None) != 0
+    assert lib.lsdf_query_workspace_size(500, 0, 20000, 0, ct.byref(n)) != 0
+    assert lib.lsdf_query_workspace_size(500, 7, 20000, 0, None) != 0
+    assert lib.lsdf_query_workspace_size(500, 7, 20000, 1, ct.byref(n)) == -3      # LSDF_E_UNSUPPORTED
 
 
 def test_fk_argument_errors(lib):
@@ -191,7 +192,7 @@ def test_batched_query_argument_errors(lib):
 
 def test_batched_workspace_size(lib):
     n1, nk = ct.c_size_t(0), ct.c_size_t(0)
-    assert lib.lsdf_query_workspace_size(500, 7, 20000, ct.byref(n1)) == 0
+    assert lib.lsdf_query_workspace_size(500, 7, 20000, 0, ct.byref(n1)) == 0
     assert lib.lsdf_query_batched_workspace_size(1, 500, 7, 20000, ct.byref(nk)) == 0
     assert n1.value == nk.value
     assert lib.lsdf_query_batched_workspace_size(64, 500, 7, 20000, ct.byref(nk)) == 0
