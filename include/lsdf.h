@@ -150,6 +150,27 @@ int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L,
                             float* out_dist, int32_t* out_link, float* out_link_dist,
                             uint32_t flags, void* workspace, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, hosts that forbid allocation): lsdf_query_min_distance
+ * with no workspace argument.  Its workspace is device memory the library
+ * holds, LSDF_QUERY_NOALLOC_SCRATCH bytes on each GPU it runs on, from the
+ * first call on that GPU until the process ends.  The call allocates
+ * nothing.  Same arguments, kernels and results, bit for bit, as
+ * lsdf_query_min_distance.  A problem whose workspace
+ * (lsdf_query_workspace_size) exceeds that size is rejected with
+ * LSDF_E_SHAPE before anything is enqueued; 8 MiB holds, for example, 500
+ * configurations of 7 links with up to 3 million points.  Every call on one
+ * GPU uses that GPU's one copy, so calls that overlap in time on one GPU
+ * (different streams, or different host threads) race and give wrong
+ * results; calls in one stream are ordered and safe.  The stream must belong
+ * to the current device. */
+#define LSDF_QUERY_NOALLOC_SCRATCH (((size_t)8) << 20)
+int lsdf_query_min_distance_noalloc(const float* link_T, int32_t C, int32_t L,
+                                    const lsdf_grid* grids, const void* grid_buf,
+                                    const float* points, int64_t M,
+                                    float* out_dist, int32_t* out_link, float* out_link_dist,
+                                    uint32_t flags, void* stream);
+
 /* ---- batched clearance query ----------------------------------------------
  * The same quantity for K trajectories in one call.  The paper re-plans a
  * path of a few hundred configurations against each new cloud, over and

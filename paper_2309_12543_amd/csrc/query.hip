@@ -45,6 +45,7 @@
 //     with no device fence).
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 
 #include "fk_chain.hpp"
 #include "grid_sample.hpp"
@@ -929,6 +930,64 @@ LSDF_API int lsdf_query_min_distance(const float* link_T, int32_t C, int32_t L, 
     lsdf::clear_error();
     return run_query("query", 1, nullptr, nullptr, link_T, C, L, grids, grid_buf, points, M, out_dist, out_link,
                      out_link_dist, nullptr, flags, workspace, ws_bytes, stream);
+}
+
+namespace {
+
+// Workspace of lsdf_query_min_distance_noalloc: one copy per GPU, loaded with
+// the code object.  Host code never names the array itself (on the host it
+// is only a stand-in for the symbol); it takes the device address that
+// hipGetSymbolAddress gives for the current device, once per device.
+constexpr size_t kNoAllocScratch = LSDF_QUERY_NOALLOC_SCRATCH;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(void** out) {
+    using namespace lsdf;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(LSDF_E_DEVICE, "query_noalloc: no current device");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(LSDF_E_DEVICE, "query_noalloc: device %d beyond the %d the library tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LSDF_E_DEVICE, "query_noalloc: hipGetSymbolAddress of the scratch array failed (%s)",
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LSDF_OK;
+}
+
+}  // namespace
+
+LSDF_API int lsdf_query_min_distance_noalloc(const float* link_T, int32_t C, int32_t L, const lsdf_grid* grids,
+                                             const void* grid_buf, const float* points, int64_t M, float* out_dist,
+                                             int32_t* out_link, float* out_link_dist, uint32_t flags, void* stream) {
+    using namespace lsdf;
+    clear_error();
+    if (flags != 0) return fail(LSDF_E_UNSUPPORTED, "query_noalloc: unsupported flags 0x%x", flags);
+    if (C < 0 || M < 0 || M > LSDF_MAX_POINTS)
+        return fail(LSDF_E_SHAPE, "query_noalloc: size out of range (C = %d, M = %lld)", (int)C, (long long)M);
+    if (L < 1 || L > LSDF_MAX_LINKS)
+        return fail(LSDF_E_SHAPE, "query_noalloc: L = %d out of [1, %d]", (int)L, LSDF_MAX_LINKS);
+    if (C == 0) return LSDF_OK;
+    const size_t need = workspace_bytes(1, C, L, M);
+    if (need > kNoAllocScratch)
+        return fail(LSDF_E_SHAPE,
+                    "query_noalloc: C = %d, L = %d, M = %lld needs %zu bytes of workspace; the library holds %zu "
+                    "(use lsdf_query_min_distance with a workspace of your own)",
+                    (int)C, (int)L, (long long)M, need, kNoAllocScratch);
+    void* ws = nullptr;
+    const int rc = noalloc_scratch(&ws);
+    if (rc != LSDF_OK) return rc;
+    return run_query("query_noalloc", 1, nullptr, nullptr, link_T, C, L, grids, grid_buf, points, M, out_dist,
+                     out_link, out_link_dist, nullptr, 0, ws, kNoAllocScratch, stream);
 }
 
 LSDF_API int lsdf_query_min_distance_batched(int32_t K, const int32_t* traj_c_offset, const int64_t* traj_m_offset,

@@ -21,6 +21,7 @@ LSDF_E_UNSUPPORTED = -3
 LSDF_E_DEVICE = -4
 LSDF_F32, LSDF_BF16, LSDF_F16 = 0, 1, 2
 LSDF_MAX_LINKS = 16
+LSDF_QUERY_NOALLOC_SCRATCH = 8 << 20
 LSDF_MAX_DOF = 15
 LSDF_MAX_COMPONENTS = 16
 LSDF_MLP_HIDDEN = 128
@@ -101,6 +102,9 @@ def load_library():
     lib.lsdf_query_min_distance.restype = ct.c_int
     lib.lsdf_query_min_distance.argtypes = [vp, i32, i32, ct.POINTER(lsdf_grid), vp, vp, i64, vp, vp, vp,
                                             u32, vp, sz, vp]
+    lib.lsdf_query_min_distance_noalloc.restype = ct.c_int
+    lib.lsdf_query_min_distance_noalloc.argtypes = [vp, i32, i32, ct.POINTER(lsdf_grid), vp, vp, i64, vp, vp, vp,
+                                                    u32, vp]
     lib.lsdf_set_kernel_events.restype = ct.c_int
     lib.lsdf_set_kernel_events.argtypes = [vp, vp]
     tun = ct.POINTER(lsdf_query_tuning)
@@ -359,6 +363,21 @@ def query_min_distance(link_T: torch.Tensor, grids: GridSet, points: torch.Tenso
         points.data_ptr() if M > 0 else None, M, dist.data_ptr(), link.data_ptr(),
         ld.data_ptr() if ld is not None else None, 0, workspace.data_ptr(), workspace.numel(),
         _stream_handle(stream, dev)))
+    return (dist, link, ld) if link_dist else (dist, link)
+
+
+def query_min_distance_noalloc(link_T: torch.Tensor, grids: GridSet, points: torch.Tensor, *,
+                               link_dist: bool = False, out=None, stream=None):
+    """query_min_distance with the library's own device workspace
+    (lsdf_query_min_distance_noalloc): the call allocates nothing when
+    ``out`` is given.  Calls that overlap in time on one GPU race."""
+    lib = load_library()
+    C, L, M, dev = _query_shapes(link_T, grids, points)
+    dist, link, ld = _query_outputs(out, C, L, dev, link_dist)
+    _check(lib.lsdf_query_min_distance_noalloc(
+        link_T.data_ptr(), C, L, grids.desc, grids.buf.data_ptr(),
+        points.data_ptr() if M > 0 else None, M, dist.data_ptr(), link.data_ptr(),
+        ld.data_ptr() if ld is not None else None, 0, _stream_handle(stream, dev)))
     return (dist, link, ld) if link_dist else (dist, link)
 
 

@@ -90,6 +90,29 @@ def test_query_argument_errors(lib):
     assert call_query(lib, C=0) == B.LSDF_OK
 
 
+def test_noalloc_query_rejects_before_touching_the_device(lib):
+    """The entry point without a workspace checks its arguments and the size
+    of the problem against the scratch the library holds before any device
+    call, so these run without a GPU."""
+    from paper_2309_12543_amd import lsdf as B
+
+    def call(C=500, L=7, M=20000, flags=0):
+        return lib.lsdf_query_min_distance_noalloc(FAKE, C, L, grid_array(L), FAKE, FAKE, M, FAKE, FAKE, None,
+                                                   flags, None)
+    assert call(flags=1) == B.LSDF_E_UNSUPPORTED
+    assert call(L=0) == B.LSDF_E_SHAPE
+    assert call(C=-1) == B.LSDF_E_SHAPE
+    assert call(C=0) == B.LSDF_OK
+    n = ct.c_size_t(0)
+    M_big = 4_000_000
+    assert lib.lsdf_query_workspace_size(500, 7, M_big, 0, ct.byref(n)) == 0
+    assert n.value > B.LSDF_QUERY_NOALLOC_SCRATCH
+    assert call(M=M_big) == B.LSDF_E_SHAPE
+    assert b"needs" in lib.lsdf_last_error()
+    assert lib.lsdf_query_workspace_size(500, 7, 3_000_000, 0, ct.byref(n)) == 0
+    assert n.value <= B.LSDF_QUERY_NOALLOC_SCRATCH        # the example the header gives fits
+
+
 def test_workspace_size(lib):
     n = ct.c_size_t(0)
     assert lib.lsdf_query_workspace_size(500, 7, 20000, 0, ct.byref(n)) == 0
