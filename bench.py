@@ -95,6 +95,19 @@ def oracle_grids(w):
     return _ORACLE_GRIDS[key]
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (the `model name` line of /proc/cpuinfo,
+    which is what lscpu prints)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
     """The CPU oracle (double-precision kinematics + query) on the same
     workload, repeated for about budget_s seconds on all the host's threads,
@@ -120,7 +133,8 @@ def cpu_baseline(w, budget_s: float = 12.0):
     one = float(np.median([batch() for _ in range(3)]))
     oracle.set_threads(threads)
     return {"value": round(w.C * w.M * w.L / sec / 1e9, 4), "unit": "G point-link queries/s",
-            "ms_per_batch": round(sec * 1e3, 3), "cores": threads, "kind": "oracle",
+            "ms_per_batch": round(sec * 1e3, 3), "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(),
             "sample": f"full {w.name} batch (C={w.C}, M={w.M}, L={w.L}) repeated {reps}x; "
                       "double-precision kinematics + query, OpenMP over waypoints",
             "single_thread": {"ms_per_batch": round(one * 1e3, 3),
@@ -140,6 +154,88 @@ def time_calls(fn, steps, warmup):
         b.record()
     torch.cuda.synchronize()
     return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+def dense_cloud(w, M: int, seed: int = 71) -> np.ndarray:
+    """M points packed inside the links' boxes along the path: each is a
+    uniform point of link i's grid box placed with link i's pose at a random
+    waypoint, so nearly every 8-point block reaches some waypoint's box (the
+    case of an obstacle right against the arm)."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    T = oracle.fk(w.robot.dh, w.q, w.robot.base_T)
+    c = rng.integers(0, w.C, M)
+    i = rng.integers(0, w.L, M)
+    lo, hi = w.grid_lo.astype(np.float64)[i], w.grid_hi.astype(np.float64)[i]
+    loc = rng.uniform(lo, hi)
+    R, t = T[c, i, :, :3], T[c, i, :, 3]
+    return (np.einsum("mab,mb->ma", R, loc) + t).astype(np.float32).astype(np.float64)
+
+
+def scene_line(dev, w, label: str, steps: int, warmup: int):
+    """A non-headline workload timed like the headline one: the prepared
+    fused step (wall time over K steps), its device time, the query kernel
+    alone (events), and the kernel's roofline fraction from the culled
+    method's algorithmic work."""
+    import torch
+
+    from paper_2309_12543_amd import lsdf
+
+    gs = lsdf.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device=dev)
+    q = torch.as_tensor(w.q, dtype=torch.float32, device=dev)
+    pts = torch.as_tensor(w.points, dtype=torch.float32, device=dev)
+    T = torch.empty((w.C, w.L, 3, 4), dtype=torch.float32, device=dev)
+    call = lsdf.PreparedQueryFromJoints(w.robot.dh, q, gs, pts, base_T=w.robot.base_T, link_T=T)
+    ms = time_calls(call, steps, warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(int(2.4e9 * 0.02))
+    e0.record()
+    for _ in range(steps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    gpu_ms = e0.elapsed_time(e1) / steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        b.record()
+    for a, b in ev:
+        lsdf.set_kernel_events(a, b)
+        call()
+    torch.cuda.synchronize()
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    tests, surv, inbox = culled_work(T.cpu().numpy(), w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64),
+                                     w.points)
+    flop = FLOP_PER_TEST * (tests + surv) + FLOP_PER_INBOX_PAIR * inbox
+    achieved = flop / (kernel_ms / 1e3) / 1e12
+    pairs = w.C * w.M * w.L
+    return {"workload": label, "ms_per_step": round(ms, 5), "gpu_ms_per_step": round(gpu_ms, 5),
+            "value": round(pairs / (ms / 1e3) / 1e9, 2), "unit": "G point-link queries/s",
+            "query_kernel_ms": round(kernel_ms, 5), "inbox_pair_fraction": round(inbox / pairs, 5),
+            "sphere_survivor_pair_fraction": round(surv / pairs, 5),
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
+                         "algorithmic_flop": flop,
+                         "inbox_pair_corner_tb_per_s": round(BYTES_PER_INBOX_PAIR * inbox / (kernel_ms / 1e3) / 1e12,
+                                                             4)}}
+
+
+def extra_scenes(dev, steps: int, warmup: int):
+    """The tiny workload (50 waypoints x 2,000 points uniform in a 2 m cube,
+    32^3 grids) and a dense cloud at the paper size (500 x 20,000, every
+    point packed inside some link's box along the path)."""
+    import synth
+    out = {}
+    t = synth.make_workload("tiny")
+    log("extra scene: tiny")
+    out["tiny"] = scene_line(dev, t, f"tiny: {t.C} waypoints x {t.M} points uniform in a 2 m cube x {t.L} links, "
+                                     f"32^3 FP32 grids", steps, warmup)
+    w = synth.make_workload("paper")
+    w.points = dense_cloud(w, w.M)
+    log("extra scene: dense cloud")
+    out["dense"] = scene_line(dev, w, f"dense: {w.C} waypoints x {w.M} points packed in the links' boxes along "
+                                      f"the path x {w.L} links, 64^3 FP32 grids", steps, warmup)
+    return out
 
 
 def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 8):
@@ -537,12 +633,13 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--no-precision", action="store_true", help="skip the 128^3 bf16/fp16 storage variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-trajectory batched variant")
+    ap.add_argument("--no-extra-scenes", action="store_true", help="skip the tiny and dense-cloud lines")
     ap.add_argument("--no-robot-sdf", action="store_true", help="skip the paper's Robot-SDF pipeline comparator")
     ap.add_argument("--frnn-steps", type=int, default=10000,
                     help="training steps of the grid-transformation network (0 skips that variant)")
     ap.add_argument("--frnn-rotations", type=int, default=100000,
                     help="random rotations of its max-error test (the paper uses 10^7)")
-    ap.add_argument("--only", choices=["learned", "precision", "batched", "robot-sdf", "frnn"], default=None,
+    ap.add_argument("--only", choices=["learned", "scenes", "precision", "batched", "robot-sdf", "frnn"], default=None,
                     help="run only this variant (for profiling) and print its record as one JSON line")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB mebibytes (reference for HBM byte counters)")
@@ -571,6 +668,7 @@ def main():
     lsdf.load_library()
     if args.only:
         only = {"learned": lambda: learned_variant(dev, args.learned_epochs, args.learned_steps),
+                "scenes": lambda: extra_scenes(dev, 50, 5),
                 "precision": lambda: precision_variant(dev, 50),
                 "batched": lambda: batched_variant(dev, 20, 3),
                 "robot-sdf": lambda: robot_sdf_variant(dev, 50),
@@ -611,10 +709,20 @@ def main():
         if instrument and k is not None:
             call_ev[k][1].record()
 
+    # lsdf_query_from_joints: the kinematics inside the query's first kernel,
+    # its arguments marshalled once (a control loop refills q and the points
+    # in place), so that a step costs the host one ctypes call
+    fused_call = lsdf.PreparedQueryFromJoints(w.robot.dh, q, gs, pts, base_T=w.robot.base_T, link_T=T,
+                                              workspace=ws, out=(dist, link, None))
+
     def step_fused(k=None, instrument=False):
-        # lsdf_query_from_joints: the kinematics inside the query's first kernel
         if instrument and k is not None:
             lsdf.set_kernel_events(*kern_ev[args.steps + k])
+        fused_call()
+
+    def step_wrapper(k=None):
+        # the same call through the convenience wrapper, which checks and
+        # marshals every argument on every call
         lsdf.query_from_joints(w.robot.dh, q, gs, pts, base_T=w.robot.base_T, link_T=T, workspace=ws,
                                out=(dist, link, None))
 
@@ -628,11 +736,29 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / args.steps
 
+    def gpu_only(step):
+        # device time per step: the steps are queued behind a 20 ms sleep
+        # kernel, so the GPU runs them back to back whatever the host's pace
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(int(2.4e9 * 0.02))
+        e0.record()
+        for _ in range(args.steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
     log(f"timing {args.steps} steps (separate calls, then the fused call)")
     sep_ms = run(step_separate)
     d_sep, l_sep = dist.clone(), link.clone()
     ms_per_step = run(step_fused)
     fused_same = bool(torch.equal(dist.view(torch.int32), d_sep.view(torch.int32)) and torch.equal(link, l_sep))
+    wrapper_ms = run(step_wrapper)
+    gpu_fused_ms = gpu_only(step_fused)
+    gpu_sep_ms = gpu_only(step_separate)
     log("instrumented passes (events around the query call and kernel)")
     sep_ev_ms = run(lambda k=None: step_separate(k, instrument=True))
     fused_ev_ms = run(lambda k=None: step_fused(k, instrument=True))
@@ -691,8 +817,12 @@ def main():
                                f"{int(w.grid_n[0, 0])}^3 FP32 link grids",
                    "waypoints": w.C, "points": w.M, "links": w.L, "grid_nodes": int(w.grid_n[0, 0]),
                    "parallelism": "single GPU"},
-        "step": "lsdf_query_from_joints: kinematics in the query's first kernel, then the query and finalize kernels",
+        "step": "lsdf_query_from_joints (arguments marshalled once): kinematics in the query's first kernel, "
+                "then the query and finalize kernels",
         "separate_calls_ms_per_step": round(sep_ms, 5),
+        "wrapper_call_ms_per_step": round(wrapper_ms, 5),
+        "gpu_ms_per_step": {"fused": round(gpu_fused_ms, 5), "separate_calls": round(gpu_sep_ms, 5),
+                            "how": "steps queued behind a sleep kernel: device time with no host wait"},
         "instrumented_ms_per_step": {"separate_calls": round(sep_ev_ms, 5), "fused": round(fused_ev_ms, 5)},
         "separate_calls_equal_fused": fused_same,
         "query_call_ms": round(call_ms, 5),
@@ -722,6 +852,8 @@ def main():
     rec["roofline"]["gather"] = {
         "inbox_pair_corner_tb_per_s": round(BYTES_PER_INBOX_PAIR * inbox / (kernel_ms / 1e3) / 1e12, 4),
         "roof_corner_tb_per_s_7mb": roof["grids_7mb"]["corner_tb_per_s"]}
+    if not args.no_extra_scenes:
+        rec["extra_scenes"] = extra_scenes(dev, 50, 5)
     if args.learned_epochs > 0:
         rec["learned"] = learned_variant(dev, args.learned_epochs, args.learned_steps)
     if not args.no_precision:

@@ -76,6 +76,10 @@ constexpr float kFar = 1e30f;       // centred coordinate of unused lanes: never
 constexpr int kBlockPts = 8;        // points per culling sphere
 constexpr int kSphereBatch = 4;     // culling spheres tested together: the blocks of a quad
 constexpr int kQuadPts = kBlockPts * kSphereBatch;   // points per quad
+#ifndef LSDF_QUERY_QUAD_BATCH
+#define LSDF_QUERY_QUAD_BATCH 8     // quad spheres of a chunk loaded and tested together
+#endif
+constexpr int kQuadBatch = LSDF_QUERY_QUAD_BATCH;
 constexpr int kUnroll = LSDF_QUERY_UNROLL;
 constexpr int kGather = LSDF_QUERY_GATHER;
 static_assert(kUnroll % kGather == 0, "gather batch must divide the unroll");
@@ -274,6 +278,25 @@ __device__ __forceinline__ void load_map(const QueryArgs& p, int i, int c, bool 
     }
 }
 
+// A deferred block as a wave holds it: the record's fields in scalar
+// registers, and this lane's bit of the mask.
+struct DeferredView {
+    int64_t blk, m_lo, m_hi;
+    int c0, link;
+    bool mine;
+};
+__device__ __forceinline__ DeferredView read_deferred(const Deferred& d, int lane) {
+    DeferredView v;
+    const uint64_t mask = (uint64_t)uniform64((int64_t)d.mask);
+    v.blk = uniform64(d.blk);
+    v.m_lo = uniform64(d.m_lo);
+    v.m_hi = uniform64(d.m_hi);
+    v.c0 = __builtin_amdgcn_readfirstlane(d.c0);
+    v.link = __builtin_amdgcn_readfirstlane(d.link);
+    v.mine = (mask >> lane) & 1u;
+    return v;
+}
+
 // The first pass of a wave: the chunks q_first, q_first + q_step, ... below
 // q_end.  A chunk's quads are tested against every lane's box, then their
 // blocks; a block some lane's box may reach is appended to the workgroup's
@@ -361,52 +384,63 @@ __device__ __forceinline__ void test_chunks(const QueryArgs& p, const float* __r
         const int nxy = lg.n[0] * lg.n[1];
 
         float best = INFINITY;
-        for (int64_t qi = mc; qi < nquad; qi += cpg) {
-            // the quad's sphere first, its blocks' spheres only when some
-            // lane's box may reach the quad (all five loaded together); a
-            // sphere bounds all points of its quad or block, so also the
-            // trajectory's share of one it shares with its neighbour
-            const int64_t qg = quad0 + qi;
-            const float4 qs = qspheres[qg];
-            float4 sph[kSphereBatch];
+        // kQuadBatch quads of the chunk at a time: their spheres are loaded
+        // together and tested (one round trip for the batch); only the
+        // quads some lane's box may reach go on to their blocks' spheres
+        for (int64_t qb = mc; qb < nquad; qb += (int64_t)kQuadBatch * cpg) {
+            float4 qs[kQuadBatch];
 #pragma unroll
-            for (int u = 0; u < kSphereBatch; ++u) sph[u] = spheres[kSphereBatch * qg + u];
-            {
-                const float s0 = fmaf(m00, qs.x, fmaf(m01, qs.y, fmaf(m02, qs.z, w0)));
-                const float s1 = fmaf(m10, qs.x, fmaf(m11, qs.y, fmaf(m12, qs.z, w1)));
-                const float s2 = fmaf(m20, qs.x, fmaf(m21, qs.y, fmaf(m22, qs.z, w2)));
-                const bool near = (fabsf(s0) <= fmaf(nr0, qs.w, k0)) & (fabsf(s1) <= fmaf(nr1, qs.w, k1)) &
-                                  (fabsf(s2) <= fmaf(nr2, qs.w, k2));
-                if (!__ballot(near)) continue;
-            }
-            const int64_t jb = kQuadPts * qg;
-            uint32_t near_mask = 0;
-            uint64_t lanes[kSphereBatch];
+            for (int k = 0; k < kQuadBatch; ++k)   // past the trajectory's quads: its last one, not tested
+                qs[k] = qspheres[quad0 + min(qb + (int64_t)k * cpg, nquad - 1)];
+            uint32_t qnear = 0;
 #pragma unroll
-            for (int u = 0; u < kSphereBatch; ++u) {
-                const float s0 = fmaf(m00, sph[u].x, fmaf(m01, sph[u].y, fmaf(m02, sph[u].z, w0)));
-                const float s1 = fmaf(m10, sph[u].x, fmaf(m11, sph[u].y, fmaf(m12, sph[u].z, w1)));
-                const float s2 = fmaf(m20, sph[u].x, fmaf(m21, sph[u].y, fmaf(m22, sph[u].z, w2)));
-                const bool near = (fabsf(s0) <= fmaf(nr0, sph[u].w, k0)) & (fabsf(s1) <= fmaf(nr1, sph[u].w, k1)) &
-                                  (fabsf(s2) <= fmaf(nr2, sph[u].w, k2));
-                const int64_t blk = kSphereBatch * qg + u;
-                lanes[u] = __ballot(near);
-                if (lanes[u] && blk >= blk0 && blk < blk1) near_mask |= 1u << u;
+            for (int k = 0; k < kQuadBatch; ++k) {
+                const float s0 = fmaf(m00, qs[k].x, fmaf(m01, qs[k].y, fmaf(m02, qs[k].z, w0)));
+                const float s1 = fmaf(m10, qs[k].x, fmaf(m11, qs[k].y, fmaf(m12, qs[k].z, w1)));
+                const float s2 = fmaf(m20, qs[k].x, fmaf(m21, qs[k].y, fmaf(m22, qs[k].z, w2)));
+                const bool near = (fabsf(s0) <= fmaf(nr0, qs[k].w, k0)) & (fabsf(s1) <= fmaf(nr1, qs[k].w, k1)) &
+                                  (fabsf(s2) <= fmaf(nr2, qs[k].w, k2));
+                if (__ballot(near) && qb + (int64_t)k * cpg < nquad) qnear |= 1u << k;
             }
-            // the blocks some lane's box may reach: handed to the workgroup
-            // while it has room, else tested here
-            int slot = kDeferCap;
-            if (near_mask && lane == 0 && *ndef < kDeferCap) slot = atomicAdd(ndef, __builtin_popcount(near_mask));
-            slot = __builtin_amdgcn_readfirstlane(slot);
-            while (near_mask) {   // wave-uniform
-                const int u = __builtin_ctz(near_mask);
-                near_mask &= near_mask - 1;
-                if (slot < kDeferCap) {
-                    if (lane == 0) s_def[slot] = Deferred{lanes[u], kSphereBatch * qg + u, m_lo, m_hi, c_lo + cb * 64, i};
-                    ++slot;
-                } else {
-                    block_min<CUBIC, DT>(points, jb + u * kBlockPts, m_lo, m_hi, lg, G, nx, nxy, m00, m01, m02, w0,
-                                         m10, m11, m12, w1, m20, m21, m22, w2, best);
+            while (qnear) {   // wave-uniform
+                const int kq = __builtin_ctz(qnear);
+                qnear &= qnear - 1;
+                // a sphere bounds all points of its quad or block, so also the
+                // trajectory's share of one it shares with its neighbour
+                const int64_t qg = quad0 + qb + (int64_t)kq * cpg;
+                float4 sph[kSphereBatch];
+#pragma unroll
+                for (int u = 0; u < kSphereBatch; ++u) sph[u] = spheres[kSphereBatch * qg + u];
+                const int64_t jb = kQuadPts * qg;
+                uint32_t near_mask = 0;
+                uint64_t lanes[kSphereBatch];
+#pragma unroll
+                for (int u = 0; u < kSphereBatch; ++u) {
+                    const float s0 = fmaf(m00, sph[u].x, fmaf(m01, sph[u].y, fmaf(m02, sph[u].z, w0)));
+                    const float s1 = fmaf(m10, sph[u].x, fmaf(m11, sph[u].y, fmaf(m12, sph[u].z, w1)));
+                    const float s2 = fmaf(m20, sph[u].x, fmaf(m21, sph[u].y, fmaf(m22, sph[u].z, w2)));
+                    const bool near = (fabsf(s0) <= fmaf(nr0, sph[u].w, k0)) &
+                                      (fabsf(s1) <= fmaf(nr1, sph[u].w, k1)) & (fabsf(s2) <= fmaf(nr2, sph[u].w, k2));
+                    const int64_t blk = kSphereBatch * qg + u;
+                    lanes[u] = __ballot(near);
+                    if (lanes[u] && blk >= blk0 && blk < blk1) near_mask |= 1u << u;
+                }
+                // the blocks some lane's box may reach: handed to the workgroup
+                // while it has room, else tested here
+                int slot = kDeferCap;
+                if (near_mask && lane == 0 && *ndef < kDeferCap) slot = atomicAdd(ndef, __builtin_popcount(near_mask));
+                slot = __builtin_amdgcn_readfirstlane(slot);
+                while (near_mask) {   // wave-uniform
+                    const int u = __builtin_ctz(near_mask);
+                    near_mask &= near_mask - 1;
+                    if (slot < kDeferCap) {
+                        if (lane == 0)
+                            s_def[slot] = Deferred{lanes[u], kSphereBatch * qg + u, m_lo, m_hi, c_lo + cb * 64, i};
+                        ++slot;
+                    } else {
+                        block_min<CUBIC, DT>(points, jb + u * kBlockPts, m_lo, m_hi, lg, G, nx, nxy, m00, m01, m02,
+                                             w0, m10, m11, m12, w1, m20, m21, m22, w2, best);
+                    }
                 }
             }
         }
@@ -464,21 +498,16 @@ __global__ __launch_bounds__(kBlock) void query_kernel(QueryArgs p, const float*
     // the deferred blocks, dealt round-robin to the workgroup's waves
     const int nd = min(s_ndef, kDeferCap);
     for (int it = wave; it < nd; it += kWavesPerBlock) {
-        const uint64_t mask = (uint64_t)uniform64((int64_t)s_def[it].mask);
-        const int64_t blk = uniform64(s_def[it].blk);
-        const int64_t m_lo = uniform64(s_def[it].m_lo), m_hi = uniform64(s_def[it].m_hi);
-        const int c0 = __builtin_amdgcn_readfirstlane(s_def[it].c0);
-        const int i = __builtin_amdgcn_readfirstlane(s_def[it].link);
-        const bool mine = (mask >> lane) & 1u;
-        const int c = c0 + lane;
-        const LinkGrid& lg = p.link[i];
+        const DeferredView d = read_deferred(s_def[it], lane);
+        const int c = d.c0 + lane;
+        const LinkGrid& lg = p.link[d.link];
         Map mp;
-        load_map(p, i, c, mine, mp);
+        load_map(p, d.link, c, d.mine, mp);
         float best = INFINITY;
-        block_min<CUBIC, DT>(points, blk * kBlockPts, m_lo, m_hi, lg, grid + lg.offset, lg.n[0], lg.n[0] * lg.n[1],
-                             mp.m00, mp.m01, mp.m02, mp.w0, mp.m10, mp.m11, mp.m12, mp.w1, mp.m20, mp.m21, mp.m22,
-                             mp.w2, best);
-        if (mine && best < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(best));
+        block_min<CUBIC, DT>(points, d.blk * kBlockPts, d.m_lo, d.m_hi, lg, grid + lg.offset, lg.n[0],
+                             lg.n[0] * lg.n[1], mp.m00, mp.m01, mp.m02, mp.w0, mp.m10, mp.m11, mp.m12, mp.w1, mp.m20,
+                             mp.m21, mp.m22, mp.w2, best);
+        if (d.mine && best < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + d.link], ~lsdf::ordered_bits(best));
     }
 }
 

@@ -468,6 +468,64 @@ def query_from_joints(dh, q: torch.Tensor, grids: GridSet, points: torch.Tensor,
     return (dist, link, ld) if link_dist else (dist, link)
 
 
+class PreparedQueryFromJoints:
+    """lsdf_query_from_joints with every argument checked and marshalled
+    once, for a loop that makes the same call over and over on the same
+    buffers (new joint angles or points written into them in place between
+    calls, as a control cycle does).  Calling the object makes the C call and
+    nothing else, so the host cost of a step is one ctypes call.  The
+    tensors given here must stay allocated and keep their shapes; the stream
+    is fixed here too (the current one when none is given).  Arguments as in
+    query_from_joints; the outputs are ``dist``, ``link`` and ``link_dist``."""
+
+    def __init__(self, dh, q: torch.Tensor, grids: GridSet, points: torch.Tensor, *, base_T=None,
+                 c_offsets: torch.Tensor | None = None, m_offsets: torch.Tensor | None = None,
+                 link_T: torch.Tensor | None = None, link_dist: bool = False, tuning=None,
+                 workspace: torch.Tensor | None = None, out=None, stream=None):
+        lib = load_library()
+        rows, dof = _dh_rows(dh)
+        if q.dim() != 2 or q.shape[1] != dof:
+            raise ValueError(f"q must be [C][{dof}]")
+        _require(q, "q", torch.float32)
+        C, L, dev = int(q.shape[0]), dof + 1, q.device
+        if grids.L != L:
+            raise ValueError(f"grids has {grids.L} links, the arm has {L} frames")
+        if points.dim() != 2 or points.shape[1] != 3:
+            raise ValueError("points must be [M][3]")
+        _require(points, "points", torch.float32)
+        M = int(points.shape[0])
+        if grids.buf.device != dev or points.device != dev:
+            raise ValueError("q, grids and points must be on one device")
+        if (c_offsets is None) != (m_offsets is None):
+            raise ValueError("give both offset arrays or neither")
+        K = 1 if c_offsets is None else _offsets(c_offsets, m_offsets, dev)
+        if link_T is not None:
+            _require(link_T, "link_T", torch.float32, (C, L, 3, 4))
+        self.dist, self.link, self.link_dist = _query_outputs(out, C, L, dev, link_dist)
+        if workspace is None:
+            workspace = torch.empty(query_batched_workspace_size(K, C, L, M), dtype=torch.uint8, device=dev)
+        _require(workspace, "workspace", torch.uint8)
+        b, base_p = _base_ptr(base_T)
+        self._tuning = tuning
+        vp, i32 = ct.c_void_p, ct.c_int32
+        self._keep = (rows, b, q, grids, points, c_offsets, m_offsets, link_T, workspace, tuning)
+        self._fn = lib.lsdf_query_from_joints
+        self._args = (
+            rows, i32(dof), base_p, vp(q.data_ptr()), i32(K),
+            vp(c_offsets.data_ptr()) if c_offsets is not None else None,
+            vp(m_offsets.data_ptr()) if m_offsets is not None else None, i32(C), grids.desc,
+            vp(grids.buf.data_ptr()), vp(points.data_ptr()) if M > 0 else None, ct.c_int64(M),
+            vp(link_T.data_ptr()) if link_T is not None else None, vp(self.dist.data_ptr()),
+            vp(self.link.data_ptr()), vp(self.link_dist.data_ptr()) if self.link_dist is not None else None,
+            ct.byref(tuning) if tuning is not None else None, ct.c_uint32(0), vp(workspace.data_ptr()),
+            ct.c_size_t(workspace.numel()), _stream_handle(stream, dev))
+
+    def __call__(self):
+        rc = self._fn(*self._args)
+        if rc != LSDF_OK:
+            _check(rc)
+
+
 def query_autotune(link_T: torch.Tensor, grids: GridSet, points: torch.Tensor, c_offsets: torch.Tensor,
                    m_offsets: torch.Tensor, *, candidates=None, reps: int = 5, workspace=None, stream=None):
     """Times the batched query under each candidate tiling

@@ -405,3 +405,26 @@ def test_end_to_end_vs_double_oracle(B, orc, name, tiny_grids, paper_grids):
     assert np.array_equal(l[single], np.argmax(cand[single], axis=1))
     say(f"  argmin: {single.sum()} waypoints with one possible link (equal), {(fin_c & ~single).sum()} near-ties")
     assert np.all((l == -1) == ~np.isfinite(d))
+
+
+def test_prepared_call_matches_the_wrapper(B, orc, tiny, tiny_grids):
+    """The prepared fused call (arguments marshalled once) gives the
+    convenience wrapper's bits, also after new joint angles and points are
+    written into its buffers in place."""
+    gs = upload_grids(B, tiny, tiny_grids)
+    q = to_dev(tiny.q)
+    pts = to_dev(tiny.points)
+    T = torch.empty((tiny.C, tiny.L, 3, 4), dtype=torch.float32, device="cuda")
+    call = B.PreparedQueryFromJoints(tiny.robot.dh, q, gs, pts, base_T=tiny.robot.base_T, link_T=T,
+                                     link_dist=True)
+    for k in range(3):
+        if k:
+            q.copy_(torch.roll(q, 7, 0))
+            pts.copy_(torch.roll(pts, 333, 0) * 0.9)
+        say(f"prepared call, round {k}")
+        call()
+        want = B.query_from_joints(tiny.robot.dh, q, gs, pts, base_T=tiny.robot.base_T, link_dist=True)
+        torch.cuda.synchronize()
+        for a, b in zip((call.dist, call.link, call.link_dist), want):
+            assert torch.equal(a.view(torch.int32), b.view(torch.int32)), k
+        assert torch.isfinite(call.dist).any()
