@@ -238,7 +238,7 @@ def extra_scenes(dev, steps: int, warmup: int):
     return out
 
 
-def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 8):
+def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 50):
     """The learned form on the 500 x 100,000 x 7 workload (64^3 grids): per-link
     networks trained on the GPU (untimed), then the grid-only query and the
     network-plus-fallback query timed on the same inputs, and the learned
@@ -275,6 +275,10 @@ def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 8):
                                                             out=outm), steps, 1)
     d_grid = outg[0].cpu().numpy().astype(np.float64)
     d_mlp = outm[0].cpu().numpy().astype(np.float64)
+    # per-link minima too (same calls, with link_dist), for the far-field judge
+    lg = lsdf.query_min_distance(T, gs, pts, workspace=ws, link_dist=True)[2].cpu().numpy().astype(np.float64)
+    lm = lsdf.query_min_distance_mlp(T, gs, params, doms, pts, margin=0.05, workspace=ws,
+                                     link_dist=True)[2].cpu().numpy().astype(np.float64)
     # judge: exact minimum of grid-in-box / mesh-outside over each link's domain
     sel = np.linspace(0, w.C - 1, judge_waypoints).round().astype(int)
     log(f"learned variant: judging {len(sel)} waypoints with the oracle")
@@ -284,7 +288,22 @@ def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 8):
     judge, _ = oracle.reduce(jcl)
     both = np.isfinite(judge) & np.isfinite(d_mlp[sel])
     err = np.abs(d_mlp[sel][both] - judge[both]) * 1e3
+    # the moving links 1-6 (link 0 stands 4 cm from the table at every
+    # waypoint, so the grid fallback decides every whole-robot clearance)
+    g6, m6, j6 = lg[sel][:, 1:], lm[sel][:, 1:], jcl[:, 1:]
+    far = ~np.isfinite(g6) & np.isfinite(j6)
+    near = np.isfinite(g6) & np.isfinite(j6)
+    ef = np.abs(m6[far] - j6[far]) * 1e3
+    en = np.abs(m6[near] - j6[near]) * 1e3
+    eg = np.abs(g6[near] - j6[near]) * 1e3
+    gw, mw, jw = g6.min(1), m6.min(1), j6.min(1)
+    farw = ~np.isfinite(gw) & np.isfinite(jw)
+    ew = np.abs(mw[farw] - jw[farw]) * 1e3
     pairs = w.C * w.M * w.L
+
+    def stats(e):
+        return {"max_mm": round(float(e.max()), 3), "mean_mm": round(float(e.mean()), 3),
+                "p99_mm": round(float(np.percentile(e, 99)), 3)} if e.size else None
     return {
         "workload": f"{w.name}: {w.C} waypoints x {w.M} points x {w.L} links, 64^3 FP32 grids, "
                     f"3-128-128-128-1 SiLU network per link (bf16 MFMA, FP32 accumulate), fallback below 5 cm",
@@ -295,6 +314,19 @@ def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 8):
         "judged_waypoints": int(len(sel)),
         "max_err_mm": round(float(err.max()), 3) if err.size else None,
         "mean_err_mm": round(float(err.mean()), 3) if err.size else None,
+        "whole_robot_note": "every whole-robot clearance here is the base link's 4 cm to the table, which the "
+                            "grid fallback gives exactly",
+        "far_field_links_1_6": {
+            "link_minima_judged": int(g6.size),
+            "grid_inf_exact_finite": int(far.sum()),
+            "network_finite_there": int(np.isfinite(m6[far]).sum()),
+            "exact_range_m": [round(float(j6[far].min()), 4), round(float(j6[far].max()), 4)] if far.any() else None,
+            "network_error": stats(ef),
+            "meets_1mm": bool(ef.size and ef.max() <= 1.0),
+            "waypoints_without_grid_answer": int(farw.sum()),
+            "waypoint_network_error": stats(ew)},
+        "inside_capture_range_links_1_6": {"link_minima": int(near.sum()), "learned_error": stats(en),
+                                           "grid_error": stats(eg)},
         "grid_inf_waypoints": int(np.sum(~np.isfinite(d_grid))),
         "mlp_inf_waypoints": int(np.sum(~np.isfinite(d_mlp))),
         "train_s": round(train_s, 1),

@@ -47,6 +47,7 @@ constexpr int TILE_TRAIN = 16 * NT_TRAIN;
 constexpr int WTILE_ELEMS = H * H;      // bf16 elements of one staged 128x128 layer
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 // Small FP32 parameters kept in LDS (W1 and w4 already rounded to bf16).
@@ -56,6 +57,7 @@ struct SmallParams {
     float b2[H];
     float b3[H];
     float w4[H];
+    __bf16 w4b[H];   // w4 as bfloat16 pairs for the output layer's dot products
     float b4;
 };
 
@@ -100,6 +102,7 @@ __device__ inline void stage_small(SmallParams* sp, const float* __restrict__ P)
         sp->b2[u] = P[OFF_B2 + u];
         sp->b3[u] = P[OFF_B3 + u];
         sp->w4[u] = bf16_round(P[OFF_W4 + u]);
+        sp->w4b[u] = (__bf16)P[OFF_W4 + u];
     }
     if (threadIdx.x == 0) sp->b4 = P[OFF_B4];
 }
@@ -161,11 +164,15 @@ __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const 
     for (int layer = 0; layer < 2; ++layer) {
         const __bf16* sW = layer == 0 ? sW2 : sW3;
         const float* bias = layer == 0 ? sp->b2 : sp->b3;
+        // the accumulators start at the bias: z = b + W h
         f32x4 acc[8][NT_];
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt)
+        for (int mt = 0; mt < 8; ++mt) {
+            const f32x4 b0 = f32x4{bias[16 * mt + 4 * g], bias[16 * mt + 4 * g + 1], bias[16 * mt + 4 * g + 2],
+                                   bias[16 * mt + 4 * g + 3]};
 #pragma unroll
-            for (int nt = 0; nt < NT_; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int nt = 0; nt < NT_; ++nt) acc[mt][nt] = b0;
+        }
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
 #pragma unroll
@@ -185,7 +192,7 @@ __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const 
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int u = 16 * mt + 4 * g + r;
-                        const float z = acc[mt][nt][r] + bias[u];
+                        const float z = acc[mt][nt][r];
                         const __bf16 h = (__bf16)silu(z);
                         b[mt >> 1][nt][(mt & 1) * 4 + r] = h;
                         if (TRACE) {
@@ -195,22 +202,27 @@ __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const 
                         }
                     }
         } else {
-            // bias + SiLU, rounded, and this lane's part of w4 . h3
+            // SiLU, rounded, and this lane's part of w4 . h3 (bfloat16
+            // pairs, products exact, FP32 sums)
 #pragma unroll
             for (int nt = 0; nt < NT_; ++nt) {
                 float part = 0.0f;
 #pragma unroll
                 for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
+                    for (int r = 0; r < 4; r += 2) {
                         const int u = 16 * mt + 4 * g + r;
-                        const float z = acc[mt][nt][r] + bias[u];
-                        const __bf16 h = (__bf16)silu(z);
-                        part = fmaf(sp->w4[u], (float)h, part);
+                        const float z0 = acc[mt][nt][r], z1 = acc[mt][nt][r + 1];
+                        const __bf16 h0 = (__bf16)silu(z0), h1 = (__bf16)silu(z1);
+                        const bf16x2 hp = {h0, h1};
+                        const bf16x2 wp = {sp->w4b[u], sp->w4b[u + 1]};
+                        part = __builtin_amdgcn_fdot2_f32_bf16(hp, wp, part, false);
                         if (TRACE) {
                             const int64_t c = tr.col0 + 16 * nt + col;
-                            tr.z3[u * tr.ld + c] = z;
-                            tr.h3[u * tr.ld + c] = h;
+                            tr.z3[u * tr.ld + c] = z0;
+                            tr.h3[u * tr.ld + c] = h0;
+                            tr.z3[(u + 1) * tr.ld + c] = z1;
+                            tr.h3[(u + 1) * tr.ld + c] = h1;
                         }
                     }
                 part += __shfl_xor(part, 16, 64);

@@ -263,18 +263,23 @@ def surface_points(mesh: Mesh, n: int, rng: np.random.Generator) -> np.ndarray:
 
 
 def mlp_samples(mesh: Mesh, lo, hi, n: int, seed: int, far: float = MLP_FAR):
-    """n link-frame training positions: 35 % near the surface (surface point +
-    N(0, 2 cm)), 25 % in the band around it (surface point + N(0, 15 cm)),
-    20 % uniform in the grid box and 20 % uniform in the network's domain."""
+    """n link-frame training positions: 20 % near the surface (surface point
+    + N(0, 2 cm)), 10 % in the band around it (surface point + N(0, 15 cm)),
+    50 % in the shell where the network's answers are used (surface point +
+    a uniform random direction times a distance uniform in [0, 60 cm]), 10 %
+    uniform in the grid box and 10 % uniform in the network's domain."""
     rng = np.random.default_rng(seed)
-    n_near, n_band, n_box = int(0.35 * n), int(0.25 * n), int(0.2 * n)
-    n_dom = n - n_near - n_band - n_box
+    n_near, n_band, n_shell, n_box = int(0.2 * n), int(0.1 * n), int(0.5 * n), int(0.1 * n)
+    n_dom = n - n_near - n_band - n_shell - n_box
     cen, half = mlp_domain(lo, hi, far)
     near = surface_points(mesh, n_near, rng) + rng.normal(0.0, 0.02, size=(n_near, 3))
     band = surface_points(mesh, n_band, rng) + rng.normal(0.0, 0.15, size=(n_band, 3))
+    u = rng.normal(size=(n_shell, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    shell = surface_points(mesh, n_shell, rng) + u * rng.uniform(0.0, 0.6, size=(n_shell, 1))
     box = rng.uniform(lo, hi, size=(n_box, 3))
     dom = rng.uniform(cen - half, cen + half, size=(n_dom, 3))
-    pts = np.concatenate([near, band, box, dom])
+    pts = np.concatenate([near, band, shell, box, dom])
     return pts[rng.permutation(n)]
 
 

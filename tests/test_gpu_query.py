@@ -428,3 +428,46 @@ def test_prepared_call_matches_the_wrapper(B, orc, tiny, tiny_grids):
         for a, b in zip((call.dist, call.link, call.link_dist), want):
             assert torch.equal(a.view(torch.int32), b.view(torch.int32)), k
         assert torch.isfinite(call.dist).any()
+
+
+@pytest.fixture(scope="module")
+def precision_ws(orc):
+    w = synth.make_workload("precision")
+    say("oracle grids 128^3 (double, brute force)")
+    return w, orc.workload_grids(w)
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
+def test_query_precision_scale_sampled(B, orc, precision_ws, dt):
+    """The precision workload at full size (500 waypoints x 100,000 points x
+    7 links, 128^3 grids stored as FP32, bfloat16 or binary16) in the launch
+    configuration the benchmark times: 16 sampled waypoints bit for bit
+    against the single-precision twin on the same rounded grids, and the
+    clearance within the storage bound of the double oracle (u times the
+    link's largest |node| plus 1e-5 m, u = 2^-8, 2^-11, 0)."""
+    w, grids64 = precision_ws
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[dt]
+    u = {"f32": 0.0, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}[dt]
+    gs = B.GridSet(w.grid_lo, w.grid_hi, w.grid_n, device="cuda", dtype=tdt)
+    for i, g in enumerate(grids64):
+        gs.set_grid(i, g.astype(np.float32))
+    # the twin's grids: the oracle's values rounded on the CPU (FP64 -> FP32 -> storage type, nearest even)
+    rounded = [torch.tensor(g.astype(np.float32)).to(tdt).float().numpy().astype(np.float64) for g in grids64]
+    T32 = orc.fk(w.robot.dh, w.q, w.robot.base_T).astype(np.float32)
+    pts = w.points.astype(np.float32)
+    say(f"precision scale {dt}: C={w.C} M={w.M} n=128")
+    d, l, ld = B.query_min_distance(to_dev(T32), gs, to_dev(pts), link_dist=True)
+    torch.cuda.synchronize()
+    d, l, ld = d.cpu().numpy(), l.cpu().numpy(), ld.cpu().numpy()
+    sel = np.linspace(0, w.C - 1, 16).round().astype(int)
+    ref = twin(orc, w, T32[sel], rounded, pts)
+    assert_bit_exact((d[sel], l[sel], ld[sel]), ref)
+    assert np.isfinite(d).mean() > 0.5
+    # against the double oracle (its own kinematics and grids)
+    rd, _ = orc.reduce(orc.query_f64(orc.fk(w.robot.dh, w.q[sel], w.robot.base_T), w.grid_lo, w.grid_hi, w.grid_n,
+                                     grids64, w.points))
+    fin = np.isfinite(rd) & np.isfinite(d[sel])
+    bound = u * max(np.abs(g).max() for g in grids64) + 1e-5
+    err = np.abs(d[sel][fin].astype(np.float64) - rd[fin])
+    say(f"  {dt}: max |gpu - double| {err.max():.3g} m over {fin.sum()} waypoints (bound {bound:.3g} m)")
+    assert err.max() <= bound
