@@ -493,6 +493,15 @@ ORC_EXPORT void orc_reduce_f32(const float* cl, int32_t C, int32_t L, float* d, 
 /* W3[128][128], b3, w4[128], b4.  Inputs are normalised coordinates.         */
 /* Loss: mean absolute error over the batch (the paper trains its own tiny   */
 /* network with an L1 loss and Adam, Sec. IV-B); subgradient sign(0) = 0.    */
+/*                                                                           */
+/* The surrogate's estimate of link i's signed distance at a link-frame     */
+/* point l is the network plus a fixed core term (the build's reading):     */
+/*   F(l) = m((l - c) / h) + E(l),  E(l) = || max(|l - c| - k, 0) ||,        */
+/* c and h the centre and half extent of the network's domain, k the half    */
+/* extent of the link's core box (its mesh's bounding box, centred at c).    */
+/* E is the distance from l to that box (0 inside it), which the true        */
+/* distance approaches far from the link, so the network only learns the     */
+/* bounded, slowly varying remainder.                                        */
 /* ------------------------------------------------------------------------ */
 #define ORC_H 128
 #define ORC_OFF_W1 0
@@ -565,11 +574,38 @@ ORC_EXPORT void orc_mlp_forward(const double* P, const double* X, int64_t N, int
     }
 }
 
+/* Distance from link-frame point l to the core box |l_a - c_a| <= k_a. */
+static double core_distance(const double* l, const double* c, const double* k) {
+    double q2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double e = fabs(l[a] - c[a]) - k[a];
+        if (e > 0.0) q2 += e * e;
+    }
+    return sqrt(q2);
+}
+
+/* The surrogate's estimate F at N link-frame points L [N][3] of one link:   */
+/* the network at (l - c) / h plus the core term E(l) (core_k NULL: none).   */
+ORC_EXPORT void orc_mlp_value(const double* P, const double* Lp, int64_t N, const double* dom_c,
+                              const double* dom_h, const double* core_k, int32_t bf16, double* out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < N; ++j) {
+        double z1[ORC_H], h1[ORC_H], z2[ORC_H], h2[ORC_H], z3[ORC_H], h3[ORC_H];
+        const double* l = Lp + 3 * j;
+        double xh[3];
+        for (int a = 0; a < 3; ++a) xh[a] = (l[a] - dom_c[a]) / dom_h[a];
+        double m = mlp_forward_one(P, xh, bf16, z1, h1, z2, h2, z3, h3);
+        out[j] = core_k ? m + core_distance(l, dom_c, core_k) : m;
+    }
+}
+
 /* Mean-absolute-error loss over N samples and its gradient (chain rule,
- * layer by layer).  With bf16 != 0 the backward pass also rounds where the
- * GPU kernels do: the delta vectors dz3 and dz2 before they are multiplied
- * (weight gradients and the back-propagated deltas). */
-ORC_EXPORT double orc_mlp_loss_grad(const double* P, const double* X, const double* Y, int64_t N,
+ * layer by layer).  The estimate of sample j is the network's output plus
+ * D[j] (the core term at the sample; D NULL: none), and the loss is
+ * mean |estimate - Y|.  With bf16 != 0 the backward pass also rounds where
+ * the GPU kernels do: the delta vectors dz3 and dz2 before they are
+ * multiplied (weight gradients and the back-propagated deltas). */
+ORC_EXPORT double orc_mlp_loss_grad(const double* P, const double* X, const double* D, const double* Y, int64_t N,
                                     int32_t bf16, double* grad) {
 #define R(v) (bf16 ? bf16r(v) : (v))
     memset(grad, 0, ORC_NPARAM * sizeof(double));
@@ -579,7 +615,7 @@ ORC_EXPORT double orc_mlp_loss_grad(const double* P, const double* X, const doub
         double d3[ORC_H], d2[ORC_H], d1[ORC_H];
         const double* x = X + 3 * j;
         double m = mlp_forward_one(P, x, bf16, z1, h1, z2, h2, z3, h3);
-        double r = m - Y[j];
+        double r = (D ? m + D[j] : m) - Y[j];
         loss += fabs(r);
         double dm = (r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0)) / (double)N;
         grad[ORC_OFF_B4] += dm;
@@ -708,7 +744,8 @@ ORC_EXPORT void orc_judge_min(const double* T, int32_t C, int32_t L, const doubl
 /*   l = R^T (x - t) in double from the FP32 pose; the pair counts only if    */
 /*   l lies in link i's network domain, |(l_a - dom_c_a) / dom_h_a| <= 1;    */
 /*   m = the network of link i at the normalised point (mlp_forward_one,      */
-/*       bfloat16 rounding points when bf16 != 0);                           */
+/*       bfloat16 rounding points when bf16 != 0) plus the core term E(l)    */
+/*       (core_k [L][3] the core boxes' half extents; NULL: no core term);   */
 /*   if m < margin and the single-precision twin places the point in the     */
 /*   grid box, the pair's value is the twin's grid value, else it is m (a     */
 /*   point outside the box keeps m: the grid has no value there).             */
@@ -719,7 +756,8 @@ ORC_EXPORT void orc_judge_min(const double* T, int32_t C, int32_t L, const doubl
 ORC_EXPORT void orc_query_mlp(const float* T, int32_t C, int32_t L, const float* lo, const float* hi,
                               const int32_t* n, const float* grids, const int64_t* offs, const float* P,
                               int64_t M, const double* params, const double* dom_c, const double* dom_h,
-                              double margin, int32_t bf16, double* out, double* each_m, double* each_g) {
+                              const double* core_k, double margin, int32_t bf16, double* out, double* each_m,
+                              double* each_g) {
     float* gl = (float*)malloc(sizeof(float) * (size_t)L);
     float* ge = (float*)malloc(sizeof(float) * (size_t)L * (size_t)(M > 0 ? M : 1));
     for (int32_t c = 0; c < C; ++c) {
@@ -733,11 +771,11 @@ ORC_EXPORT void orc_query_mlp(const float* T, int32_t C, int32_t L, const float*
 #pragma omp parallel for schedule(static) reduction(min : best)
             for (int64_t j = 0; j < M; ++j) {
                 double d[3] = {(double)P[3 * j] - Ti[3], (double)P[3 * j + 1] - Ti[7], (double)P[3 * j + 2] - Ti[11]};
-                double xh[3];
+                double xh[3], l[3];
                 int indom = 1;
                 for (int a = 0; a < 3; ++a) {
-                    double l = (double)Ti[0 + a] * d[0] + (double)Ti[4 + a] * d[1] + (double)Ti[8 + a] * d[2];
-                    xh[a] = (l - dom_c[3 * i + a]) / dom_h[3 * i + a];
+                    l[a] = (double)Ti[0 + a] * d[0] + (double)Ti[4 + a] * d[1] + (double)Ti[8 + a] * d[2];
+                    xh[a] = (l[a] - dom_c[3 * i + a]) / dom_h[3 * i + a];
                     if (fabs(xh[a]) > 1.0) indom = 0;
                 }
                 const double g = (double)ge[(int64_t)i * M + j];
@@ -745,6 +783,7 @@ ORC_EXPORT void orc_query_mlp(const float* T, int32_t C, int32_t L, const float*
                 if (indom || each_m) {
                     double z1[ORC_H], h1[ORC_H], z2[ORC_H], h2[ORC_H], z3[ORC_H], h3[ORC_H];
                     m = mlp_forward_one(Pi, xh, bf16, z1, h1, z2, h2, z3, h3);
+                    if (core_k) m += core_distance(l, dom_c + 3 * i, core_k + 3 * i);
                 }
                 if (indom) {
                     double v = (m < margin && g < INFINITY) ? g : m;

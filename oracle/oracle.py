@@ -78,8 +78,10 @@ def load():
     lib.orc_mlp_nparam.argtypes = []
     lib.orc_mlp_forward.restype = None
     lib.orc_mlp_forward.argtypes = [_dp, _dp, ct.c_int64, ct.c_int32, _dp]
+    lib.orc_mlp_value.restype = None
+    lib.orc_mlp_value.argtypes = [_dp, _dp, ct.c_int64, _dp, _dp, _dp, ct.c_int32, _dp]
     lib.orc_mlp_loss_grad.restype = ct.c_double
-    lib.orc_mlp_loss_grad.argtypes = [_dp, _dp, _dp, ct.c_int64, ct.c_int32, _dp]
+    lib.orc_mlp_loss_grad.argtypes = [_dp, _dp, _dp, _dp, ct.c_int64, ct.c_int32, _dp]
     lib.orc_adam_step.restype = None
     lib.orc_adam_step.argtypes = [_dp, _dp, _dp, _dp, ct.c_int64, ct.c_int64, ct.c_double, ct.c_double,
                                   ct.c_double, ct.c_double]
@@ -88,7 +90,7 @@ def load():
                                   ct.POINTER(_ip), ct.POINTER(_ip), _ip, _dp, _dp, _dp, _dp, _dp, ct.c_int64, _dp]
     lib.orc_query_mlp.restype = None
     lib.orc_query_mlp.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _fp, _ip, _fp, _lp, _fp, ct.c_int64, _dp, _dp,
-                                  _dp, ct.c_double, ct.c_int32, _dp, _dp, _dp]
+                                  _dp, _dp, ct.c_double, ct.c_int32, _dp, _dp, _dp]
     lib.orc_query_f32_each.restype = None
     lib.orc_query_f32_each.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _fp, _ip, _fp, _lp, _fp, ct.c_int64, _fp,
                                        _fp]
@@ -438,11 +440,13 @@ def judge_min(T, lo, hi, n, grids, meshes, dom_c, dom_h, points) -> np.ndarray:
     return out
 
 
-def query_mlp(T, lo, hi, n, grids, points, params, dom_c, dom_h, margin, bf16=True, each=False):
+def query_mlp(T, lo, hi, n, grids, points, params, dom_c, dom_h, margin, bf16=True, each=False, core_k=None):
     """Per-link minima [C][L] of the learned clearance with its margin
-    fallback: network value per in-domain pair, replaced by the single-
+    fallback: the surrogate's estimate per in-domain pair (the network plus
+    the distance to the core box of half extents core_k [L][3] centred on the
+    domain; core_k None: the network alone), replaced by the single-
     precision twin's grid value when it is below the margin and the point is
-    in the grid box.  With each=True also returns the per-pair network values
+    in the grid box.  With each=True also returns the per-pair estimates
     (evaluated for every pair, in the domain or not) and twin grid values
     (+inf outside the box), [C][L][M]."""
     lib = load()
@@ -458,9 +462,10 @@ def query_mlp(T, lo, hi, n, grids, points, params, dom_c, dom_h, margin, bf16=Tr
     em = np.empty((C, L, M), dtype=np.float64) if each else None
     eg = np.empty((C, L, M), dtype=np.float64) if each else None
     null = ct.POINTER(ct.c_double)()
+    ck = None if core_k is None else _c(core_k, np.float64).reshape(L, 3)
     lib.orc_query_mlp(_ptr(T, _fp), C, L, _ptr(lo, _fp), _ptr(hi, _fp), _ptr(n, _ip), _ptr(buf, _fp),
                       _ptr(offs, _lp), _ptr(P, _fp), M, _ptr(prm, _dp), _ptr(dc, _dp), _ptr(dh, _dp),
-                      float(margin), int(bool(bf16)), _ptr(out, _dp),
+                      null if ck is None else _ptr(ck, _dp), float(margin), int(bool(bf16)), _ptr(out, _dp),
                       _ptr(em, _dp) if each else null, _ptr(eg, _dp) if each else null)
     return (out, em, eg) if each else out
 
@@ -518,14 +523,32 @@ def mlp_forward(params, X, bf16: bool = False) -> np.ndarray:
     return out
 
 
-def mlp_loss_grad(params, X, Y, bf16: bool = False):
-    """(mean absolute error, gradient [nparam])."""
+def mlp_value(params, points, dom_c, dom_h, core_k=None, bf16: bool = False) -> np.ndarray:
+    """The surrogate's estimate at link-frame points [N][3] of one link: the
+    network at (l - dom_c) / dom_h plus the distance from l to the core box
+    |l - dom_c| <= core_k (core_k None: the network alone)."""
+    lib = load()
+    P = _c(params, np.float64)
+    X = _c(np.atleast_2d(points), np.float64)
+    dc, dh = _c(dom_c, np.float64).reshape(3), _c(dom_h, np.float64).reshape(3)
+    ck = None if core_k is None else _c(core_k, np.float64).reshape(3)
+    out = np.empty(X.shape[0], dtype=np.float64)
+    lib.orc_mlp_value(_ptr(P, _dp), _ptr(X, _dp), X.shape[0], _ptr(dc, _dp), _ptr(dh, _dp),
+                      ct.POINTER(ct.c_double)() if ck is None else _ptr(ck, _dp), int(bf16), _ptr(out, _dp))
+    return out
+
+
+def mlp_loss_grad(params, X, Y, bf16: bool = False, offset=None):
+    """(mean absolute error, gradient [nparam]) of the estimate network(X) +
+    offset (per sample; None: the network alone) against Y."""
     lib = load()
     P = _c(params, np.float64)
     X = _c(np.atleast_2d(X), np.float64)
     Y = _c(Y, np.float64)
+    D = None if offset is None else _c(offset, np.float64)
     g = np.empty(P.shape[0], dtype=np.float64)
-    loss = lib.orc_mlp_loss_grad(_ptr(P, _dp), _ptr(X, _dp), _ptr(Y, _dp), X.shape[0], int(bf16), _ptr(g, _dp))
+    loss = lib.orc_mlp_loss_grad(_ptr(P, _dp), _ptr(X, _dp), ct.POINTER(ct.c_double)() if D is None else _ptr(D, _dp),
+                                 _ptr(Y, _dp), X.shape[0], int(bf16), _ptr(g, _dp))
     return float(loss), g
 
 
@@ -554,5 +577,5 @@ def mlp_unpack(params):
 
 __all__ = ["FRNN_HIDDEN", "frnn_forward", "frnn_loss_grad", "frnn_nparam", "frnn_target", "align", "robot_sdf_f64", "robot_sdf_query", "voxel_centres", "voxel_index", "build_grid", "exact_min", "fk", "grid_bound", "mesh_sdf", "point_triangle_distance",
            "query_batched", "query_f32", "query_f32_each", "query_f64", "query_f64_each", "query_mlp", "reduce", "trilinear_f64", "winding_number", "workload_grids",
-           "MLP_HIDDEN", "adam_step", "judge_min", "mlp_forward", "mlp_loss_grad", "mlp_nparam", "mlp_unpack",
+           "MLP_HIDDEN", "adam_step", "judge_min", "mlp_forward", "mlp_loss_grad", "mlp_value", "mlp_nparam", "mlp_unpack",
            "max_threads", "set_threads"]

@@ -13,7 +13,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .robot import (GRID_PAD, MLP_FAR, Mesh, Robot, box_mesh, capsule_mesh, grid_box, make_robot, mlp_domain, mlp_init,
+from .robot import (GRID_PAD, MLP_FAR, Mesh, Robot, box_mesh, capsule_mesh, grid_box, make_robot, mlp_core, mlp_domain, mlp_init,
                     mlp_samples, sphere_mesh, surface_points, union_mesh)
 from .scene import human_table, uniform_cube
 from .traj import make_waypoints
@@ -164,5 +164,5 @@ def make_batched(K: int = 64, C_range=(50, 1000), M_range=(5000, 200000), n: int
 
 __all__ = ["BatchedWorkload", "make_batched", "BASE_SEED", "GRID_PAD", "Mesh", "Robot", "Workload", "WORKLOADS", "box_mesh",
            "capsule_mesh", "grid_box", "human_table", "make_robot", "make_waypoints",
-           "make_workload", "sphere_mesh", "uniform_cube", "union_mesh", "MLP_FAR", "mlp_domain", "mlp_init",
+           "make_workload", "sphere_mesh", "uniform_cube", "union_mesh", "MLP_FAR", "mlp_core", "mlp_domain", "mlp_init",
            "mlp_samples", "surface_points"]

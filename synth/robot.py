@@ -251,6 +251,16 @@ def mlp_domain(lo, hi, far: float = MLP_FAR):
     return (lo + hi) / 2, (hi - lo) / 2 + far
 
 
+def mlp_core(lo, hi, pad: float = GRID_PAD):
+    """Half extents of a link's core box, centred on its grid box (and
+    network domain): the mesh's bounding box, i.e. the grid box shrunk by the
+    pad it was grown by.  The surrogate adds the distance to this box to its
+    network's output."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    return np.maximum((hi - lo) / 2 - pad, 0.0)
+
+
 def surface_points(mesh: Mesh, n: int, rng: np.random.Generator) -> np.ndarray:
     """Uniform points on the mesh surface (area-weighted triangles, uniform
     barycentric coordinates)."""

@@ -250,3 +250,105 @@ def test_query_mlp_fallback_rule_with_constant_network(orc, tiny, tiny_grids, k)
             assert got[c, i] == want, (c, i, got[c, i], want)
     if k < 0.05:
         assert (inbox.any(-1) & (got < k)).any()     # some minima come from the grid
+
+
+# ---------------------------------------------------------------------------
+# the core term: the estimate is the network plus the distance to the core box
+# ---------------------------------------------------------------------------
+
+_CORE_C = np.array([0.1, -0.2, 0.3])
+_CORE_K = np.array([0.2, 0.1, 0.3])
+_CORE_H = np.array([1.5, 1.4, 1.6])
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_core_term_closed_forms(orc, bf16):
+    """A network that outputs the constant b4 (every weight zero, SiLU(0) =
+    0): the estimate is b4 + the distance to the core box, worked out by hand
+    for points inside it, on a face, beyond a face, an edge (3-4-5) and a
+    corner (3-4-12-13)."""
+    P = np.zeros(orc.mlp_nparam())
+    c, k = _CORE_C, _CORE_K
+    pts = np.array([c,                                              # centre
+                    c + [0.1, 0.05, -0.2],                          # inside
+                    c + [0.2, 0.0, 0.0],                            # on a face
+                    c + [0.2 + 0.05, 0.0, 0.0],                     # beyond a face
+                    c + [0.0, -(0.1 + 0.03), 0.3 + 0.04],           # beyond an edge
+                    c + [0.2 + 0.03, 0.1 + 0.04, -(0.3 + 0.12)]])   # beyond a corner
+    want = np.array([0.0, 0.0, 0.0, 0.05, 0.05, 0.13])
+    for b4 in (0.0, 0.25):
+        P[-1] = b4
+        got = orc.mlp_value(P, pts, c, _CORE_H, k, bf16=bf16)
+        assert np.allclose(got, b4 + want, rtol=0, atol=1e-15), (b4, got)
+    # without a core box the estimate is the network alone
+    assert np.all(orc.mlp_value(P, pts, c, _CORE_H, None, bf16=bf16) == 0.25)
+
+
+def test_core_term_adds_the_projection_distance(orc):
+    """A random network: the estimate equals the network at the normalised
+    point plus the distance from the point to its projection onto the box
+    (a clamp, formed here independently of the oracle's formula)."""
+    P = rand_params(orc, 31, scale=2.0)
+    rng = np.random.default_rng(32)
+    pts = _CORE_C + rng.uniform(-1.2, 1.2, size=(200, 3)) * _CORE_H
+    proj = np.clip(pts, _CORE_C - _CORE_K, _CORE_C + _CORE_K)
+    want = orc.mlp_forward(P, (pts - _CORE_C) / _CORE_H) + np.linalg.norm(pts - proj, axis=1)
+    got = orc.mlp_value(P, pts, _CORE_C, _CORE_H, _CORE_K)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert np.mean(np.linalg.norm(pts - proj, axis=1) > 0) > 0.5      # most points lie outside the box
+
+
+def test_loss_grad_with_offset_matches_torch_autograd(orc):
+    """The loss of the estimate network(x) + D against Y, and its gradient,
+    against PyTorch autograd in float64 with the offset added there."""
+    P = rand_params(orc, 33, scale=2.0)
+    rng = np.random.default_rng(34)
+    X = rng.uniform(-1, 1, size=(40, 3))
+    D = rng.uniform(0.0, 0.8, size=40)
+    Y = rng.uniform(-1, 2, size=40)
+    loss, g = orc.mlp_loss_grad(P, X, Y, offset=D)
+    net = torch_net(orc, P)
+    out = net(torch.tensor(X))[:, 0] + torch.tensor(D)
+    tl = torch.nn.functional.l1_loss(out, torch.tensor(Y))
+    tl.backward()
+    tg = np.concatenate([net[0].weight.grad.numpy().ravel(), net[0].bias.grad.numpy(),
+                         net[2].weight.grad.numpy().ravel(), net[2].bias.grad.numpy(),
+                         net[4].weight.grad.numpy().ravel(), net[4].bias.grad.numpy(),
+                         net[6].weight.grad.numpy().ravel(), net[6].bias.grad.numpy()])
+    assert loss == pytest.approx(tl.item(), abs=1e-14)
+    assert np.max(np.abs(g - tg)) < 1e-13 * max(1.0, np.abs(tg).max())
+    # the offset matters: without it some residual signs differ
+    _, g0 = orc.mlp_loss_grad(P, X, Y)
+    assert np.max(np.abs(g0 - g)) > 1e-3 * np.abs(tg).max()
+
+
+@pytest.mark.parametrize("margin", [-np.inf, 0.05])
+def test_query_mlp_core_term_with_constant_network(orc, tiny, tiny_grids, margin):
+    """A constant network b4 = 0.01 with each link's core box (its mesh's
+    bounding box): an in-domain pair's estimate is 0.01 + its distance to
+    the box (a clamp, in numpy).  margin -inf: the per-link minimum is the
+    smallest estimate; margin 0.05: a pair whose estimate is below the
+    margin and whose point is in the grid box takes the single-precision
+    twin's grid value instead."""
+    import synth
+    T32, dc, dh, pts = _mlp_setup(orc, tiny)
+    ck = synth.mlp_core(tiny.grid_lo, tiny.grid_hi)
+    alo = np.array([m.verts.min(0) for m in tiny.robot.links])
+    ahi = np.array([m.verts.max(0) for m in tiny.robot.links])
+    assert np.allclose(dc - ck, alo, atol=1e-6) and np.allclose(dc + ck, ahi, atol=1e-6)
+    P = np.zeros((tiny.L, orc.mlp_nparam()))
+    P[:, -1] = 0.01
+    g32 = [g.astype(np.float32) for g in tiny_grids]
+    got = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P, dc, dh, margin, core_k=ck)
+    ind, X = _in_domain(T32, dc, dh, pts)
+    loc = X * dh[None, :, None, :] + dc[None, :, None, :]
+    proj = np.clip(loc, (dc - ck)[None, :, None, :], (dc + ck)[None, :, None, :])
+    est = 0.01 + np.linalg.norm(loc - proj, axis=-1)
+    each = orc.query_f32_each(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts).astype(np.float64)
+    if margin > 0:
+        est = np.where((est < margin) & np.isfinite(each), each, est)
+    want = np.where(ind, est, np.inf).min(-1)
+    assert np.max(np.abs(np.where(np.isfinite(want), got - want, 0))) < 1e-9
+    assert np.array_equal(np.isfinite(got), np.isfinite(want))
+    if margin > 0:
+        assert ((got < 0.01) & np.isfinite(got)).any()             # some minima come from the grid
