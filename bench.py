@@ -238,7 +238,7 @@ def extra_scenes(dev, steps: int, warmup: int):
     return out
 
 
-def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 50):
+def learned_variant(dev, steps: int, judge_waypoints: int = 50):
     """The learned form on the 500 x 100,000 x 7 workload (64^3 grids): per-link
     networks trained on the GPU (untimed), then the grid-only query and the
     network-plus-fallback query timed on the same inputs, and the learned
@@ -250,20 +250,20 @@ def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 50):
     from paper_2309_12543_amd import learned, lsdf
 
     w = synth.make_workload("learned")
-    log(f"learned variant: C={w.C} M={w.M} L={w.L}, training {epochs} epochs")
+    log(f"learned variant: C={w.C} M={w.M} L={w.L}, training with the library's recipe")
     gs = lsdf.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device=dev)
     cen, half = synth.mlp_domain(w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64))
+    core = synth.mlp_core(w.grid_lo, w.grid_hi)
     n = 1 << 20
     S = torch.as_tensor(np.stack([synth.mlp_samples(m, w.grid_lo[i], w.grid_hi[i], n, synth.BASE_SEED + 4 + i)
                                   for i, m in enumerate(w.robot.links)]).astype(np.float32), device=dev)
     t0 = time.perf_counter()
     labels = learned.labels_for_samples(w.robot.links, gs, S)
     params = torch.as_tensor(synth.mlp_init(w.L, synth.BASE_SEED + 5).astype(np.float32), device=dev)
-    hist = learned.train(params, (cen, half), S, labels, epochs=epochs, batch=4096, lr=3e-3, lr_final=3e-5,
-                         log_every=max(1, epochs // 4), log=log)
+    hist = learned.fit(params, (cen, half, core), S, labels, log_every=300, log=log)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    doms = lsdf.make_domains(cen, half)
+    doms = lsdf.make_domains(cen, half, core)
     q = torch.as_tensor(w.q, dtype=torch.float32, device=dev)
     pts = torch.as_tensor(w.points, dtype=torch.float32, device=dev)
     T = lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T)
@@ -306,7 +306,8 @@ def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 50):
                 "p99_mm": round(float(np.percentile(e, 99)), 3)} if e.size else None
     return {
         "workload": f"{w.name}: {w.C} waypoints x {w.M} points x {w.L} links, 64^3 FP32 grids, "
-                    f"3-128-128-128-1 SiLU network per link (bf16 MFMA, FP32 accumulate), fallback below 5 cm",
+                    f"3-128-128-128-1 SiLU network per link (bf16 MFMA, FP32 accumulate) plus the distance to the "
+                    f"link's core box, fallback below 5 cm",
         "grid_ms_per_batch": round(grid_ms, 4),
         "mlp_ms_per_batch": round(mlp_ms, 3),
         "grid_gq_s": round(pairs / (grid_ms / 1e3) / 1e9, 2),
@@ -330,17 +331,21 @@ def learned_variant(dev, epochs: int, steps: int, judge_waypoints: int = 50):
         "grid_inf_waypoints": int(np.sum(~np.isfinite(d_grid))),
         "mlp_inf_waypoints": int(np.sum(~np.isfinite(d_mlp))),
         "train_s": round(train_s, 1),
-        "train_epochs": epochs,
+        "train_recipe": {"batch": learned.BATCH, "epochs": learned.EPOCHS, "lr": [learned.LR, learned.LR_FINAL],
+                         "mining_rounds": [{"lr": lr, "epochs": e} for lr, e in learned.MINE_ROUNDS],
+                         "mined_fraction": learned.MINE_FRACTION, "mined_repeat": learned.MINE_REPEAT,
+                         "epochs_total": int(len(hist))},
         "train_samples_per_link": n,
         "final_train_l1_mm": [round(1e3 * float(x), 2) for x in hist[-1]],
-        **learned_pair_stats(w, T, pts, params, cen, half, margin=0.05),
+        **learned_pair_stats(w, T, pts, params, cen, half, core, margin=0.05),
     }
 
 
-def learned_pair_stats(w, T, pts, params, cen, half, margin: float, sample: int = 1 << 20, seed: int = 7):
+def learned_pair_stats(w, T, pts, params, cen, half, core, margin: float, sample: int = 1 << 20, seed: int = 7):
     """On a seeded sample of (waypoint, point) pairs per link: the fraction
-    inside the network's domain, and among those the fraction whose network
-    value falls below the margin (the pairs that take the exact grid value)."""
+    inside the network's domain, and among those the fraction whose estimate
+    falls below the margin (the pairs that take the exact grid value when
+    their point is in the grid box)."""
     import torch
 
     from paper_2309_12543_amd import lsdf
@@ -360,7 +365,7 @@ def learned_pair_stats(w, T, pts, params, cen, half, margin: float, sample: int 
         lpi = lp[inside].contiguous()
         n_dom += int(lpi.shape[0])
         if lpi.shape[0]:
-            m = lsdf.mlp_eval(params[i].contiguous(), (cen[i:i + 1], half[i:i + 1]), lpi)
+            m = lsdf.mlp_eval(params[i].contiguous(), (cen[i:i + 1], half[i:i + 1], core[i:i + 1]), lpi)
             n_fb += int((m < margin).sum().item())
     return {"pair_sample_per_link": sample,
             "in_domain_pair_fraction": round(n_dom / (sample * w.L), 4),
@@ -660,8 +665,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="paper")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--learned-epochs", type=int, default=400,
-                    help="training epochs of the learned variant (0 skips the learned variant)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned variant (about 90 s of training)")
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--no-precision", action="store_true", help="skip the 128^3 bf16/fp16 storage variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-trajectory batched variant")
@@ -699,7 +703,7 @@ def main():
         return
     lsdf.load_library()
     if args.only:
-        only = {"learned": lambda: learned_variant(dev, args.learned_epochs, args.learned_steps),
+        only = {"learned": lambda: learned_variant(dev, args.learned_steps),
                 "scenes": lambda: extra_scenes(dev, 50, 5),
                 "precision": lambda: precision_variant(dev, 50),
                 "batched": lambda: batched_variant(dev, 20, 3),
@@ -886,8 +890,8 @@ def main():
         "roof_corner_tb_per_s_7mb": roof["grids_7mb"]["corner_tb_per_s"]}
     if not args.no_extra_scenes:
         rec["extra_scenes"] = extra_scenes(dev, 50, 5)
-    if args.learned_epochs > 0:
-        rec["learned"] = learned_variant(dev, args.learned_epochs, args.learned_steps)
+    if not args.no_learned:
+        rec["learned"] = learned_variant(dev, args.learned_steps)
     if not args.no_precision:
         rec["precision"] = precision_variant(dev, 50)
     if not args.no_batched:

@@ -374,9 +374,12 @@ int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* tris, int
 /* ---- learned per-link SDF surrogate ---------------------------------------
  * An extension of the method (not in the paper): per link, a small network
  * m(x) = w4 . h3 + b4, h_k = SiLU(W_k h_{k-1} + b_k), widths 3 -> 128 -> 128
- * -> 128 -> 1, SiLU(z) = z / (1 + exp(-z)), maps a link-frame point
- * normalised to the link's domain to an estimate of the link's signed
- * distance.  It answers queries beyond the grid box (the far field); the
+ * -> 128 -> 1, SiLU(z) = z / (1 + exp(-z)), maps a link-frame point l
+ * normalised to the link's domain to the remainder of the link's signed
+ * distance over E(l), the distance from l to the link's core box (its mesh's
+ * bounding box); the estimate is m + E.  E carries the distance's growth far
+ * from the link, so the network only fits a bounded, slowly varying
+ * remainder.  It answers queries beyond the grid box (the far field); the
  * grid stays the answer for every pair whose estimate is below a safety
  * margin, and the judge of the network's error.  The paper's own network
  * (Sec. III-B-1) is a different one (it approximates the grid transform);
@@ -392,21 +395,28 @@ int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* tris, int
 #define LSDF_MLP_PARAMS 33665
 
 /* Normalisation of a link's network input: xhat = (x_link - centre) / half;
- * the domain is |xhat_a| <= 1 on every axis. */
+ * the domain is |xhat_a| <= 1 on every axis.  The core box is
+ * |x_link - centre| <= core_half on every axis; its distance
+ * E = || max(|x_link - centre| - core_half, 0) || (FP32: u = x_link - centre,
+ * q = max(|u| - core_half, 0), E = sqrt(fma(qx, qx, fma(qy, qy, qz * qz))),
+ * correctly rounded) is added to the network's output. */
 typedef struct lsdf_mlp_domain {
     float centre[3];
-    float half[3];     /* each > 0 */
+    float half[3];       /* each > 0 */
+    float core_half[3];  /* each >= 0 */
 } lsdf_mlp_domain;
 
-/* Network outputs at N link-frame points of one link.
+/* The surrogate's estimates (network + core distance) at N link-frame points
+ * of one link.
  *   params  device float [LSDF_MLP_PARAMS]; domain host; points device [N][3];
  *   out     device float [N] (evaluated also outside the domain). */
 int lsdf_mlp_eval(const float* params, const lsdf_mlp_domain* domain, const float* points, int64_t N,
                   float* out, void* stream);
 
 /* Clearance with the learned surrogate: as lsdf_query_min_distance, but the
- * value of pair (c, i, j) is m = the network of link i at the point if the
- * point lies in link i's domain (the pair is skipped otherwise), replaced by
+ * value of pair (c, i, j) is m = the estimate of link i at the point (network
+ * + core distance) if the point lies in link i's domain (the pair is skipped
+ * otherwise), replaced by
  * the grid value when m < margin (strict) and the point lies in link i's grid
  * box.  A point outside the box keeps m whatever its value, since the grid
  * has no value there (when the box pads the link's bounding box by at least
@@ -424,7 +434,8 @@ int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t L, const
 /* Training.  For each link i, B samples are taken from that link's N
  * samples (link-frame points [L][N][3] with labels [L][N]) through
  * batch_index [L][B] (NULL = the first B), and the mean absolute error of
- * the network over them is differentiated (Sec. IV-B trains with an L1 loss).
+ * the estimate (network + core distance) over them is differentiated
+ * (Sec. IV-B trains with an L1 loss).
  *   lsdf_mlp_loss_grad: loss_out [L] (or NULL), grad_out [L][LSDF_MLP_PARAMS]
  *   lsdf_mlp_train_step: the same, then one Adam step (Kingma & Ba) on
  *     params with moments adam_m, adam_v (FP32, same shape, zero at t = 1),

@@ -25,6 +25,7 @@ constexpr int kQueryWaves = kQueryBlock / 64;
 struct Domain {
     float cen[3];
     float inv[3];    // 1 / half
+    float core[3];   // half extents of the core box
 };
 
 __device__ inline float wave_min(float v) {
@@ -63,12 +64,17 @@ __global__ __launch_bounds__(kBlock) void mlp_eval_kernel(EvalArgs p) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int64_t t = (int64_t)blockIdx.x * kWaves + wave; t < p.tiles; t += (int64_t)gridDim.x * kWaves) {
-        float xh[NT][3];
+        float xh[NT][3], e[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int64_t j = min(t * TILE + 16 * nt + (lane & 15), p.N - 1);
+            float u[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) xh[nt][a] = (p.points[3 * j + a] - p.d.cen[a]) * p.d.inv[a];
+            for (int a = 0; a < 3; ++a) {
+                u[a] = p.points[3 * j + a] - p.d.cen[a];
+                xh[nt][a] = u[a] * p.d.inv[a];
+            }
+            e[nt] = core_distance(u[0], u[1], u[2], p.d.core);
         }
         float m[NT];
         forward_tile<NT, false>(sW2, sW3, &sp, xh, m, ForwardTrace{});
@@ -76,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void mlp_eval_kernel(EvalArgs p) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int64_t j = t * TILE + 16 * nt + lane;
-                if (j < p.N) p.out[j] = m[nt];
+                if (j < p.N) p.out[j] = m[nt] + e[nt];
             }
         }
     }
@@ -146,7 +152,7 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
                 tr[r] = T[4 * r + 3];
             }
         }
-        float xh[NT][3], px[NT][3];
+        float xh[NT][3], px[NT][3], e[NT];
         bool indom[NT];
         bool any = false;
 #pragma unroll
@@ -159,13 +165,15 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
             px[nt][0] = p.points[3 * jj + 0];
             px[nt][1] = p.points[3 * jj + 1];
             px[nt][2] = p.points[3 * jj + 2];
-            float mx = 0.0f;
+            float mx = 0.0f, u[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const float l = fmaf(R[a], dx, fmaf(R[3 + a], dy, R[6 + a] * dz));   // (R^T d)_a
-                xh[nt][a] = (l - dm.cen[a]) * dm.inv[a];
+                u[a] = l - dm.cen[a];
+                xh[nt][a] = u[a] * dm.inv[a];
                 mx = fmaxf(mx, fabsf(xh[nt][a]));
             }
+            e[nt] = core_distance(u[0], u[1], u[2], dm.core);
             indom[nt] = (j < p.M) && (mx <= 1.0f);
             any |= indom[nt];
         }
@@ -179,8 +187,9 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
                 // below the margin the grid's value replaces the estimate; a
                 // point outside the grid box keeps the estimate, since the
                 // grid has no value there
-                float v = m[nt];
-                if (m[nt] < p.margin) {
+                const float est = m[nt] + e[nt];
+                float v = est;
+                if (est < p.margin) {
                     const float g = sample_or_inf<CUBIC, DT>(G, lg, gm, px[nt][0], px[nt][1], px[nt][2]);
                     if (g < INFINITY) v = g;
                 }
@@ -239,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void train_forward_kernel(TrainArgs p) {
     const int tt = blockIdx.x * kWaves + wave;          // tile of this wave
     const int64_t B = p.B;
     const int64_t lB = (int64_t)l * B;
-    float xh[NT_TRAIN][3];
+    float xh[NT_TRAIN][3], e[NT_TRAIN];
     int64_t idx[NT_TRAIN];
 #pragma unroll
     for (int nt = 0; nt < NT_TRAIN; ++nt) {
@@ -248,8 +257,13 @@ __global__ __launch_bounds__(kBlock) void train_forward_kernel(TrainArgs p) {
         k = min(max(k, (int64_t)0), p.N - 1);          // a bad index reads a valid sample
         idx[nt] = (int64_t)l * p.N + k;
         const Domain& d = p.dom[l];
+        float u[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) xh[nt][a] = (p.samples[3 * idx[nt] + a] - d.cen[a]) * d.inv[a];
+        for (int a = 0; a < 3; ++a) {
+            u[a] = p.samples[3 * idx[nt] + a] - d.cen[a];
+            xh[nt][a] = u[a] * d.inv[a];
+        }
+        e[nt] = core_distance(u[0], u[1], u[2], d.core);
         if (lane < 16) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) p.w.xh[(lB + s) * 3 + a] = xh[nt][a];
@@ -265,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void train_forward_kernel(TrainArgs p) {
 #pragma unroll
         for (int nt = 0; nt < NT_TRAIN; ++nt) {
             const int64_t s = (int64_t)tt * TILE_TRAIN + 16 * nt + lane;
-            const float r = m[nt] - p.labels[idx[nt]];
+            const float r = (m[nt] + e[nt]) - p.labels[idx[nt]];
             p.w.dm[lB + s] = (r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f)) / (float)B;
             absr += fabsf(r);
         }
@@ -537,8 +551,11 @@ int make_domain(const lsdf_mlp_domain& d, int index, Domain* out) {
     for (int a = 0; a < 3; ++a) {
         if (!std::isfinite(d.centre[a]) || !std::isfinite(d.half[a]) || !(d.half[a] > 0.0f))
             return fail(LSDF_E_INVALID_ARG, "mlp domain %d: centre must be finite and half > 0", index);
+        if (!std::isfinite(d.core_half[a]) || !(d.core_half[a] >= 0.0f))
+            return fail(LSDF_E_INVALID_ARG, "mlp domain %d: core_half must be finite and >= 0", index);
         out->cen[a] = d.centre[a];
         out->inv[a] = (float)(1.0 / (double)d.half[a]);
+        out->core[a] = d.core_half[a];
     }
     return LSDF_OK;
 }

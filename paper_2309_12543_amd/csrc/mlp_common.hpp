@@ -4,6 +4,8 @@
 // widths 3 -> 128 -> 128 -> 128 -> 1, SiLU(z) = z / (1 + exp(-z)), input the
 // link-frame point normalised to the link's domain.  FP32 master parameters,
 // [W1 128x3 | b1 | W2 128x128 | b2 | W3 128x128 | b3 | w4 | b4] (33665).
+// The estimate of the link's signed distance is m plus the distance from the
+// point to the link's core box (its mesh's bounding box, core_distance).
 //
 // Precision: W1, W2, W3, w4 are used as bfloat16 (round to nearest even);
 // the input layer runs on the VALU in FP32 (bfloat16 coordinates would be
@@ -67,6 +69,16 @@ __device__ inline int perm_unit(int s, int kappa) {
 }
 
 __device__ inline float bf16_round(float x) { return (float)(__bf16)x; }
+
+// Core term of the estimate: the distance from a link-frame point to the
+// link's core box, given u = l - centre and the box's half extents k:
+// || max(|u| - k, 0) ||, the square root correctly rounded.
+__device__ inline float core_distance(float ux, float uy, float uz, const float (&k)[3]) {
+    const float qx = fmaxf(fabsf(ux) - k[0], 0.0f);
+    const float qy = fmaxf(fabsf(uy) - k[1], 0.0f);
+    const float qz = fmaxf(fabsf(uz) - k[2], 0.0f);
+    return __builtin_sqrtf(fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+}
 
 __device__ inline float silu(float z) {
     const float e = __builtin_amdgcn_exp2f(-z * 1.44269504088896340736f);

@@ -156,11 +156,17 @@ def test_mlp_argument_errors(lib):
     assert lib.lsdf_mlp_train_workspace_size(7, 4096, ct.byref(n)) == 0 and n.value > 7 * 4096 * 128 * 4
     assert lib.lsdf_mlp_train_workspace_size(7, 1000, ct.byref(n)) == B.LSDF_E_SHAPE     # not a multiple of 512
     assert lib.lsdf_mlp_train_workspace_size(0, 4096, ct.byref(n)) == B.LSDF_E_SHAPE
-    dom = B.make_domains([[0, 0, 0], [0, 0, 0]], [[1, 1, 1], [1, 1, 1]])
-    bad = B.make_domains([[0, 0, 0]], [[1, 0, 1]])
-    # lsdf_mlp_eval: domain NULL, half <= 0, N < 0, N = 0 no-op
+    dom = B.make_domains([[0, 0, 0], [0, 0, 0]], [[1, 1, 1], [1, 1, 1]], [[0.2, 0.1, 0], [0, 0, 0]])
+    bad = B.make_domains([[0, 0, 0]], [[1, 0, 1]], [[0, 0, 0]])
+    bad_core = B.make_domains([[0, 0, 0]], [[1, 1, 1]], [[0, -0.1, 0]])
+    nan_core = B.make_domains([[0, 0, 0]], [[1, 1, 1]], [[0, float("nan"), 0]])
+    with pytest.raises(ValueError):
+        B.make_domains([[0, 0, 0]], [[1, 1, 1]], [[0, 0, 0], [0, 0, 0]])         # shapes differ
+    # lsdf_mlp_eval: domain NULL, half <= 0, core_half < 0 or NaN, N < 0, N = 0 no-op
     assert lib.lsdf_mlp_eval(FAKE, None, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG
     assert lib.lsdf_mlp_eval(FAKE, bad, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG
+    assert lib.lsdf_mlp_eval(FAKE, bad_core, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG
+    assert lib.lsdf_mlp_eval(FAKE, nan_core, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG
     assert lib.lsdf_mlp_eval(FAKE, dom, FAKE, -1, FAKE, None) == B.LSDF_E_SHAPE
     assert lib.lsdf_mlp_eval(FAKE, dom, FAKE, 0, FAKE, None) == B.LSDF_OK
     # training: B not a multiple of 512, NULL moments, t = 0, workspace too small or misaligned

@@ -6,8 +6,10 @@ grown by a 5 cm pad; the paper sizes this range in Sec. III-A and IV-C), and
 a point outside every box contributes nothing, so a link with no point in its
 box reports +inf ("at least the pad away").  The network's domain reaches
 1 m past the box, so the learned query gives a finite clearance there.  The
-network is trained on the GPU by the library's own kernels (labels, forward,
-backward, Adam), and judged against the oracle's exact field: the grid value
+estimate is the network plus the distance to the link's core box (its mesh's
+bounding box).  The networks are trained on the GPU by the library's own
+kernels (labels, forward, backward, Adam) with the library's recipe
+(learned.fit), and judged against the oracle's exact field: the grid value
 inside the box, the brute-force mesh distance outside it (orc_judge_min).
 
 The base link (link 0) sits still next to the table, so its clearance is
@@ -23,7 +25,6 @@ import synth
 pytestmark = pytest.mark.gpu
 
 MARGIN = 0.05
-EPOCHS = 200
 SAMPLES = 1 << 20
 
 
@@ -41,25 +42,25 @@ def trained():
     dev = torch.device("cuda")
     gs = lsdf.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device=dev)
     cen, half = synth.mlp_domain(w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64))
+    core = synth.mlp_core(w.grid_lo, w.grid_hi)
     S = torch.as_tensor(np.stack([synth.mlp_samples(m, w.grid_lo[i], w.grid_hi[i], SAMPLES, synth.BASE_SEED + 4 + i)
                                   for i, m in enumerate(w.robot.links)]).astype(np.float32), device=dev)
-    say(f"training 7 networks, {SAMPLES} samples each, {EPOCHS} epochs")
+    say(f"training 7 networks on {SAMPLES} samples each with the library's recipe")
     labels = learned.labels_for_samples(w.robot.links, gs, S)
     params = torch.as_tensor(synth.mlp_init(w.L, synth.BASE_SEED + 5).astype(np.float32), device=dev)
-    hist = learned.train(params, (cen, half), S, labels, epochs=EPOCHS, batch=4096, lr=3e-3, lr_final=3e-5,
-                         log_every=EPOCHS // 2, log=say)
+    hist = learned.fit(params, (cen, half, core), S, labels, log_every=300, log=say)
     torch.cuda.synchronize()
-    return w, gs, params, cen, half, hist
+    return w, gs, params, cen, half, core, hist
 
 
 def test_trained_network_answers_beyond_the_grid_box(orc, trained):
     from paper_2309_12543_amd import lsdf
-    w, gs, params, cen, half, hist = trained
+    w, gs, params, cen, half, core, hist = trained
     dev = params.device
     T = lsdf.fk_batch(w.robot.dh, torch.as_tensor(w.q, dtype=torch.float32, device=dev), base_T=w.robot.base_T)
     pts = torch.as_tensor(w.points, dtype=torch.float32, device=dev)
     lg = lsdf.query_min_distance(T, gs, pts, link_dist=True)[2].cpu().numpy().astype(np.float64)
-    lm = lsdf.query_min_distance_mlp(T, gs, params, (cen, half), pts, margin=MARGIN,
+    lm = lsdf.query_min_distance_mlp(T, gs, params, (cen, half, core), pts, margin=MARGIN,
                                      link_dist=True)[2].cpu().numpy().astype(np.float64)
     sel = np.arange(0, w.C, 5)
     say(f"judging {len(sel)} waypoints with the oracle")
@@ -90,7 +91,7 @@ def test_trained_network_answers_beyond_the_grid_box(orc, trained):
     en = np.abs(m[near] - j[near]) * 1e3
     say(f"{near.sum()} link minima inside the capture range: learned vs exact max {en.max():.2f} mm, "
         f"mean {en.mean():.3f} mm; grid vs exact max {np.abs(g[near] - j[near]).max() * 1e3:.3f} mm")
-    # bounds a trained network of this recipe stays within (the figures above are the record)
-    assert err_far.max() <= 10.0 and err_far.mean() <= 3.0
-    assert ew.max() <= 10.0
-    assert hist[-1].max() <= 3e-3                     # final mean L1 per link below 3 mm
+    # the library's recipe meets the 1 mm target on these minima, beyond the
+    # grid box and inside it
+    assert err_far.max() <= 1.0 and ew.max() <= 1.0 and en.max() <= 1.0
+    assert hist[-1].max() <= 1e-3                     # final mean L1 per link below 1 mm

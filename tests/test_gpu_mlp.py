@@ -43,8 +43,11 @@ def params_f32(L, seed, scale=2.0):
 
 
 def domains_of(w):
+    """Network domains and core boxes of a workload's links, as the GPU is
+    given them (float32): (centre, half, core_half)."""
     cen, half = synth.mlp_domain(w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64))
-    return cen.astype(np.float32), half.astype(np.float32)
+    core = synth.mlp_core(w.grid_lo, w.grid_hi)
+    return cen.astype(np.float32), half.astype(np.float32), core.astype(np.float32)
 
 
 def normalise(points, cen, half):
@@ -54,41 +57,54 @@ def normalise(points, cen, half):
 
 
 def test_mlp_eval_matches_twin(B, orc, tiny):
-    cen, half = domains_of(tiny)
+    """Estimates (network + core distance) over the whole domain against the
+    oracle's bfloat16 twin and its double network, each plus the oracle's
+    core distance in double."""
+    cen, half, core = domains_of(tiny)
     P = params_f32(1, 0)[0]
     rng = np.random.default_rng(40)
     pts = rng.uniform(cen[2] - half[2], cen[2] + half[2], size=(3001, 3)).astype(np.float32)
     say("mlp_eval N=3001")
-    got = B.mlp_eval(dev(P), (cen[2:3], half[2:3]), dev(pts)).cpu().numpy().astype(np.float64)
+    got = B.mlp_eval(dev(P), (cen[2:3], half[2:3], core[2:3]), dev(pts)).cpu().numpy().astype(np.float64)
     torch.cuda.synchronize()
-    X = normalise(pts, cen[2], half[2])
-    twin = orc.mlp_forward(P.astype(np.float64), X, bf16=True)
-    full = orc.mlp_forward(P.astype(np.float64), X, bf16=False)
-    scale = max(1.0, np.abs(twin).max())
+    p64 = pts.astype(np.float64)
+    twin = orc.mlp_value(P.astype(np.float64), p64, cen[2], half[2], core[2], bf16=True)
+    full = orc.mlp_value(P.astype(np.float64), p64, cen[2], half[2], core[2], bf16=False)
+    E = orc.mlp_value(np.zeros_like(P, dtype=np.float64), p64, cen[2], half[2], core[2])
+    assert (E > 0.3).mean() > 0.5                                   # the core term is exercised
+    scale = max(1.0, np.abs(twin - E).max())
     e_twin, e_full = np.abs(got - twin).max(), np.abs(got - full).max()
-    say(f"max |gpu - bf16 twin| = {e_twin:.3g}, max |gpu - double net| = {e_full:.3g}, output scale {scale:.3g}")
+    say(f"max |gpu - bf16 twin| = {e_twin:.3g}, max |gpu - double net| = {e_full:.3g}, network output scale "
+        f"{scale:.3g}, core distance up to {E.max():.3f} m")
     assert e_twin <= TOL_EVAL * scale
     assert e_full <= 5e-2 * scale
+    # the core term alone: a zero network gives the FP32 core distance
+    z = B.mlp_eval(dev(np.zeros_like(P)), (cen[2:3], half[2:3], core[2:3]), dev(pts)).cpu().numpy().astype(np.float64)
+    assert np.abs(z - E).max() <= 4e-7 * max(1.0, E.max())
 
 
 def test_mlp_loss_grad_matches_twin(B, orc, tiny):
-    cen, half = domains_of(tiny)
+    cen, half, core = domains_of(tiny)
     L, N, Bt = 2, 1536, 1024
     P = params_f32(L, 1)
     rng = np.random.default_rng(41)
     samples = np.stack([rng.uniform(cen[i] - half[i], cen[i] + half[i], size=(N, 3)) for i in range(L)]).astype(np.float32)
     X = [normalise(samples[i], cen[i], half[i]) for i in range(L)]
-    # labels 0.3 away from the outputs, so that sign(m - y) is the same everywhere
-    labels = np.stack([orc.mlp_forward(P[i].astype(np.float64), X[i], bf16=True) + rng.choice([-0.3, 0.3], size=N)
-                       for i in range(L)]).astype(np.float32)
+    # the core distance of every sample (the oracle's, zero network)
+    E = [orc.mlp_value(np.zeros(P.shape[1]), samples[i].astype(np.float64), cen[i], half[i], core[i])
+         for i in range(L)]
+    # labels 0.3 away from the estimates, so that sign(m - y) is the same everywhere
+    labels = np.stack([orc.mlp_forward(P[i].astype(np.float64), X[i], bf16=True) + E[i]
+                       + rng.choice([-0.3, 0.3], size=N) for i in range(L)]).astype(np.float32)
     bidx = np.stack([rng.permutation(N)[:Bt] for _ in range(L)]).astype(np.int32)
     say(f"mlp_loss_grad L={L} N={N} B={Bt}")
-    loss, grad = B.mlp_loss_grad(dev(P), (cen[:L], half[:L]), dev(samples), dev(labels), Bt, dev(bidx, torch.int32))
+    loss, grad = B.mlp_loss_grad(dev(P), (cen[:L], half[:L], core[:L]), dev(samples), dev(labels), Bt,
+                                 dev(bidx, torch.int32))
     loss, grad = loss.cpu().numpy().astype(np.float64), grad.cpu().numpy().astype(np.float64)
     for i in range(L):
-        Xi, Yi = X[i][bidx[i]], labels[i][bidx[i]].astype(np.float64)
-        l_twin, g_twin = orc.mlp_loss_grad(P[i].astype(np.float64), Xi, Yi, bf16=True)
-        l_full, g_full = orc.mlp_loss_grad(P[i].astype(np.float64), Xi, Yi, bf16=False)
+        Xi, Yi, Ei = X[i][bidx[i]], labels[i][bidx[i]].astype(np.float64), E[i][bidx[i]]
+        l_twin, g_twin = orc.mlp_loss_grad(P[i].astype(np.float64), Xi, Yi, bf16=True, offset=Ei)
+        l_full, g_full = orc.mlp_loss_grad(P[i].astype(np.float64), Xi, Yi, bf16=False, offset=Ei)
         cos_t = g_twin @ grad[i] / np.linalg.norm(g_twin) / np.linalg.norm(grad[i])
         cos_f = g_full @ grad[i] / np.linalg.norm(g_full) / np.linalg.norm(grad[i])
         rel_t = np.abs(grad[i] - g_twin).max() / np.abs(g_twin).max()
@@ -100,7 +116,7 @@ def test_mlp_loss_grad_matches_twin(B, orc, tiny):
 
 
 def test_mlp_train_step_is_adam(B, orc, tiny):
-    cen, half = domains_of(tiny)
+    cen, half, core = domains_of(tiny)
     L, N, Bt = 2, 1024, 512
     P = params_f32(L, 2)
     rng = np.random.default_rng(42)
@@ -114,7 +130,7 @@ def test_mlp_train_step_is_adam(B, orc, tiny):
     for t in (1, 2):
         before = p.cpu().numpy().astype(np.float64)
         m64, v64 = m.cpu().numpy().astype(np.float64), v.cpu().numpy().astype(np.float64)
-        B.mlp_train_step(p, m, v, t, lr, (cen[:L], half[:L]), dev(samples), dev(labels), Bt, grad=grad)
+        B.mlp_train_step(p, m, v, t, lr, (cen[:L], half[:L], core[:L]), dev(samples), dev(labels), Bt, grad=grad)
         torch.cuda.synchronize()
         g = grad.cpu().numpy().astype(np.float64)
         want = before.copy()
@@ -186,7 +202,8 @@ def test_query_mlp_constant_network_matches_oracle(B, orc, tiny, tiny_grids, k, 
     the query clears its keys itself."""
     sel = np.arange(0, tiny.C, 5)
     T32 = _poses(orc, tiny, sel)
-    cen, half = domains_of(tiny)
+    cen, half, _ = domains_of(tiny)
+    core = half            # the core box fills the domain: every in-domain estimate is k exactly
     pts = tiny.points.astype(np.float32)
     g32 = [g.astype(np.float32) for g in tiny_grids]
     gs = _grid_set(B, tiny, tiny_grids)
@@ -195,11 +212,11 @@ def test_query_mlp_constant_network_matches_oracle(B, orc, tiny, tiny_grids, k, 
     C = len(sel)
     ws = torch.full((B.query_workspace_size(C, tiny.L, tiny.M),), 0xFF, dtype=torch.uint8, device="cuda")
     say(f"query_mlp constant network k={k} margin={margin} C={C} M={tiny.M}")
-    d, l, ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half), dev(pts), margin=margin,
+    d, l, ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half, core), dev(pts), margin=margin,
                                         link_dist=True, workspace=ws)
     ld = ld.cpu().numpy().astype(np.float64)
     want = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P.astype(np.float64), cen, half,
-                         margin)
+                         margin, core_k=core)
     # (c, i) whose result a pair in the domain's boundary band could change
     sure, maybe = _domain_bands(T32, cen, half, pts)
     inbox = np.isfinite(orc.query_f32_each(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts))
@@ -222,26 +239,41 @@ def test_query_mlp_constant_network_matches_oracle(B, orc, tiny, tiny_grids, k, 
         assert np.array_equal(ld[fin].astype(np.float32).view(np.uint32), plain[fin].view(np.uint32))
 
 
-def _shift_to_margin(orc, w, T32, pts, P, cen, half, margin, q=0.4, s=1.0):
+def _core_each(orc, w, T32, pts, cen, half, core):
+    """[C][L][M] core distance of every pair, the oracle's (a zero network's
+    estimates)."""
+    zero = np.zeros((T32.shape[1], orc.mlp_nparam()))
+    lo, hi, n = w.grid_lo[:T32.shape[1]], w.grid_hi[:T32.shape[1]], w.grid_n[:T32.shape[1]]
+    _, E, _ = orc.query_mlp(T32, lo, hi, n, [np.zeros(tuple(k[::-1]), np.float32) for k in n], pts, zero, cen, half,
+                            -np.inf, each=True, core_k=core)
+    return E
+
+
+def _shift_to_margin(orc, w, T32, pts, P, cen, half, core, margin, q=0.4, s=1.0):
     """Scale each link's output weights w4 by s and shift its output bias so
-    that the margin sits at quantile q of the twin network's values over the
-    pairs in that link's domain.  Returns the FP32 parameters (what the GPU
-    is given; the oracle reads the same values) and the per-pair tolerance
-    function: a GPU-twin difference comes from bfloat16 rounding flips inside
-    the network, so it scales with the output's distance from its bias."""
+    that the margin sits at quantile q of the twin network's outputs (the
+    estimates less the core distance) over the pairs in that link's domain:
+    pairs near the link (small core distance) then fall on both sides of the
+    margin, and so do some farther ones.  Returns the FP32
+    parameters (what the GPU is given; the oracle reads the same values) and
+    the per-pair tolerance function of the estimates em and core distances E:
+    a GPU-twin difference comes from bfloat16 rounding flips inside the
+    network, so it scales with the network output's distance from its bias
+    (the core distance differs only by FP32 rounding)."""
     P = P.copy()
     P[:, -129:-1] *= np.float32(s)
     _, em, _ = orc.query_mlp(T32, w.grid_lo, w.grid_hi, w.grid_n, [np.zeros(tuple(n[::-1]), np.float32)
                                                                     for n in w.grid_n],
-                             pts, P.astype(np.float64), cen, half, -np.inf, each=True)
+                             pts, P.astype(np.float64), cen, half, -np.inf, each=True, core_k=core)
+    net = em - _core_each(orc, w, T32, pts, cen, half, core)
     sure, _ = _domain_bands(T32, cen, half, pts)
     for i in range(w.L):
-        P[i, -1] += np.float32(margin - np.quantile(em[:, i][sure[:, i]], q))
+        P[i, -1] += np.float32(margin - np.quantile(net[:, i][sure[:, i]], q))
     P = P.astype(np.float32)
     b4 = P[:, -1].astype(np.float64)
 
-    def tol(em):
-        return TOL_EVAL * np.maximum(s, np.abs(em - b4.reshape((1, -1) + (1,) * (em.ndim - 2))))
+    def tol(em, E):
+        return TOL_EVAL * np.maximum(s, np.abs(em - E - b4.reshape((1, -1) + (1,) * (em.ndim - 2)))) + 1e-6
     return P, tol
 
 
@@ -275,7 +307,7 @@ def test_query_mlp_finite_margin_pairs_match_oracle(B, orc, tiny, tiny_grids):
     value far beyond the tolerance."""
     sel = np.arange(0, tiny.C, 5)
     T32 = _poses(orc, tiny, sel)
-    cen, half = domains_of(tiny)
+    cen, half, core = domains_of(tiny)
     g32 = [g.astype(np.float32) for g in tiny_grids]
     # the 100 points in the most grid boxes over these poses, and 60 others
     nbox = np.isfinite(orc.query_f32_each(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32,
@@ -284,9 +316,10 @@ def test_query_mlp_finite_margin_pairs_match_oracle(B, orc, tiny, tiny_grids):
     pts = tiny.points[np.concatenate([order[:100], order[-60:]])].astype(np.float32)
     gs = _grid_set(B, tiny, tiny_grids)
     margin = 0.05
-    P, tolf = _shift_to_margin(orc, tiny, T32, pts, params_f32(7, 7), cen, half, margin)
+    P, tolf = _shift_to_margin(orc, tiny, T32, pts, params_f32(7, 7), cen, half, core, margin, q=0.8, s=2.0)
     _, em, eg = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P.astype(np.float64), cen, half,
-                              margin, each=True)
+                              margin, each=True, core_k=core)
+    E = _core_each(orc, tiny, T32, pts, cen, half, core)
     sure, maybe = _domain_bands(T32, cen, half, pts)
     C, L, M = em.shape
     Tg, Pg = dev(T32), dev(P)
@@ -294,9 +327,9 @@ def test_query_mlp_finite_margin_pairs_match_oracle(B, orc, tiny, tiny_grids):
     say(f"query_mlp margin={margin}: {M} single-point calls, C={C}")
     got = np.empty((C, L, M))
     for j in range(M):
-        got[:, :, j] = B.query_min_distance_mlp(Tg, gs, Pg, (cen, half), dev(pts[j:j + 1]), margin=margin,
+        got[:, :, j] = B.query_min_distance_mlp(Tg, gs, Pg, (cen, half, core), dev(pts[j:j + 1]), margin=margin,
                                                 link_dist=True, workspace=ws)[2].cpu().numpy()
-    tol = tolf(em)
+    tol = tolf(em, E)
     fixed = sure & (np.abs(em - margin) > tol)
     inbox = np.isfinite(eg)
     grid_pairs = fixed & (em < margin) & inbox
@@ -335,19 +368,20 @@ def test_query_mlp_finite_margin_minima_match_oracle(B, orc, tiny, tiny_grids):
     lie within the oracle's per-pair intervals."""
     sel = np.arange(0, tiny.C, 5)
     T32 = _poses(orc, tiny, sel)
-    cen, half = domains_of(tiny)
+    cen, half, core = domains_of(tiny)
     pts = tiny.points.astype(np.float32)
     g32 = [g.astype(np.float32) for g in tiny_grids]
     gs = _grid_set(B, tiny, tiny_grids)
     margin = 0.05
-    P, tolf = _shift_to_margin(orc, tiny, T32, pts[:300], params_f32(7, 8), cen, half, margin, q=0.5, s=0.05)
+    P, tolf = _shift_to_margin(orc, tiny, T32, pts[:300], params_f32(7, 8), cen, half, core, margin, q=0.5, s=0.05)
     _, em, eg = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P.astype(np.float64), cen, half,
-                              margin, each=True)
+                              margin, each=True, core_k=core)
+    E = _core_each(orc, tiny, T32, pts, cen, half, core)
     sure, maybe = _domain_bands(T32, cen, half, pts)
     say(f"query_mlp margin={margin} C={len(sel)} M={tiny.M}")
-    ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half), dev(pts), margin=margin,
+    ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half, core), dev(pts), margin=margin,
                                   link_dist=True)[2].cpu().numpy().astype(np.float64)
-    tol = tolf(em)
+    tol = tolf(em, E)
     lo, hi = _pair_intervals(em, eg, sure, maybe, margin, tol)
     n_exact = _check_minima(ld, lo, hi, "tiny")
     n_net = int((np.isfinite(hi.min(-1)) & (lo.min(-1) < hi.min(-1))).sum())
@@ -362,24 +396,28 @@ def test_query_mlp_finite_margin_learned_scale_sampled(B, orc):
     sampled per-link minima against the oracle's per-pair intervals over all
     100,000 points of that link."""
     w = synth.make_workload("learned")
-    cen, half = domains_of(w)
+    cen, half, core = domains_of(w)
     g32 = [g.astype(np.float32) for g in orc.workload_grids(w)]
     gs = _grid_set(B, w, g32)                    # the oracle's grids on both sides
     T32 = orc.fk(w.robot.dh, w.q, w.robot.base_T).astype(np.float32)
     pts = w.points.astype(np.float32)
     margin = 0.05
     s = 0.05
-    P, _ = _shift_to_margin(orc, w, T32[::100], pts[::50], params_f32(7, 9), cen, half, margin, q=0.5, s=s)
+    P, tolf = _shift_to_margin(orc, w, T32[::100], pts[::50], params_f32(7, 9), cen, half, core, margin, q=0.5, s=s)
     say(f"query_mlp learned scale C={w.C} M={w.M} margin={margin}")
-    ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half), dev(pts), margin=margin,
+    ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half, core), dev(pts), margin=margin,
                                   link_dist=True)[2].cpu().numpy().astype(np.float64)
     n_exact = 0
     for c, i in [(0, 1), (123, 4), (250, 0), (377, 6), (499, 3)]:
         Tci = T32[c:c + 1, i:i + 1]
         _, em, eg = orc.query_mlp(Tci, w.grid_lo[i:i + 1], w.grid_hi[i:i + 1], w.grid_n[i:i + 1], [g32[i]], pts,
-                                  P[i:i + 1].astype(np.float64), cen[i:i + 1], half[i:i + 1], margin, each=True)
+                                  P[i:i + 1].astype(np.float64), cen[i:i + 1], half[i:i + 1], margin, each=True,
+                                  core_k=core[i:i + 1])
+        _, E, _ = orc.query_mlp(Tci, w.grid_lo[i:i + 1], w.grid_hi[i:i + 1], w.grid_n[i:i + 1], [g32[i]], pts,
+                                np.zeros((1, P.shape[1])), cen[i:i + 1], half[i:i + 1], -np.inf, each=True,
+                                core_k=core[i:i + 1])
         sure, maybe = _domain_bands(Tci, cen[i:i + 1], half[i:i + 1], pts)
-        tol = TOL_EVAL * np.maximum(s, np.abs(em - np.float64(P[i, -1])))
+        tol = TOL_EVAL * np.maximum(s, np.abs(em - E - np.float64(P[i, -1]))) + 1e-6
         lo, hi = _pair_intervals(em, eg, sure, maybe, margin, tol)
         below = (em < margin) & sure
         say(f"  c={c} link={i}: {sure.sum()} in-domain pairs, {(below & np.isfinite(eg)).sum()} take the grid, "
@@ -390,9 +428,10 @@ def test_query_mlp_finite_margin_learned_scale_sampled(B, orc):
 
 
 def test_query_mlp_no_fallback_matches_twin(B, orc, tiny, tiny_grids):
-    """With margin -inf every in-domain pair takes the network value: the
-    per-link minima must match the twin network's over the same pairs."""
-    cen, half = domains_of(tiny)
+    """With margin -inf every in-domain pair takes the estimate: the per-link
+    minima must match the twin's estimates (network + core distance) over the
+    same pairs."""
+    cen, half, core = domains_of(tiny)
     gs = B.GridSet(tiny.grid_lo, tiny.grid_hi, tiny.grid_n, device="cuda")
     for k, g in enumerate(tiny_grids):
         gs.set_grid(k, g.astype(np.float32))
@@ -401,7 +440,7 @@ def test_query_mlp_no_fallback_matches_twin(B, orc, tiny, tiny_grids):
     pts = tiny.points[:M].astype(np.float32)
     P = params_f32(7, 4)
     say(f"query_mlp margin=-inf C={C} M={M}")
-    d, l, ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half), dev(pts), margin=float("-inf"),
+    d, l, ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half, core), dev(pts), margin=float("-inf"),
                                         link_dist=True)
     ld = ld.cpu().numpy().astype(np.float64)
     for c in range(C):
@@ -410,7 +449,8 @@ def test_query_mlp_no_fallback_matches_twin(B, orc, tiny, tiny_grids):
             loc = (pts.astype(np.float64) - t) @ R
             X = (loc - cen[i]) / half[i]
             ind = np.all(np.abs(X) <= 1.0, axis=1)
-            want = orc.mlp_forward(P[i].astype(np.float64), X[ind], bf16=True).min() if ind.any() else np.inf
+            want = orc.mlp_value(P[i].astype(np.float64), loc[ind], cen[i], half[i], core[i], bf16=True).min() \
+                if ind.any() else np.inf
             assert abs(ld[c, i] - want) <= TOL_EVAL * max(1.0, abs(want)), (c, i, ld[c, i], want)
 
 
@@ -420,21 +460,23 @@ def test_query_mlp_learned_scale_sampled(B, orc):
     in-domain pair takes the network value): sampled per-link minima against
     the twin network over all of that link's in-domain points."""
     w = synth.make_workload("learned")
-    cen, half = domains_of(w)
+    cen, half, core = domains_of(w)
     gs = B.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device="cuda")
     T32 = orc.fk(w.robot.dh, w.q, w.robot.base_T).astype(np.float32)
     pts = w.points.astype(np.float32)
     P = params_f32(7, 6)
     say(f"query_mlp learned scale C={w.C} M={w.M} margin=-inf")
-    d, l, ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half), dev(pts), margin=float("-inf"),
+    d, l, ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half, core), dev(pts), margin=float("-inf"),
                                         link_dist=True)
     ld = ld.cpu().numpy().astype(np.float64)
     assert np.isfinite(ld).mean() > 0.5
     for c, i in [(0, 1), (123, 4), (377, 6), (499, 3)]:
         R, t = T32[c, i, :, :3].astype(np.float64), T32[c, i, :, 3].astype(np.float64)
-        X = ((pts.astype(np.float64) - t) @ R - cen[i]) / half[i]
+        loc = (pts.astype(np.float64) - t) @ R
+        X = (loc - cen[i]) / half[i]
         ind = np.all(np.abs(X) <= 1.0, axis=1)
-        want = orc.mlp_forward(P[i].astype(np.float64), X[ind], bf16=True).min() if ind.any() else np.inf
+        want = orc.mlp_value(P[i].astype(np.float64), loc[ind], cen[i], half[i], core[i], bf16=True).min() \
+            if ind.any() else np.inf
         say(f"  c={c} link={i}: {ind.sum()} in-domain points, gpu {ld[c, i]:.6g} twin {want:.6g}")
         assert abs(ld[c, i] - want) <= TOL_EVAL * max(1.0, abs(want)), (c, i, ld[c, i], want)
     # per-waypoint results are the minima over links (lowest link on ties)
