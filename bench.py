@@ -238,9 +238,11 @@ def extra_scenes(dev, steps: int, warmup: int):
     return out
 
 
-def learned_variant(dev, steps: int, judge_waypoints: int = 50):
+def learned_variant(dev, steps: int, epochs=None, judge_waypoints: int = 50):
     """The learned form on the 500 x 100,000 x 7 workload (64^3 grids): per-link
-    networks trained on the GPU (untimed), then the grid-only query and the
+    networks trained on the GPU (untimed; the library's recipe, or with
+    ``epochs`` only that many epochs of its first phase, for profiling runs),
+    then the grid-only query and the
     network-plus-fallback query timed on the same inputs, and the learned
     clearances judged against the oracle's exact minimum on sampled waypoints."""
     import torch
@@ -250,7 +252,8 @@ def learned_variant(dev, steps: int, judge_waypoints: int = 50):
     from paper_2309_12543_amd import learned, lsdf
 
     w = synth.make_workload("learned")
-    log(f"learned variant: C={w.C} M={w.M} L={w.L}, training with the library's recipe")
+    log(f"learned variant: C={w.C} M={w.M} L={w.L}, training "
+        + ("with the library's recipe" if epochs is None else f"{epochs} epochs (profiling run)"))
     gs = lsdf.build_robot_grids(w.robot.links, w.grid_lo, w.grid_hi, w.grid_n, device=dev)
     cen, half = synth.mlp_domain(w.grid_lo.astype(np.float64), w.grid_hi.astype(np.float64))
     core = synth.mlp_core(w.grid_lo, w.grid_hi)
@@ -260,7 +263,11 @@ def learned_variant(dev, steps: int, judge_waypoints: int = 50):
     t0 = time.perf_counter()
     labels = learned.labels_for_samples(w.robot.links, gs, S)
     params = torch.as_tensor(synth.mlp_init(w.L, synth.BASE_SEED + 5).astype(np.float32), device=dev)
-    hist = learned.fit(params, (cen, half, core), S, labels, log_every=300, log=log)
+    if epochs is None:
+        hist = learned.fit(params, (cen, half, core), S, labels, log_every=300, log=log)
+    else:
+        hist = learned.train(params, (cen, half, core), S, labels, epochs=epochs, batch=learned.BATCH, lr=learned.LR,
+                             lr_final=learned.LR_FINAL)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     doms = lsdf.make_domains(cen, half, core)
@@ -331,10 +338,11 @@ def learned_variant(dev, steps: int, judge_waypoints: int = 50):
         "grid_inf_waypoints": int(np.sum(~np.isfinite(d_grid))),
         "mlp_inf_waypoints": int(np.sum(~np.isfinite(d_mlp))),
         "train_s": round(train_s, 1),
-        "train_recipe": {"batch": learned.BATCH, "epochs": learned.EPOCHS, "lr": [learned.LR, learned.LR_FINAL],
-                         "mining_rounds": [{"lr": lr, "epochs": e} for lr, e in learned.MINE_ROUNDS],
-                         "mined_fraction": learned.MINE_FRACTION, "mined_repeat": learned.MINE_REPEAT,
-                         "epochs_total": int(len(hist))},
+        "train_recipe": ({"batch": learned.BATCH, "epochs": learned.EPOCHS, "lr": [learned.LR, learned.LR_FINAL],
+                          "mining_rounds": [{"lr": lr, "epochs": e} for lr, e in learned.MINE_ROUNDS],
+                          "mined_fraction": learned.MINE_FRACTION, "mined_repeat": learned.MINE_REPEAT,
+                          "epochs_total": int(len(hist))} if epochs is None else
+                         f"profiling run: {epochs} epochs of the first phase only (accuracy figures not the recipe's)"),
         "train_samples_per_link": n,
         "final_train_l1_mm": [round(1e3 * float(x), 2) for x in hist[-1]],
         **learned_pair_stats(w, T, pts, params, cen, half, core, margin=0.05),
@@ -665,7 +673,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="paper")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned variant (about 90 s of training)")
+    ap.add_argument("--learned-epochs", type=int, default=None,
+                    help="train only this many epochs of the recipe's first phase (profiling runs); 0 skips the "
+                         "learned variant; default: the library's recipe (about 90 s)")
     ap.add_argument("--learned-steps", type=int, default=5)
     ap.add_argument("--no-precision", action="store_true", help="skip the 128^3 bf16/fp16 storage variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-trajectory batched variant")
@@ -703,7 +713,7 @@ def main():
         return
     lsdf.load_library()
     if args.only:
-        only = {"learned": lambda: learned_variant(dev, args.learned_steps),
+        only = {"learned": lambda: learned_variant(dev, args.learned_steps, args.learned_epochs),
                 "scenes": lambda: extra_scenes(dev, 50, 5),
                 "precision": lambda: precision_variant(dev, 50),
                 "batched": lambda: batched_variant(dev, 20, 3),
@@ -890,8 +900,8 @@ def main():
         "roof_corner_tb_per_s_7mb": roof["grids_7mb"]["corner_tb_per_s"]}
     if not args.no_extra_scenes:
         rec["extra_scenes"] = extra_scenes(dev, 50, 5)
-    if not args.no_learned:
-        rec["learned"] = learned_variant(dev, args.learned_steps)
+    if args.learned_epochs != 0:
+        rec["learned"] = learned_variant(dev, args.learned_steps, args.learned_epochs)
     if not args.no_precision:
         rec["precision"] = precision_variant(dev, 50)
     if not args.no_batched:
