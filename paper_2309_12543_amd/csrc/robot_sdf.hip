@@ -6,7 +6,8 @@
 // It is kept here as the comparator of the per-point query: heavy
 // preparation and C x V voxels of memory against a trivial runtime.
 //
-// Build (one thread per environment voxel column of 8, voxels x fastest,
+// Build (one thread per environment voxel column of 32, or of 8 for the
+// network build, voxels x fastest,
 // so every store is coalesced and each voxel is written exactly once,
 // without atomics):
 //   * link i's block at configuration c covers voxels k .. k + 2m - 1 per
@@ -73,47 +74,51 @@ __global__ __launch_bounds__(kBlock) void align_kernel(BuildArgs a) {
 }
 
 // Build tiles: a workgroup covers 64 (x, one per lane) x 4 (y, one per
-// wave) x kTileZ (z, looped) voxels of one configuration, so that each
-// wave reads a link's block corner and map once (scalar loads) for
-// kTileZ x 64 voxels and skips, with one uniform test, every link whose
-// block misses its tile.
-constexpr int kTileX = 64, kTileY = kBlock / 64, kTileZ = 8;
+// wave) x TZ (z, looped) voxels of one configuration, so that each wave
+// reads a link's block corner and map once (scalar loads) for TZ x 64
+// voxels and skips, with one uniform test, every link whose block misses
+// its tile.  The exact build takes TZ = 32: four times fewer workgroups
+// than 8, and its stores stream past the caches (non-temporal), since the
+// Robot SDFs are read only by a later runtime call (1.62 -> 1.06 ms for 500
+// waypoints over 128^3 voxels, against 0.61 ms for a plain fill of the same
+// 4.2 GB).  The network build keeps TZ = 8 (its per-voxel work is larger).
+constexpr int kTileX = 64, kTileY = kBlock / 64, kTileZ = 8, kBuildTileZ = 32;
 
 struct Tile {
     int vx, vy, z0;
     bool lane_ok;        // this lane's x and the wave's y lie in the environment
 };
 
-__device__ inline Tile tile_of(const int32_t n[3]) {
+__device__ inline Tile tile_of(const int32_t n[3], int tz) {
     const int tiles_x = (n[0] + kTileX - 1) / kTileX;
     const int ty = (int)blockIdx.x / tiles_x;
     const int tx = (int)blockIdx.x - ty * tiles_x;
     Tile t;
     t.vx = tx * kTileX + (int)(threadIdx.x & 63);
     t.vy = ty * kTileY + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    t.z0 = (int)blockIdx.y * kTileZ;
+    t.z0 = (int)blockIdx.y * tz;
     t.lane_ok = t.vx < n[0] && t.vy < n[1];
     return t;
 }
 
 // Does the block [k, k + w) per axis meet this wave's tile (x over the
-// wave's 64 voxels, its y row, z over kTileZ levels)?  Wave-uniform.
-__device__ inline bool tile_meets(const Tile& t, const int32_t k[3], int w) {
+// wave's 64 voxels, its y row, z over tz levels)?  Wave-uniform.
+__device__ inline bool tile_meets(const Tile& t, const int32_t k[3], int w, int tz) {
     const int x0 = t.vx - (int)(threadIdx.x & 63);
-    return k[0] < x0 + kTileX && k[0] + w > x0 && t.vy >= k[1] && t.vy < k[1] + w && k[2] < t.z0 + kTileZ &&
+    return k[0] < x0 + kTileX && k[0] + w > x0 && t.vy >= k[1] && t.vy < k[1] + w && k[2] < t.z0 + tz &&
            k[2] + w > t.z0;
 }
 
 template <bool CUBIC, int DT>
 __global__ __launch_bounds__(kBlock) void build_kernel(BuildArgs a, int32_t c0,
                                                        const typename GridT<DT>::T* __restrict__ grid) {
-    const Tile t = tile_of(a.n);
+    const Tile t = tile_of(a.n, kBuildTileZ);
     const int c = c0 + (int)blockIdx.z;
     const float x = (float)(a.lo[0] + ((double)t.vx + 0.5) * a.r);
     const float y = (float)(a.lo[1] + ((double)t.vy + 0.5) * a.r);
-    float zc[kTileZ], best[kTileZ];
+    float zc[kBuildTileZ], best[kBuildTileZ];
 #pragma unroll
-    for (int dz = 0; dz < kTileZ; ++dz) {
+    for (int dz = 0; dz < kBuildTileZ; ++dz) {
         zc[dz] = (float)(a.lo[2] + ((double)(t.z0 + dz) + 0.5) * a.r);
         best[dz] = INFINITY;
     }
@@ -121,12 +126,12 @@ __global__ __launch_bounds__(kBlock) void build_kernel(BuildArgs a, int32_t c0,
     for (int i = 0; i < a.L; ++i) {
         const LinkBlock b = bl[i];
         const int w = 2 * a.halfw[i];
-        if (!tile_meets(t, b.k, w)) continue;
+        if (!tile_meets(t, b.k, w, kBuildTileZ)) continue;
         // only the voxels the link's aligned block covers
         if (!(t.vx >= b.k[0] && t.vx < b.k[0] + w)) continue;
         const LinkGrid& lg = a.link[i];
 #pragma unroll
-        for (int dz = 0; dz < kTileZ; ++dz) {
+        for (int dz = 0; dz < kBuildTileZ; ++dz) {
             const int vz = t.z0 + dz;
             if (vz >= b.k[2] && vz < b.k[2] + w)
                 best[dz] = fminf(best[dz], lsdf::sample_or_inf<CUBIC, DT>(grid + lg.offset, lg, b.gm, x, y, zc[dz]));
@@ -136,8 +141,8 @@ __global__ __launch_bounds__(kBlock) void build_kernel(BuildArgs a, int32_t c0,
     const int64_t V = (int64_t)a.n[0] * a.n[1] * a.n[2];
     float* out = a.rs + (int64_t)c * V + ((int64_t)t.z0 * a.n[1] + t.vy) * a.n[0] + t.vx;
 #pragma unroll
-    for (int dz = 0; dz < kTileZ; ++dz)
-        if (t.z0 + dz < a.n[2]) out[(int64_t)dz * a.n[0] * a.n[1]] = best[dz];
+    for (int dz = 0; dz < kBuildTileZ; ++dz)
+        if (t.z0 + dz < a.n[2]) __builtin_nontemporal_store(best[dz], &out[(int64_t)dz * a.n[0] * a.n[1]]);
 }
 
 // The same build with the transformation of Eq. 5: each block voxel's
@@ -199,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void align_nn_kernel(BuildNNArgs a) {
 template <bool CUBIC, int DT>
 __global__ __launch_bounds__(kBlock) void build_nn_kernel(BuildNNArgs a, int32_t c0,
                                                           const typename GridT<DT>::T* __restrict__ grid) {
-    const Tile t = tile_of(a.n);
+    const Tile t = tile_of(a.n, kTileZ);
     const int c = c0 + (int)blockIdx.z;
     const int w = 2 * a.m;
     const int64_t O = 3 * (int64_t)w * w * w;
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void build_nn_kernel(BuildNNArgs a, int32_t
     const LinkBlockNN* bl = a.blocks + (int64_t)c * a.L;
     for (int i = 0; i < a.L; ++i) {
         const LinkBlockNN& b = bl[i];
-        if (!tile_meets(t, b.k, w)) continue;
+        if (!tile_meets(t, b.k, w, kTileZ)) continue;
         const int jx = t.vx - b.k[0], jy = t.vy - b.k[1];
         if (!(jx >= 0 && jx < w)) continue;
         const LinkGrid& lg = a.link[i];
@@ -452,7 +457,7 @@ LSDF_API int lsdf_robot_sdf_build(const float* link_T, int32_t C, int32_t L, con
     const dim3 bd(kBlock);
     for (int32_t c0 = 0; c0 < C; c0 += 65535) {
         const dim3 gd((unsigned)(((env->n[0] + kTileX - 1) / kTileX) * ((env->n[1] + kTileY - 1) / kTileY)),
-                      (unsigned)((env->n[2] + kTileZ - 1) / kTileZ), (unsigned)std::min<int32_t>(65535, C - c0));
+                      (unsigned)((env->n[2] + kBuildTileZ - 1) / kBuildTileZ), (unsigned)std::min<int32_t>(65535, C - c0));
         switch (dtype * 2 + (cubic ? 1 : 0)) {
             case LSDF_F32 * 2 + 1: hipLaunchKernelGGL((build_kernel<true, LSDF_F32>), gd, bd, 0, s, a, c0, static_cast<const float*>(grid_buf)); break;
             case LSDF_F32 * 2: hipLaunchKernelGGL((build_kernel<false, LSDF_F32>), gd, bd, 0, s, a, c0, static_cast<const float*>(grid_buf)); break;
