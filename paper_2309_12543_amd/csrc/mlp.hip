@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void mlp_eval_kernel(EvalArgs p) {
             e[nt] = core_distance(u[0], u[1], u[2], p.d.core);
         }
         float m[NT];
-        forward_tile<NT, false>(sW2, sW3, &sp, xh, m, ForwardTrace{});
+        forward_tile<NT>(sW2, sW3, &sp, xh, m);
         if (lane < 16) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
         }
         if (!__ballot(any)) continue;
         float m[NT];
-        forward_tile<NT, false>(sW2, sW3, &sp, xh, m, ForwardTrace{});
+        forward_tile<NT>(sW2, sW3, &sp, xh, m);
         if (lane < 16) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
@@ -206,10 +206,7 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
 
 // Per-link slices of the training workspace ([L][...] arrays).
 struct TrainBufs {
-    float* z1;      // [L][128][B]
-    float* z2;
-    float* z3;
-    float* dz1;
+    float* dz1;     // [L][128][B]
     __bf16* h1;     // [L][128][B]
     __bf16* h2;
     __bf16* h3;
@@ -233,132 +230,182 @@ struct TrainArgs {
     int32_t nsplit;
 };
 
-__global__ __launch_bounds__(kBlock) void train_forward_kernel(TrainArgs p) {
+// Forward and backward pass of one wave tile of the batch (16 samples per
+// wave), in one kernel: the pre-activations never leave the registers.
+// SiLU(z) and SiLU'(z) share one sigmoid, s = 1 / (1 + exp(-z)):
+// SiLU = z s, SiLU' = s (1 + z (1 - s)).  SiLU'(z2) and SiLU'(z3) of every
+// unit a lane holds are kept for the backward pass; SiLU'(z1), needed last,
+// is recomputed from the inputs then (the same bits, three FMA and the
+// sigmoid per unit), which keeps the kernel within its registers.  A
+// lane's units in a result tile (16 mt + 4 g + r) are the units of its B
+// operand slots (perm_unit), so the kept derivatives line up with the
+// backward products with no exchange.
+// Stored for the weight gradients: the rounded activations h1, h2, h3, the
+// rounded deltas dz3, dz2 and the FP32 delta dz1, the normalised inputs and
+// dm = d(loss)/dm; the loss per tile.
+#ifndef LSDF_TRAIN_BLOCK
+#define LSDF_TRAIN_BLOCK 512
+#endif
+constexpr int kTrainBlock = LSDF_TRAIN_BLOCK;
+constexpr int kTrainWaves = kTrainBlock / 64;
+static_assert(kSplit % (TILE_TRAIN * kTrainWaves) == 0, "a batch of whole workgroups");
+
+__global__ __launch_bounds__(kTrainBlock) void train_fwdbwd_kernel(TrainArgs p) {
     __shared__ __bf16 sW2[WTILE_ELEMS];
     __shared__ __bf16 sW3[WTILE_ELEMS];
+    __shared__ __bf16 sW3t[WTILE_ELEMS];
+    __shared__ __bf16 sW2t[WTILE_ELEMS];
     __shared__ SmallParams sp;
     const int l = blockIdx.y;
     const float* P = p.params + (int64_t)l * NPARAM;
     stage_weights(sW2, P + OFF_W2, false);
     stage_weights(sW3, P + OFF_W3, false);
-    stage_small(&sp, P);
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tt = blockIdx.x * kWaves + wave;          // tile of this wave
-    const int64_t B = p.B;
-    const int64_t lB = (int64_t)l * B;
-    float xh[NT_TRAIN][3], e[NT_TRAIN];
-    int64_t idx[NT_TRAIN];
-#pragma unroll
-    for (int nt = 0; nt < NT_TRAIN; ++nt) {
-        const int64_t s = (int64_t)tt * TILE_TRAIN + 16 * nt + (lane & 15);
-        int64_t k = p.bidx ? (int64_t)p.bidx[lB + s] : s;
-        k = min(max(k, (int64_t)0), p.N - 1);          // a bad index reads a valid sample
-        idx[nt] = (int64_t)l * p.N + k;
-        const Domain& d = p.dom[l];
-        float u[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            u[a] = p.samples[3 * idx[nt] + a] - d.cen[a];
-            xh[nt][a] = u[a] * d.inv[a];
-        }
-        e[nt] = core_distance(u[0], u[1], u[2], d.core);
-        if (lane < 16) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) p.w.xh[(lB + s) * 3 + a] = xh[nt][a];
-        }
-    }
-    const int64_t plane = (int64_t)l * H * B;
-    ForwardTrace tr{p.w.z1 + plane, p.w.z2 + plane, p.w.z3 + plane, p.w.h1 + plane, p.w.h2 + plane, p.w.h3 + plane,
-                    B, (int64_t)tt * TILE_TRAIN};
-    float m[NT_TRAIN];
-    forward_tile<NT_TRAIN, true>(sW2, sW3, &sp, xh, m, tr);
-    float absr = 0.0f;
-    if (lane < 16) {
-#pragma unroll
-        for (int nt = 0; nt < NT_TRAIN; ++nt) {
-            const int64_t s = (int64_t)tt * TILE_TRAIN + 16 * nt + lane;
-            const float r = (m[nt] + e[nt]) - p.labels[idx[nt]];
-            p.w.dm[lB + s] = (r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f)) / (float)B;
-            absr += fabsf(r);
-        }
-    }
-    absr = wave_sum(absr);
-    if (lane == 0) p.w.loss[(int64_t)l * (B / TILE_TRAIN) + tt] = absr;
-}
-
-__global__ __launch_bounds__(kBlock) void train_backward_kernel(TrainArgs p) {
-    __shared__ __bf16 sW3t[WTILE_ELEMS];
-    __shared__ __bf16 sW2t[WTILE_ELEMS];
-    __shared__ float sw4[H];
-    const int l = blockIdx.y;
-    const float* P = p.params + (int64_t)l * NPARAM;
     stage_weights(sW3t, P + OFF_W3, true);
     stage_weights(sW2t, P + OFF_W2, true);
-    for (int u = threadIdx.x; u < H; u += blockDim.x) sw4[u] = bf16_round(P[OFF_W4 + u]);
+    stage_small(&sp, P);
     __syncthreads();
+    static_assert(NT_TRAIN == 1, "one 16-sample column tile per wave");
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4;
     const int col = lane & 15;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tt = blockIdx.x * kWaves + wave;
+    const int tt = blockIdx.x * kTrainWaves + wave;          // tile of this wave
     const int64_t B = p.B;
     const int64_t lB = (int64_t)l * B;
     const int64_t plane = (int64_t)l * H * B;
-    const int64_t c0 = (int64_t)tt * TILE_TRAIN;
+    const int64_t s_idx = (int64_t)tt * TILE_TRAIN + col;   // this lane's sample in the batch
+    const int64_t c = s_idx;
+    int64_t k = p.bidx ? (int64_t)p.bidx[lB + s_idx] : s_idx;
+    k = min(max(k, (int64_t)0), p.N - 1);              // a bad index reads a valid sample
+    const int64_t idx = (int64_t)l * p.N + k;
+    const Domain& d = p.dom[l];
+    float xh[3], u3[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        u3[a] = p.samples[3 * idx + a] - d.cen[a];
+        xh[a] = u3[a] * d.inv[a];
+    }
+    const float e_core = core_distance(u3[0], u3[1], u3[2], d.core);
+    if (lane < 16) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p.w.xh[(lB + s_idx) * 3 + a] = xh[a];
+    }
+    asm volatile("" ::: "memory");
 
-    // dz3 = dm * w4 * SiLU'(z3), rounded: B operand of dh2 = W3^T dz3
-    bf16x8 b[4][NT_TRAIN];
+    // ---- forward ----
+    float g2[8][4], g3[8][4];   // SiLU' of this lane's units
+    bf16x8 b[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int u = perm_unit(s, 8 * g + e);
+            const float z = fmaf(sp.w1[u][0], xh[0], fmaf(sp.w1[u][1], xh[1], fmaf(sp.w1[u][2], xh[2], sp.b1[u])));
+            const __bf16 h = (__bf16)silu(z);
+            b[s][e] = h;
+            p.w.h1[plane + u * B + c] = h;
+        }
+    float m = 0.0f;
 #pragma unroll
-            for (int nt = 0; nt < NT_TRAIN; ++nt) {
-                const int64_t c = c0 + 16 * nt + col;
-                const float d = p.w.dm[lB + c] * sw4[u] * silu_grad(p.w.z3[plane + u * B + c]);
-                const __bf16 db = (__bf16)d;
-                b[s][nt][e] = db;
-                p.w.dz3[plane + u * B + c] = db;
-            }
+    for (int layer = 0; layer < 2; ++layer) {
+        const __bf16* sW = layer == 0 ? sW2 : sW3;
+        const float* bias = layer == 0 ? sp.b2 : sp.b3;
+        f32x4 acc[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+            acc[mt] = f32x4{bias[16 * mt + 4 * g], bias[16 * mt + 4 * g + 1], bias[16 * mt + 4 * g + 2],
+                            bias[16 * mt + 4 * g + 3]};
+        asm volatile("" ::: "memory");   // the layer's weight reads stay inside the layer
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_a(sW, mt, s, lane), b[s], acc[mt], 0, 0, 0);
+        if (layer == 0) {
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int u = 16 * mt + 4 * g + r;
+                    const float z = acc[mt][r];
+                    const float sg = sigmoid(z);
+                    const __bf16 h = (__bf16)(z * sg);
+                    g2[mt][r] = silu_grad_of(z, sg);
+                    b[mt >> 1][(mt & 1) * 4 + r] = h;
+                    p.w.h2[plane + u * B + c] = h;
+                }
+        } else {
+            float part = 0.0f;
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; r += 2) {
+                    const int u = 16 * mt + 4 * g + r;
+                    __bf16 hh[2];
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const float z = acc[mt][r + q];
+                        const float sg = sigmoid(z);
+                        hh[q] = (__bf16)(z * sg);
+                        g3[mt][r + q] = silu_grad_of(z, sg);
+                        p.w.h3[plane + (u + q) * B + c] = hh[q];
+                    }
+                    const bf16x2 hp = {hh[0], hh[1]};
+                    const bf16x2 wp = {sp.w4b[u], sp.w4b[u + 1]};
+                    part = __builtin_amdgcn_fdot2_f32_bf16(hp, wp, part, false);
+                }
+            part += __shfl_xor(part, 16, 64);
+            part += __shfl_xor(part, 32, 64);
+            m = part + sp.b4;
+        }
+    }
+    // loss of the estimate (network + core distance) and its derivative
+    const float r_ = (m + e_core) - p.labels[idx];
+    const float dm = (r_ > 0.0f ? 1.0f : (r_ < 0.0f ? -1.0f : 0.0f)) / (float)B;
+    float absr = lane < 16 ? fabsf(r_) : 0.0f;
+    if (lane < 16) p.w.dm[lB + s_idx] = dm;
+    absr = wave_sum(absr);
+    if (lane == 0) p.w.loss[(int64_t)l * (B / TILE_TRAIN) + tt] = absr;
+
+    // ---- backward ----
+    // dz3 = dm * w4 * SiLU'(z3), rounded: B operand of dh2 = W3^T dz3
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int u = perm_unit(s, 8 * g + e);
+            const __bf16 db = (__bf16)(dm * sp.w4[u] * g3[2 * s + (e >> 2)][e & 3]);
+            b[s][e] = db;
+            p.w.dz3[plane + u * B + c] = db;
         }
 #pragma unroll
     for (int layer = 0; layer < 2; ++layer) {
         const __bf16* sW = layer == 0 ? sW3t : sW2t;
-        f32x4 acc[8][NT_TRAIN];
+        f32x4 acc[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < NT_TRAIN; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int s = 0; s < 4; ++s)
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_a(sW, mt, s, lane), b[s], acc[mt], 0, 0, 0);
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const bf16x8 a = lds_a(sW, mt, s, lane);
-#pragma unroll
-                for (int nt = 0; nt < NT_TRAIN; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[s][nt], acc[mt][nt], 0, 0, 0);
-            }
-#pragma unroll
-        for (int mt = 0; mt < 8; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < NT_TRAIN; ++nt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int u = 16 * mt + 4 * g + r;
-                    const int64_t c = c0 + 16 * nt + col;
-                    if (layer == 0) {
-                        // dz2 = (W3^T dz3) * SiLU'(z2), rounded: B operand of dh1 = W2^T dz2
-                        const __bf16 db = (__bf16)(acc[mt][nt][r] * silu_grad(p.w.z2[plane + u * B + c]));
-                        b[mt >> 1][nt][(mt & 1) * 4 + r] = db;
-                        p.w.dz2[plane + u * B + c] = db;
-                    } else {
-                        // dz1 = (W2^T dz2) * SiLU'(z1), kept in FP32
-                        p.w.dz1[plane + u * B + c] = acc[mt][nt][r] * silu_grad(p.w.z1[plane + u * B + c]);
-                    }
+            for (int r = 0; r < 4; ++r) {
+                const int u = 16 * mt + 4 * g + r;
+                if (layer == 0) {
+                    // dz2 = (W3^T dz3) * SiLU'(z2), rounded: B operand of dh1 = W2^T dz2
+                    const __bf16 db = (__bf16)(acc[mt][r] * g2[mt][r]);
+                    b[mt >> 1][(mt & 1) * 4 + r] = db;
+                    p.w.dz2[plane + u * B + c] = db;
+                } else {
+                    // dz1 = (W2^T dz2) * SiLU'(z1), kept in FP32
+                    const float z = fmaf(sp.w1[u][0], xh[0], fmaf(sp.w1[u][1], xh[1], fmaf(sp.w1[u][2], xh[2], sp.b1[u])));
+                    p.w.dz1[plane + u * B + c] = acc[mt][r] * silu_grad_of(z, sigmoid(z));
                 }
+            }
     }
 }
 
@@ -581,9 +628,6 @@ size_t train_layout(int32_t L, int32_t B, char* base, TrainBufs* w) {
         return p;
     };
     TrainBufs t{};
-    t.z1 = (float*)take(f_plane);
-    t.z2 = (float*)take(f_plane);
-    t.z3 = (float*)take(f_plane);
     t.dz1 = (float*)take(f_plane);
     t.h1 = (__bf16*)take(h_plane);
     t.h2 = (__bf16*)take(h_plane);
@@ -636,11 +680,9 @@ int train_common(const float* params, float* adam_m, float* adam_v, int64_t t, f
     a.B = B;
     a.nsplit = B / kSplit;
     hipStream_t s = as_stream(stream);
-    const dim3 tiles_grid(B / (TILE_TRAIN * kWaves), L);
-    hipLaunchKernelGGL(train_forward_kernel, tiles_grid, dim3(kBlock), 0, s, a);
-    if ((rc = check_launch("mlp train forward")) != LSDF_OK) return rc;
-    hipLaunchKernelGGL(train_backward_kernel, tiles_grid, dim3(kBlock), 0, s, a);
-    if ((rc = check_launch("mlp train backward")) != LSDF_OK) return rc;
+    const dim3 tiles_grid(B / (TILE_TRAIN * kTrainWaves), L);
+    hipLaunchKernelGGL(train_fwdbwd_kernel, tiles_grid, dim3(kTrainBlock), 0, s, a);
+    if ((rc = check_launch("mlp train forward and backward")) != LSDF_OK) return rc;
     hipLaunchKernelGGL(train_wgrad_kernel, dim3(a.nsplit, L, 1 + kSmallGradBlocks), dim3(kBlock), 0, s, a);
     if ((rc = check_launch("mlp train weight gradients")) != LSDF_OK) return rc;
     ReduceArgs r{};

@@ -80,15 +80,15 @@ __device__ inline float core_distance(float ux, float uy, float uz, const float 
     return __builtin_sqrtf(fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
 }
 
-__device__ inline float silu(float z) {
-    const float e = __builtin_amdgcn_exp2f(-z * 1.44269504088896340736f);
-    return z * __builtin_amdgcn_rcpf(1.0f + e);
+// sigmoid(z) = 1 / (1 + exp(-z)); SiLU(z) = z sigmoid(z) and
+// SiLU'(z) = s (1 + z (1 - s)) with s = sigmoid(z)
+__device__ inline float sigmoid(float z) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z * 1.44269504088896340736f));
 }
 
-__device__ inline float silu_grad(float z) {
-    const float s = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-z * 1.44269504088896340736f));
-    return s * (1.0f + z * (1.0f - s));
-}
+__device__ inline float silu(float z) { return z * sigmoid(z); }
+
+__device__ inline float silu_grad_of(float z, float s) { return s * (1.0f + z * (1.0f - s)); }
 
 // Stages one 128x128 weight matrix W (row-major [out][in], FP32) into LDS as
 // bf16 A-operand tiles [mt][s][lane][8].  transpose = false: rows are output
@@ -123,28 +123,14 @@ __device__ inline bf16x8 lds_a(const __bf16* tiles, int mt, int s, int lane) {
     return *reinterpret_cast<const bf16x8*>(tiles + ((mt * 4 + s) * 64 + lane) * 8);
 }
 
-// Optional per-sample outputs of the forward pass (training).  Arrays are
-// unit-major [128][ld]; sample index `col0 + 16 nt + lane % 16`.
-struct ForwardTrace {
-    float* z1;
-    float* z2;
-    float* z3;
-    __bf16* h1;
-    __bf16* h2;
-    __bf16* h3;
-    int64_t ld;
-    int64_t col0;
-};
-
 // Forward pass of one wave tile (16 NT_ pairs).  xh[nt] is this lane's input
 // for pair 16 nt + lane % 16 (all four lane groups hold the same pairs).
 // Returns the output for pair 16 nt + lane % 16 in m[nt] (every lane).
-template <int NT_, bool TRACE>
+template <int NT_>
 __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const SmallParams* sp,
-                                    const float (&xh)[NT_][3], float (&m)[NT_], const ForwardTrace& tr) {
+                                    const float (&xh)[NT_][3], float (&m)[NT_]) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4;
-    const int col = lane & 15;
     // keeps the weight reads from LDS inside the tile: hoisted out of a tile
     // loop they would need 256 VGPRs
     asm volatile("" ::: "memory");
@@ -162,11 +148,6 @@ __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const 
                                      fmaf(sp->w1[u][1], xh[nt][1], fmaf(sp->w1[u][2], xh[nt][2], sp->b1[u])));
                 const __bf16 h = (__bf16)silu(z);
                 b[s][nt][e] = h;
-                if (TRACE) {
-                    const int64_t c = tr.col0 + 16 * nt + col;
-                    tr.z1[u * tr.ld + c] = z;
-                    tr.h1[u * tr.ld + c] = h;
-                }
             }
         }
     }
@@ -203,15 +184,9 @@ __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const 
                 for (int nt = 0; nt < NT_; ++nt)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int u = 16 * mt + 4 * g + r;
                         const float z = acc[mt][nt][r];
                         const __bf16 h = (__bf16)silu(z);
                         b[mt >> 1][nt][(mt & 1) * 4 + r] = h;
-                        if (TRACE) {
-                            const int64_t c = tr.col0 + 16 * nt + col;
-                            tr.z2[u * tr.ld + c] = z;
-                            tr.h2[u * tr.ld + c] = h;
-                        }
                     }
         } else {
             // SiLU, rounded, and this lane's part of w4 . h3 (bfloat16
@@ -229,13 +204,6 @@ __device__ inline void forward_tile(const __bf16* sW2, const __bf16* sW3, const 
                         const bf16x2 hp = {h0, h1};
                         const bf16x2 wp = {sp->w4b[u], sp->w4b[u + 1]};
                         part = __builtin_amdgcn_fdot2_f32_bf16(hp, wp, part, false);
-                        if (TRACE) {
-                            const int64_t c = tr.col0 + 16 * nt + col;
-                            tr.z3[u * tr.ld + c] = z0;
-                            tr.h3[u * tr.ld + c] = h0;
-                            tr.z3[(u + 1) * tr.ld + c] = z1;
-                            tr.h3[(u + 1) * tr.ld + c] = h1;
-                        }
                     }
                 part += __shfl_xor(part, 16, 64);
                 part += __shfl_xor(part, 32, 64);
