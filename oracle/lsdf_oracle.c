@@ -501,7 +501,10 @@ ORC_EXPORT void orc_reduce_f32(const float* cl, int32_t C, int32_t L, float* d, 
 /* extent of the link's core box (its mesh's bounding box, centred at c).    */
 /* E is the distance from l to that box (0 inside it), which the true        */
 /* distance approaches far from the link, so the network only learns the     */
-/* bounded, slowly varying remainder.                                        */
+/* bounded, slowly varying remainder.  With a remainder bound B > 0 per link */
+/* the network's share is B tanh(m / B) (B = +inf: m itself), so that        */
+/*   E - B <= F <= E + B,                                                    */
+/* which lets a query skip, exactly, the points that cannot hold a minimum.  */
 /* ------------------------------------------------------------------------ */
 #define ORC_H 128
 #define ORC_OFF_W1 0
@@ -584,10 +587,14 @@ static double core_distance(const double* l, const double* c, const double* k) {
     return sqrt(q2);
 }
 
+/* The network's share of the estimate: B tanh(m / B), or m when B = +inf. */
+static double bounded(double m, double B) { return isinf(B) ? m : B * tanh(m / B); }
+
 /* The surrogate's estimate F at N link-frame points L [N][3] of one link:   */
-/* the network at (l - c) / h plus the core term E(l) (core_k NULL: none).   */
+/* the network at (l - c) / h, bounded by B, plus the core term E(l)         */
+/* (core_k NULL: none).                                                      */
 ORC_EXPORT void orc_mlp_value(const double* P, const double* Lp, int64_t N, const double* dom_c,
-                              const double* dom_h, const double* core_k, int32_t bf16, double* out) {
+                              const double* dom_h, const double* core_k, double bound, int32_t bf16, double* out) {
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j) {
         double z1[ORC_H], h1[ORC_H], z2[ORC_H], h2[ORC_H], z3[ORC_H], h3[ORC_H];
@@ -595,18 +602,19 @@ ORC_EXPORT void orc_mlp_value(const double* P, const double* Lp, int64_t N, cons
         double xh[3];
         for (int a = 0; a < 3; ++a) xh[a] = (l[a] - dom_c[a]) / dom_h[a];
         double m = mlp_forward_one(P, xh, bf16, z1, h1, z2, h2, z3, h3);
+        m = bounded(m, bound);
         out[j] = core_k ? m + core_distance(l, dom_c, core_k) : m;
     }
 }
 
 /* Mean-absolute-error loss over N samples and its gradient (chain rule,
- * layer by layer).  The estimate of sample j is the network's output plus
- * D[j] (the core term at the sample; D NULL: none), and the loss is
- * mean |estimate - Y|.  With bf16 != 0 the backward pass also rounds where
+ * layer by layer).  The estimate of sample j is the network's output m,
+ * bounded (B tanh(m / B); bound = +inf: m), plus D[j] (the core term at the
+ * sample; D NULL: none), and the loss is mean |estimate - Y|.  With bf16 != 0 the backward pass also rounds where
  * the GPU kernels do: the delta vectors dz3 and dz2 before they are
  * multiplied (weight gradients and the back-propagated deltas). */
 ORC_EXPORT double orc_mlp_loss_grad(const double* P, const double* X, const double* D, const double* Y, int64_t N,
-                                    int32_t bf16, double* grad) {
+                                    double bound, int32_t bf16, double* grad) {
 #define R(v) (bf16 ? bf16r(v) : (v))
     memset(grad, 0, ORC_NPARAM * sizeof(double));
     double loss = 0.0;
@@ -615,9 +623,14 @@ ORC_EXPORT double orc_mlp_loss_grad(const double* P, const double* X, const doub
         double d3[ORC_H], d2[ORC_H], d1[ORC_H];
         const double* x = X + 3 * j;
         double m = mlp_forward_one(P, x, bf16, z1, h1, z2, h2, z3, h3);
-        double r = (D ? m + D[j] : m) - Y[j];
+        const double f = bounded(m, bound);
+        double r = (D ? f + D[j] : f) - Y[j];
         loss += fabs(r);
         double dm = (r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0)) / (double)N;
+        if (!isinf(bound)) {
+            const double t = tanh(m / bound);
+            dm *= 1.0 - t * t;   /* d(B tanh(m / B)) / dm */
+        }
         grad[ORC_OFF_B4] += dm;
         for (int k = 0; k < ORC_H; ++k) {
             grad[ORC_OFF_W4 + k] += dm * h3[k];
@@ -745,7 +758,8 @@ ORC_EXPORT void orc_judge_min(const double* T, int32_t C, int32_t L, const doubl
 /*   l lies in link i's network domain, |(l_a - dom_c_a) / dom_h_a| <= 1;    */
 /*   m = the network of link i at the normalised point (mlp_forward_one,      */
 /*       bfloat16 rounding points when bf16 != 0) plus the core term E(l)    */
-/*       (core_k [L][3] the core boxes' half extents; NULL: no core term);   */
+/*       (core_k [L][3] the core boxes' half extents; NULL: no core term), */
+/*       the network's share bounded by bounds[i] (NULL: unbounded);         */
 /*   if m < margin and the single-precision twin places the point in the     */
 /*   grid box, the pair's value is the twin's grid value, else it is m (a     */
 /*   point outside the box keeps m: the grid has no value there).             */
@@ -756,7 +770,8 @@ ORC_EXPORT void orc_judge_min(const double* T, int32_t C, int32_t L, const doubl
 ORC_EXPORT void orc_query_mlp(const float* T, int32_t C, int32_t L, const float* lo, const float* hi,
                               const int32_t* n, const float* grids, const int64_t* offs, const float* P,
                               int64_t M, const double* params, const double* dom_c, const double* dom_h,
-                              const double* core_k, double margin, int32_t bf16, double* out, double* each_m,
+                              const double* core_k, const double* bounds, double margin, int32_t bf16, double* out,
+                              double* each_m,
                               double* each_g) {
     float* gl = (float*)malloc(sizeof(float) * (size_t)L);
     float* ge = (float*)malloc(sizeof(float) * (size_t)L * (size_t)(M > 0 ? M : 1));
@@ -783,6 +798,7 @@ ORC_EXPORT void orc_query_mlp(const float* T, int32_t C, int32_t L, const float*
                 if (indom || each_m) {
                     double z1[ORC_H], h1[ORC_H], z2[ORC_H], h2[ORC_H], z3[ORC_H], h3[ORC_H];
                     m = mlp_forward_one(Pi, xh, bf16, z1, h1, z2, h2, z3, h3);
+                    if (bounds) m = bounded(m, bounds[i]);
                     if (core_k) m += core_distance(l, dom_c + 3 * i, core_k + 3 * i);
                 }
                 if (indom) {

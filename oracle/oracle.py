@@ -79,9 +79,9 @@ def load():
     lib.orc_mlp_forward.restype = None
     lib.orc_mlp_forward.argtypes = [_dp, _dp, ct.c_int64, ct.c_int32, _dp]
     lib.orc_mlp_value.restype = None
-    lib.orc_mlp_value.argtypes = [_dp, _dp, ct.c_int64, _dp, _dp, _dp, ct.c_int32, _dp]
+    lib.orc_mlp_value.argtypes = [_dp, _dp, ct.c_int64, _dp, _dp, _dp, ct.c_double, ct.c_int32, _dp]
     lib.orc_mlp_loss_grad.restype = ct.c_double
-    lib.orc_mlp_loss_grad.argtypes = [_dp, _dp, _dp, _dp, ct.c_int64, ct.c_int32, _dp]
+    lib.orc_mlp_loss_grad.argtypes = [_dp, _dp, _dp, _dp, ct.c_int64, ct.c_double, ct.c_int32, _dp]
     lib.orc_adam_step.restype = None
     lib.orc_adam_step.argtypes = [_dp, _dp, _dp, _dp, ct.c_int64, ct.c_int64, ct.c_double, ct.c_double,
                                   ct.c_double, ct.c_double]
@@ -90,7 +90,7 @@ def load():
                                   ct.POINTER(_ip), ct.POINTER(_ip), _ip, _dp, _dp, _dp, _dp, _dp, ct.c_int64, _dp]
     lib.orc_query_mlp.restype = None
     lib.orc_query_mlp.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _fp, _ip, _fp, _lp, _fp, ct.c_int64, _dp, _dp,
-                                  _dp, _dp, ct.c_double, ct.c_int32, _dp, _dp, _dp]
+                                  _dp, _dp, _dp, ct.c_double, ct.c_int32, _dp, _dp, _dp]
     lib.orc_query_f32_each.restype = None
     lib.orc_query_f32_each.argtypes = [_fp, ct.c_int32, ct.c_int32, _fp, _fp, _ip, _fp, _lp, _fp, ct.c_int64, _fp,
                                        _fp]
@@ -440,11 +440,13 @@ def judge_min(T, lo, hi, n, grids, meshes, dom_c, dom_h, points) -> np.ndarray:
     return out
 
 
-def query_mlp(T, lo, hi, n, grids, points, params, dom_c, dom_h, margin, bf16=True, each=False, core_k=None):
+def query_mlp(T, lo, hi, n, grids, points, params, dom_c, dom_h, margin, bf16=True, each=False, core_k=None,
+              bounds=None):
     """Per-link minima [C][L] of the learned clearance with its margin
     fallback: the surrogate's estimate per in-domain pair (the network plus
     the distance to the core box of half extents core_k [L][3] centred on the
-    domain; core_k None: the network alone), replaced by the single-
+    domain; core_k None: the network alone; with bounds [L], the network's
+    share is bounds[i] tanh(m / bounds[i])), replaced by the single-
     precision twin's grid value when it is below the margin and the point is
     in the grid box.  With each=True also returns the per-pair estimates
     (evaluated for every pair, in the domain or not) and twin grid values
@@ -463,9 +465,10 @@ def query_mlp(T, lo, hi, n, grids, points, params, dom_c, dom_h, margin, bf16=Tr
     eg = np.empty((C, L, M), dtype=np.float64) if each else None
     null = ct.POINTER(ct.c_double)()
     ck = None if core_k is None else _c(core_k, np.float64).reshape(L, 3)
+    bd = None if bounds is None else _c(np.broadcast_to(np.asarray(bounds, dtype=np.float64), (L,)), np.float64)
     lib.orc_query_mlp(_ptr(T, _fp), C, L, _ptr(lo, _fp), _ptr(hi, _fp), _ptr(n, _ip), _ptr(buf, _fp),
                       _ptr(offs, _lp), _ptr(P, _fp), M, _ptr(prm, _dp), _ptr(dc, _dp), _ptr(dh, _dp),
-                      null if ck is None else _ptr(ck, _dp), float(margin), int(bool(bf16)), _ptr(out, _dp),
+                      null if ck is None else _ptr(ck, _dp), null if bd is None else _ptr(bd, _dp), float(margin), int(bool(bf16)), _ptr(out, _dp),
                       _ptr(em, _dp) if each else null, _ptr(eg, _dp) if each else null)
     return (out, em, eg) if each else out
 
@@ -523,10 +526,11 @@ def mlp_forward(params, X, bf16: bool = False) -> np.ndarray:
     return out
 
 
-def mlp_value(params, points, dom_c, dom_h, core_k=None, bf16: bool = False) -> np.ndarray:
+def mlp_value(params, points, dom_c, dom_h, core_k=None, bf16: bool = False, bound=np.inf) -> np.ndarray:
     """The surrogate's estimate at link-frame points [N][3] of one link: the
-    network at (l - dom_c) / dom_h plus the distance from l to the core box
-    |l - dom_c| <= core_k (core_k None: the network alone)."""
+    network m at (l - dom_c) / dom_h, bounded (bound tanh(m / bound); bound
+    = inf: m), plus the distance from l to the core box |l - dom_c| <= core_k
+    (core_k None: no core term)."""
     lib = load()
     P = _c(params, np.float64)
     X = _c(np.atleast_2d(points), np.float64)
@@ -534,13 +538,15 @@ def mlp_value(params, points, dom_c, dom_h, core_k=None, bf16: bool = False) -> 
     ck = None if core_k is None else _c(core_k, np.float64).reshape(3)
     out = np.empty(X.shape[0], dtype=np.float64)
     lib.orc_mlp_value(_ptr(P, _dp), _ptr(X, _dp), X.shape[0], _ptr(dc, _dp), _ptr(dh, _dp),
-                      ct.POINTER(ct.c_double)() if ck is None else _ptr(ck, _dp), int(bf16), _ptr(out, _dp))
+                      ct.POINTER(ct.c_double)() if ck is None else _ptr(ck, _dp), float(bound), int(bf16),
+                      _ptr(out, _dp))
     return out
 
 
-def mlp_loss_grad(params, X, Y, bf16: bool = False, offset=None):
-    """(mean absolute error, gradient [nparam]) of the estimate network(X) +
-    offset (per sample; None: the network alone) against Y."""
+def mlp_loss_grad(params, X, Y, bf16: bool = False, offset=None, bound=np.inf):
+    """(mean absolute error, gradient [nparam]) of the estimate
+    bounded(network(X)) + offset (per sample; None: none) against Y, where
+    bounded(m) = bound tanh(m / bound) (bound = inf: m)."""
     lib = load()
     P = _c(params, np.float64)
     X = _c(np.atleast_2d(X), np.float64)
@@ -548,7 +554,7 @@ def mlp_loss_grad(params, X, Y, bf16: bool = False, offset=None):
     D = None if offset is None else _c(offset, np.float64)
     g = np.empty(P.shape[0], dtype=np.float64)
     loss = lib.orc_mlp_loss_grad(_ptr(P, _dp), _ptr(X, _dp), ct.POINTER(ct.c_double)() if D is None else _ptr(D, _dp),
-                                 _ptr(Y, _dp), X.shape[0], int(bf16), _ptr(g, _dp))
+                                 _ptr(Y, _dp), X.shape[0], float(bound), int(bf16), _ptr(g, _dp))
     return float(loss), g
 
 

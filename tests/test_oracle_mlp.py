@@ -352,3 +352,82 @@ def test_query_mlp_core_term_with_constant_network(orc, tiny, tiny_grids, margin
     assert np.array_equal(np.isfinite(got), np.isfinite(want))
     if margin > 0:
         assert ((got < 0.01) & np.isfinite(got)).any()             # some minima come from the grid
+
+
+# ---------------------------------------------------------------------------
+# the remainder bound: the network's share is B tanh(m / B)
+# ---------------------------------------------------------------------------
+
+def test_bounded_share_closed_forms(orc):
+    """A constant network b4 = k with bound B: the estimate is E + B tanh(k/B);
+    tanh(0.5) = 0.46211715726000974 and tanh(2) = 0.9640275800758169 (tables),
+    and a zero network gives E exactly."""
+    P = np.zeros(orc.mlp_nparam())
+    pts = np.array([_CORE_C, _CORE_C + [0.2 + 0.05, 0.0, 0.0]])       # E = 0 and 0.05
+    E = np.array([0.0, 0.05])
+    assert np.allclose(orc.mlp_value(P, pts, _CORE_C, _CORE_H, _CORE_K, bound=0.2), E, rtol=0, atol=1e-15)
+    P[-1] = 0.1
+    got = orc.mlp_value(P, pts, _CORE_C, _CORE_H, _CORE_K, bound=0.2)
+    assert np.allclose(got, E + 0.2 * 0.46211715726000974, rtol=0, atol=1e-15)
+    P[-1] = -0.4
+    got = orc.mlp_value(P, pts, _CORE_C, _CORE_H, _CORE_K, bound=0.2, bf16=True)
+    assert np.allclose(got, E - 0.2 * 0.9640275800758169, rtol=0, atol=1e-15)
+
+
+def test_bounded_share_stays_within_the_bound(orc):
+    """A random network with large outputs: every estimate lies within B of
+    the core distance, and with B = inf the estimate is the unbounded one."""
+    P = rand_params(orc, 35, scale=6.0)
+    rng = np.random.default_rng(36)
+    pts = _CORE_C + rng.uniform(-1, 1, size=(300, 3)) * _CORE_H
+    E = orc.mlp_value(np.zeros_like(P), pts, _CORE_C, _CORE_H, _CORE_K)
+    raw = orc.mlp_value(P, pts, _CORE_C, _CORE_H, _CORE_K) - E
+    assert np.abs(raw).max() > 1.0                                    # the network does exceed the bound
+    got = orc.mlp_value(P, pts, _CORE_C, _CORE_H, _CORE_K, bound=0.15)
+    assert np.all(np.abs(got - E) <= 0.15 + 1e-12)                  # (up to the rounding of the sum)
+    assert np.allclose(got - E, 0.15 * np.tanh(raw / 0.15), rtol=0, atol=1e-12)
+
+
+def test_loss_grad_with_bound_matches_torch_autograd(orc):
+    """Loss of E + B tanh(net / B) against Y and its gradient, against PyTorch
+    autograd in float64 (torch.tanh)."""
+    P = rand_params(orc, 37, scale=2.0)
+    rng = np.random.default_rng(38)
+    X = rng.uniform(-1, 1, size=(40, 3))
+    D = rng.uniform(0.0, 0.8, size=40)
+    Y = rng.uniform(-0.2, 1.0, size=40)
+    B = 0.3
+    loss, g = orc.mlp_loss_grad(P, X, Y, offset=D, bound=B)
+    net = torch_net(orc, P)
+    out = B * torch.tanh(net(torch.tensor(X))[:, 0] / B) + torch.tensor(D)
+    tl = torch.nn.functional.l1_loss(out, torch.tensor(Y))
+    tl.backward()
+    tg = np.concatenate([net[0].weight.grad.numpy().ravel(), net[0].bias.grad.numpy(),
+                         net[2].weight.grad.numpy().ravel(), net[2].bias.grad.numpy(),
+                         net[4].weight.grad.numpy().ravel(), net[4].bias.grad.numpy(),
+                         net[6].weight.grad.numpy().ravel(), net[6].bias.grad.numpy()])
+    assert loss == pytest.approx(tl.item(), abs=1e-14)
+    assert np.max(np.abs(g - tg)) < 1e-13 * max(1.0, np.abs(tg).max())
+    _, g_inf = orc.mlp_loss_grad(P, X, Y, offset=D)
+    assert np.max(np.abs(g_inf - g)) > 1e-3 * np.abs(tg).max()        # the bound changes the gradient
+
+
+def test_query_mlp_bound_with_constant_network(orc, tiny, tiny_grids):
+    """A constant network b4 = 0.3 with bound 0.1 and each link's core box:
+    every in-domain estimate is E + 0.1 tanh(3) (tanh(3) =
+    0.9950547536867305), margin -inf."""
+    import synth
+    T32, dc, dh, pts = _mlp_setup(orc, tiny)
+    ck = synth.mlp_core(tiny.grid_lo, tiny.grid_hi)
+    P = np.zeros((tiny.L, orc.mlp_nparam()))
+    P[:, -1] = 0.3
+    g32 = [g.astype(np.float32) for g in tiny_grids]
+    got = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P, dc, dh, -np.inf, core_k=ck,
+                        bounds=np.full(tiny.L, 0.1))
+    ind, X = _in_domain(T32, dc, dh, pts)
+    loc = X * dh[None, :, None, :] + dc[None, :, None, :]
+    proj = np.clip(loc, (dc - ck)[None, :, None, :], (dc + ck)[None, :, None, :])
+    est = 0.1 * 0.9950547536867305 + np.linalg.norm(loc - proj, axis=-1)
+    want = np.where(ind, est, np.inf).min(-1)
+    assert np.array_equal(np.isfinite(got), np.isfinite(want))
+    assert np.max(np.abs(np.where(np.isfinite(want), got - want, 0))) < 1e-9
