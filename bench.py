@@ -262,15 +262,16 @@ def learned_variant(dev, steps: int, epochs=None, judge_waypoints: int = 50):
                                   for i, m in enumerate(w.robot.links)]).astype(np.float32), device=dev)
     t0 = time.perf_counter()
     labels = learned.labels_for_samples(w.robot.links, gs, S)
+    bound = learned.remainder_bounds((cen, half, core), S, labels)
     params = torch.as_tensor(synth.mlp_init(w.L, synth.BASE_SEED + 5).astype(np.float32), device=dev)
     if epochs is None:
-        hist = learned.fit(params, (cen, half, core), S, labels, log_every=300, log=log)
+        hist = learned.fit(params, (cen, half, core, bound), S, labels, log_every=400, log=log)
     else:
-        hist = learned.train(params, (cen, half, core), S, labels, epochs=epochs, batch=learned.BATCH, lr=learned.LR,
-                             lr_final=learned.LR_FINAL)
+        hist = learned.train(params, (cen, half, core, bound), S, labels, epochs=epochs, batch=learned.BATCH,
+                             lr=learned.LR, lr_final=learned.LR_FINAL)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    doms = lsdf.make_domains(cen, half, core)
+    doms = lsdf.make_domains(cen, half, core, bound)
     q = torch.as_tensor(w.q, dtype=torch.float32, device=dev)
     pts = torch.as_tensor(w.points, dtype=torch.float32, device=dev)
     T = lsdf.fk_batch(w.robot.dh, q, base_T=w.robot.base_T)
@@ -313,8 +314,8 @@ def learned_variant(dev, steps: int, epochs=None, judge_waypoints: int = 50):
                 "p99_mm": round(float(np.percentile(e, 99)), 3)} if e.size else None
     return {
         "workload": f"{w.name}: {w.C} waypoints x {w.M} points x {w.L} links, 64^3 FP32 grids, "
-                    f"3-128-128-128-1 SiLU network per link (bf16 MFMA, FP32 accumulate) plus the distance to the "
-                    f"link's core box, fallback below 5 cm",
+                    f"3-128-128-128-1 SiLU network per link (bf16 MFMA, FP32 accumulate), its share bounded, plus the "
+                    f"distance to the link's core box; tiles that cannot hold a minimum skipped; fallback below 5 cm",
         "grid_ms_per_batch": round(grid_ms, 4),
         "mlp_ms_per_batch": round(mlp_ms, 3),
         "grid_gq_s": round(pairs / (grid_ms / 1e3) / 1e9, 2),
@@ -344,12 +345,14 @@ def learned_variant(dev, steps: int, epochs=None, judge_waypoints: int = 50):
                           "epochs_total": int(len(hist))} if epochs is None else
                          f"profiling run: {epochs} epochs of the first phase only (accuracy figures not the recipe's)"),
         "train_samples_per_link": n,
+        "remainder_bounds_m": [round(float(b), 3) for b in bound],
         "final_train_l1_mm": [round(1e3 * float(x), 2) for x in hist[-1]],
-        **learned_pair_stats(w, T, pts, params, cen, half, core, margin=0.05),
+        **learned_pair_stats(w, T, pts, params, cen, half, core, bound, margin=0.05),
     }
 
 
-def learned_pair_stats(w, T, pts, params, cen, half, core, margin: float, sample: int = 1 << 20, seed: int = 7):
+def learned_pair_stats(w, T, pts, params, cen, half, core, bound, margin: float, sample: int = 1 << 20,
+                       seed: int = 7):
     """On a seeded sample of (waypoint, point) pairs per link: the fraction
     inside the network's domain, and among those the fraction whose estimate
     falls below the margin (the pairs that take the exact grid value when
@@ -373,7 +376,7 @@ def learned_pair_stats(w, T, pts, params, cen, half, core, margin: float, sample
         lpi = lp[inside].contiguous()
         n_dom += int(lpi.shape[0])
         if lpi.shape[0]:
-            m = lsdf.mlp_eval(params[i].contiguous(), (cen[i:i + 1], half[i:i + 1], core[i:i + 1]), lpi)
+            m = lsdf.mlp_eval(params[i].contiguous(), (cen[i:i + 1], half[i:i + 1], core[i:i + 1], bound[i]), lpi)
             n_fb += int((m < margin).sum().item())
     return {"pair_sample_per_link": sample,
             "in_domain_pair_fraction": round(n_dom / (sample * w.L), 4),

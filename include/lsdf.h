@@ -377,9 +377,11 @@ int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* tris, int
  * -> 128 -> 1, SiLU(z) = z / (1 + exp(-z)), maps a link-frame point l
  * normalised to the link's domain to the remainder of the link's signed
  * distance over E(l), the distance from l to the link's core box (its mesh's
- * bounding box); the estimate is m + E.  E carries the distance's growth far
- * from the link, so the network only fits a bounded, slowly varying
- * remainder.  It answers queries beyond the grid box (the far field); the
+ * bounding box); the estimate is E + B tanh(m / B) with the link's remainder
+ * bound B (B = +inf: E + m).  E carries the distance's growth far from the
+ * link, so the network only fits a bounded, slowly varying remainder, and
+ * since the estimate lies within B of E a query skips, exactly, the points
+ * that cannot hold a link's minimum.  It answers queries beyond the grid box (the far field); the
  * grid stays the answer for every pair whose estimate is below a safety
  * margin, and the judge of the network's error.  The paper's own network
  * (Sec. III-B-1) is a different one (it approximates the grid transform);
@@ -399,24 +401,27 @@ int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* tris, int
  * |x_link - centre| <= core_half on every axis; its distance
  * E = || max(|x_link - centre| - core_half, 0) || (FP32: u = x_link - centre,
  * q = max(|u| - core_half, 0), E = sqrt(fma(qx, qx, fma(qy, qy, qz * qz))),
- * correctly rounded) is added to the network's output. */
+ * correctly rounded) is added to the network's share, which is
+ * bound * t with t = clamp(1 - 2 / (1 + exp(2 m / bound)), -1, 1) (in FP32,
+ * m times (float)(1 / bound)), or m itself when bound = +inf. */
 typedef struct lsdf_mlp_domain {
     float centre[3];
     float half[3];       /* each > 0 */
     float core_half[3];  /* each >= 0 */
+    float bound;         /* > 0, or +inf */
 } lsdf_mlp_domain;
 
-/* The surrogate's estimates (network + core distance) at N link-frame points
- * of one link.
+/* The surrogate's estimates (bounded network share + core distance) at N
+ * link-frame points of one link.
  *   params  device float [LSDF_MLP_PARAMS]; domain host; points device [N][3];
  *   out     device float [N] (evaluated also outside the domain). */
 int lsdf_mlp_eval(const float* params, const lsdf_mlp_domain* domain, const float* points, int64_t N,
                   float* out, void* stream);
 
 /* Clearance with the learned surrogate: as lsdf_query_min_distance, but the
- * value of pair (c, i, j) is m = the estimate of link i at the point (network
- * + core distance) if the point lies in link i's domain (the pair is skipped
- * otherwise), replaced by
+ * value of pair (c, i, j) is m = the estimate of link i at the point (bounded
+ * network share + core distance) if the point lies in link i's domain (the
+ * pair is skipped otherwise), replaced by
  * the grid value when m < margin (strict) and the point lies in link i's grid
  * box.  A point outside the box keeps m whatever its value, since the grid
  * has no value there (when the box pads the link's bounding box by at least
@@ -424,7 +429,12 @@ int lsdf_mlp_eval(const float* params, const lsdf_mlp_domain* domain, const floa
  * workspace as lsdf_query_min_distance
  * (lsdf_query_workspace_size).  margin may be +inf (every in-box pair takes
  * the grid value) or -inf (none does).  A pair that takes the grid value gets
- * exactly the bits lsdf_query_min_distance would give it. */
+ * exactly the bits lsdf_query_min_distance would give it.  With a finite
+ * bound B_i a first kernel finds, per (c, i), U = the smallest E + B_i over
+ * the in-domain pairs with E - B_i >= margin (pairs that cannot fall back),
+ * and the network is evaluated only for 32-pair tiles holding a pair with
+ * E - B_i <= max(U, margin): every other pair's value exceeds U, so the
+ * per-link minima are those of evaluating every pair. */
 int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t L, const lsdf_grid* grids,
                                 const void* grid_buf, const float* mlp_params, const lsdf_mlp_domain* domains,
                                 float margin, const float* points, int64_t M, float* out_dist, int32_t* out_link,
@@ -434,7 +444,8 @@ int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t L, const
 /* Training.  For each link i, B samples are taken from that link's N
  * samples (link-frame points [L][N][3] with labels [L][N]) through
  * batch_index [L][B] (NULL = the first B), and the mean absolute error of
- * the estimate (network + core distance) over them is differentiated
+ * the estimate (bounded network share + core distance) over them is
+ * differentiated
  * (Sec. IV-B trains with an L1 loss).
  *   lsdf_mlp_loss_grad: loss_out [L] (or NULL), grad_out [L][LSDF_MLP_PARAMS]
  *   lsdf_mlp_train_step: the same, then one Adam step (Kingma & Ba) on

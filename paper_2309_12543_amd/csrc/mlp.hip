@@ -21,12 +21,33 @@ constexpr int kBlocksPerCu = 2;             // 69 KB of LDS per block
 // per CU
 constexpr int kQueryBlock = 768;
 constexpr int kQueryWaves = kQueryBlock / 64;
+constexpr int kTileChunk = 8;               // consecutive 32-pair tiles a wave takes at a time
 
 struct Domain {
     float cen[3];
     float inv[3];    // 1 / half
     float core[3];   // half extents of the core box
+    float bound;     // remainder bound B (+inf: unbounded)
+    float inv_bound; // 1 / B, 0 when B = +inf
 };
+
+// A pair's link-frame point relative to the domain centre (u), its
+// normalised network input (xh) and whether it lies in the domain, from the
+// pose (R, t) and the world point: the same operations in every kernel that
+// decides or evaluates pairs, so that they agree bit for bit.
+__device__ inline bool pair_frame(const float (&R)[9], const float (&tr)[3], const Domain& dm, float x, float y,
+                                  float z, float (&u)[3], float (&xh)[3]) {
+    const float dx = x - tr[0], dy = y - tr[1], dz = z - tr[2];
+    float mx = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float l = fmaf(R[a], dx, fmaf(R[3 + a], dy, R[6 + a] * dz));   // (R^T d)_a
+        u[a] = l - dm.cen[a];
+        xh[a] = u[a] * dm.inv[a];
+        mx = fmaxf(mx, fabsf(xh[a]));
+    }
+    return mx <= 1.0f;
+}
 
 __device__ inline float wave_min(float v) {
 #pragma unroll
@@ -82,7 +103,8 @@ __global__ __launch_bounds__(kBlock) void mlp_eval_kernel(EvalArgs p) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int64_t j = t * TILE + 16 * nt + lane;
-                if (j < p.N) p.out[j] = m[nt] + e[nt];
+                float t;
+                if (j < p.N) p.out[j] = bounded_share(m[nt], p.d.bound, p.d.inv_bound, t) + e[nt];
             }
         }
     }
@@ -100,6 +122,7 @@ struct QueryMlpArgs {
     const void* grid;
     const float* points;
     uint32_t* keys;
+    const float* ubound;     // [C][L] upper bounds U of the first kernel, or NULL (no bound: no skipping)
     int64_t M;
     int64_t tiles_per_link;
     int32_t tiles_per_c;
@@ -115,89 +138,157 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
     __shared__ __bf16 sW2[WTILE_ELEMS];
     __shared__ __bf16 sW3[WTILE_ELEMS];
     __shared__ SmallParams sp;
-    const int i = blockIdx.y;
-    const float* P = p.params + (int64_t)i * NPARAM;
-    stage_weights(sW2, P + OFF_W2, false);
-    stage_weights(sW3, P + OFF_W3, false);
-    stage_small(&sp, P);
-    __syncthreads();
-
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const LinkGrid& lg = p.link[i];
-    const Domain& dm = p.dom[i];
-    const typename GridT<DT>::T* G = static_cast<const typename GridT<DT>::T*>(p.grid) + lg.offset;
-    const int64_t t0 = p.tiles_per_link * blockIdx.x / gridDim.x;
-    const int64_t t1 = p.tiles_per_link * (blockIdx.x + 1) / gridDim.x;
+    // every workgroup takes every link in turn (its weights staged once per
+    // link), and a link's tiles in chunks of kTileChunk consecutive tiles (one
+    // configuration's points, mostly) are dealt round-robin to all waves of
+    // the grid: the tiles a bounded query must evaluate cluster (points near
+    // a link, at configurations near the obstacle, and some links far more
+    // than others), and dealing small chunks over the whole grid spreads them
+    const int64_t waves = (int64_t)gridDim.x * kQueryWaves;
+    const int64_t nchunks = (p.tiles_per_link + kTileChunk - 1) / kTileChunk;
+    for (int i = 0; i < p.L; ++i) {
+        const float* P = p.params + (int64_t)i * NPARAM;
+        __syncthreads();   // every wave is done with the previous link's weights
+        stage_weights(sW2, P + OFF_W2, false);
+        stage_weights(sW3, P + OFF_W3, false);
+        stage_small(&sp, P);
+        __syncthreads();
 
-    float best = INFINITY;
-    int cur = -1;
-    GridMap gm{};
-    float R[9] = {}, tr[3] = {};
-    auto flush = [&](int c) {
-        const float w = wave_min(best);
-        if (lane == 0 && w < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(w));
-        best = INFINITY;
-    };
-    for (int64_t t = t0 + wave; t < t1; t += kQueryWaves) {
-        const int c = (int)(t / p.tiles_per_c);
-        const int64_t j0 = (t - (int64_t)c * p.tiles_per_c) * TILE;
-        if (c != cur) {
-            if (cur >= 0) flush(cur);
-            cur = c;
-            const float* T = p.link_T + ((int64_t)c * p.L + i) * 12;
-            gm = grid_map(lg, T);
-            for (int r = 0; r < 3; ++r) {
-                for (int s = 0; s < 3; ++s) R[3 * r + s] = T[4 * r + s];
-                tr[r] = T[4 * r + 3];
+        const LinkGrid& lg = p.link[i];
+        const Domain& dm = p.dom[i];
+        const typename GridT<DT>::T* G = static_cast<const typename GridT<DT>::T*>(p.grid) + lg.offset;
+        float best = INFINITY;
+        int cur = -1;
+        GridMap gm{};
+        float R[9] = {}, tr[3] = {};
+        float thr = INFINITY;   // tiles whose pairs all have E - B above this are skipped
+        auto flush = [&](int c) {
+            const float w = wave_min(best);
+            if (lane == 0 && w < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(w));
+            best = INFINITY;
+        };
+        for (int64_t ch = (int64_t)blockIdx.x * kQueryWaves + wave; ch < nchunks; ch += waves)
+        for (int64_t t = ch * kTileChunk; t < min((ch + 1) * kTileChunk, p.tiles_per_link); ++t) {
+            const int c = (int)(t / p.tiles_per_c);
+            const int64_t j0 = (t - (int64_t)c * p.tiles_per_c) * TILE;
+            if (c != cur) {
+                if (cur >= 0) flush(cur);
+                cur = c;
+                const float* T = p.link_T + ((int64_t)c * p.L + i) * 12;
+                gm = grid_map(lg, T);
+                for (int r = 0; r < 3; ++r) {
+                    for (int s = 0; s < 3; ++s) R[3 * r + s] = T[4 * r + s];
+                    tr[r] = T[4 * r + 3];
+                }
+                thr = p.ubound ? fmaxf(p.ubound[(int64_t)c * p.L + i], p.margin) : INFINITY;
             }
-        }
-        float xh[NT][3], px[NT][3], e[NT];
-        bool indom[NT];
-        bool any = false;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int64_t j = j0 + 16 * nt + (lane & 15);
-            const int64_t jj = min(j, p.M - 1);
-            const float dx = p.points[3 * jj + 0] - tr[0];
-            const float dy = p.points[3 * jj + 1] - tr[1];
-            const float dz = p.points[3 * jj + 2] - tr[2];
-            px[nt][0] = p.points[3 * jj + 0];
-            px[nt][1] = p.points[3 * jj + 1];
-            px[nt][2] = p.points[3 * jj + 2];
-            float mx = 0.0f, u[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float l = fmaf(R[a], dx, fmaf(R[3 + a], dy, R[6 + a] * dz));   // (R^T d)_a
-                u[a] = l - dm.cen[a];
-                xh[nt][a] = u[a] * dm.inv[a];
-                mx = fmaxf(mx, fabsf(xh[nt][a]));
-            }
-            e[nt] = core_distance(u[0], u[1], u[2], dm.core);
-            indom[nt] = (j < p.M) && (mx <= 1.0f);
-            any |= indom[nt];
-        }
-        if (!__ballot(any)) continue;
-        float m[NT];
-        forward_tile<NT>(sW2, sW3, &sp, xh, m);
-        if (lane < 16) {
+            float xh[NT][3], px[NT][3], e[NT];
+            bool indom[NT];
+            bool any = false;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                if (!indom[nt]) continue;
-                // below the margin the grid's value replaces the estimate; a
-                // point outside the grid box keeps the estimate, since the
-                // grid has no value there
-                const float est = m[nt] + e[nt];
-                float v = est;
-                if (est < p.margin) {
-                    const float g = sample_or_inf<CUBIC, DT>(G, lg, gm, px[nt][0], px[nt][1], px[nt][2]);
-                    if (g < INFINITY) v = g;
+                const int64_t j = j0 + 16 * nt + (lane & 15);
+                const int64_t jj = min(j, p.M - 1);
+                px[nt][0] = p.points[3 * jj + 0];
+                px[nt][1] = p.points[3 * jj + 1];
+                px[nt][2] = p.points[3 * jj + 2];
+                float u[3];
+                const bool in = pair_frame(R, tr, dm, px[nt][0], px[nt][1], px[nt][2], u, xh[nt]);
+                e[nt] = core_distance(u[0], u[1], u[2], dm.core);
+                indom[nt] = (j < p.M) && in;
+                // a pair with E - B above thr cannot hold the minimum (its
+                // value exceeds the upper bound U of some pair that cannot
+                // fall back)
+                any |= indom[nt] && (e[nt] - dm.bound <= thr);
+            }
+            if (!__ballot(any)) continue;
+            float m[NT];
+            forward_tile<NT>(sW2, sW3, &sp, xh, m);
+            if (lane < 16) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    if (!indom[nt]) continue;
+                    // below the margin the grid's value replaces the estimate;
+                    // a point outside the grid box keeps the estimate, since
+                    // the grid has no value there
+                    float tb;
+                    const float est = bounded_share(m[nt], dm.bound, dm.inv_bound, tb) + e[nt];
+                    float v = est;
+                    if (est < p.margin) {
+                        const float g = sample_or_inf<CUBIC, DT>(G, lg, gm, px[nt][0], px[nt][1], px[nt][2]);
+                        if (g < INFINITY) v = g;
+                    }
+                    best = fminf(best, v);
                 }
-                best = fminf(best, v);
             }
         }
+        if (cur >= 0) flush(cur);
     }
-    if (cur >= 0) flush(cur);
+}
+
+// First kernel of a bounded learned query: per (configuration c, link i),
+// U = the smallest E + B over the in-domain pairs with E - B >= margin (pairs
+// whose estimate, at least E - B, cannot fall below the margin and so cannot
+// take the grid's value), +inf if none.  Every such pair's value is at most
+// its E + B, so U bounds the minimum from above, and a pair with E - B > U
+// cannot hold it.  A workgroup takes one link and kBoundConfigs
+// configurations (their poses in scalar registers) and strides over the
+// points; the pair arithmetic is pair_frame's and core_distance's, as in
+// the query.
+constexpr int kBoundBlock = 256;
+constexpr int kBoundConfigs = 4;
+
+struct BoundArgs {
+    Domain dom[LSDF_MAX_LINKS];
+    const float* link_T;
+    const float* points;
+    float* ubound;           // [C][L]
+    int64_t M;
+    int32_t C;
+    int32_t L;
+    float margin;
+};
+
+__global__ __launch_bounds__(kBoundBlock) void mlp_bound_kernel(BoundArgs p) {
+    const int i = blockIdx.y;
+    const int c0 = blockIdx.x * kBoundConfigs;
+    const Domain& dm = p.dom[i];
+    float R[kBoundConfigs][9], tr[kBoundConfigs][3], ub[kBoundConfigs];
+#pragma unroll
+    for (int k = 0; k < kBoundConfigs; ++k) {
+        const int c = min(c0 + k, p.C - 1);
+        const float* T = p.link_T + ((int64_t)c * p.L + i) * 12;
+        for (int r = 0; r < 3; ++r) {
+            for (int s = 0; s < 3; ++s) R[k][3 * r + s] = T[4 * r + s];
+            tr[k][r] = T[4 * r + 3];
+        }
+        ub[k] = INFINITY;
+    }
+    for (int64_t j = threadIdx.x; j < p.M; j += kBoundBlock) {
+        const float x = p.points[3 * j + 0], y = p.points[3 * j + 1], z = p.points[3 * j + 2];
+#pragma unroll
+        for (int k = 0; k < kBoundConfigs; ++k) {
+            float u[3], xh[3];
+            if (!pair_frame(R[k], tr[k], dm, x, y, z, u, xh)) continue;
+            const float e = core_distance(u[0], u[1], u[2], dm.core);
+            if (e - dm.bound >= p.margin) ub[k] = fminf(ub[k], e + dm.bound);
+        }
+    }
+    __shared__ float s_ub[kBoundConfigs][kBoundBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kBoundConfigs; ++k) {
+        const float w = wave_min(ub[k]);
+        if (lane == 0) s_ub[k][wave] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < kBoundConfigs && c0 + (int)threadIdx.x < p.C) {
+        float v = INFINITY;
+        for (int w = 0; w < kBoundBlock / 64; ++w) v = fminf(v, s_ub[threadIdx.x][w]);
+        p.ubound[(int64_t)(c0 + threadIdx.x) * p.L + i] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -359,9 +450,13 @@ __global__ __launch_bounds__(kTrainBlock) void train_fwdbwd_kernel(TrainArgs p) 
             m = part + sp.b4;
         }
     }
-    // loss of the estimate (network + core distance) and its derivative
-    const float r_ = (m + e_core) - p.labels[idx];
-    const float dm = (r_ > 0.0f ? 1.0f : (r_ < 0.0f ? -1.0f : 0.0f)) / (float)B;
+    // loss of the estimate (bounded network share + core distance) and its
+    // derivative with respect to the network's output m
+    float tb;
+    const float share = bounded_share(m, d.bound, d.inv_bound, tb);
+    const float r_ = (share + e_core) - p.labels[idx];
+    float dm = (r_ > 0.0f ? 1.0f : (r_ < 0.0f ? -1.0f : 0.0f)) / (float)B;
+    if (d.inv_bound != 0.0f) dm *= 1.0f - tb * tb;
     float absr = lane < 16 ? fabsf(r_) : 0.0f;
     if (lane < 16) p.w.dm[lB + s_idx] = dm;
     absr = wave_sum(absr);
@@ -604,6 +699,10 @@ int make_domain(const lsdf_mlp_domain& d, int index, Domain* out) {
         out->inv[a] = (float)(1.0 / (double)d.half[a]);
         out->core[a] = d.core_half[a];
     }
+    if (!(d.bound > 0.0f))   // NaN, zero or negative; +inf is allowed
+        return fail(LSDF_E_INVALID_ARG, "mlp domain %d: bound must be > 0 (or +inf)", index);
+    out->bound = d.bound;
+    out->inv_bound = std::isinf(d.bound) ? 0.0f : (float)(1.0 / (double)d.bound);
     return LSDF_OK;
 }
 
@@ -778,11 +877,31 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
     if (a.tiles_per_link > 0) {
         const int cus = device_cus();
         if (cus <= 0) return fail(LSDF_E_DEVICE, "query_mlp: cannot read the device's compute-unit count");
-        // one round of workgroups: as many per link as leave no CU with two
-        const int64_t per_link = std::max<int64_t>(
-            1, std::min<int64_t>((int64_t)cus / L, (a.tiles_per_link + kQueryWaves - 1) / kQueryWaves));
-        const dim3 grid((unsigned)per_link, L);
+        // one workgroup per CU (each takes every link in turn), no more than
+        // the chunks of one link need
+        const int64_t chunks = (a.tiles_per_link + kTileChunk - 1) / kTileChunk;
+        const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(cus, (chunks + kQueryWaves - 1) / kQueryWaves)));
         if ((rc = launch_zero_words(a.keys, (int64_t)C * L, s)) != LSDF_OK) return rc;
+        bool bounded = false;
+        for (int i = 0; i < L; ++i) bounded = bounded || a.dom[i].inv_bound != 0.0f;
+        if (bounded) {
+            // the upper bounds, after the keys in the workspace (which holds
+            // the plain query's tables too, far more than C L words)
+            float* ub = reinterpret_cast<float*>(static_cast<char*>(workspace) + ((size_t)C * L * 4 + 255) / 256 * 256);
+            BoundArgs b{};
+            for (int i = 0; i < L; ++i) b.dom[i] = a.dom[i];
+            b.link_T = link_T;
+            b.points = points;
+            b.ubound = ub;
+            b.M = M;
+            b.C = C;
+            b.L = L;
+            b.margin = margin;
+            hipLaunchKernelGGL(mlp_bound_kernel, dim3((unsigned)((C + kBoundConfigs - 1) / kBoundConfigs), L),
+                               dim3(kBoundBlock), 0, s, b);
+            if ((rc = check_launch("query_min_distance_mlp bounds")) != LSDF_OK) return rc;
+            a.ubound = ub;
+        }
         hipEvent_t ev0, ev1;
         take_kernel_events(&ev0, &ev1);
         if (ev0 && hipEventRecord(ev0, s) != hipSuccess) return fail(LSDF_E_DEVICE, "query_mlp: event record failed");

@@ -4,8 +4,10 @@
 // widths 3 -> 128 -> 128 -> 128 -> 1, SiLU(z) = z / (1 + exp(-z)), input the
 // link-frame point normalised to the link's domain.  FP32 master parameters,
 // [W1 128x3 | b1 | W2 128x128 | b2 | W3 128x128 | b3 | w4 | b4] (33665).
-// The estimate of the link's signed distance is m plus the distance from the
-// point to the link's core box (its mesh's bounding box, core_distance).
+// The estimate of the link's signed distance is the network's share
+// (bounded_share: m, or B tanh(m / B) with the link's remainder bound B) plus
+// the distance from the point to the link's core box (its mesh's bounding
+// box, core_distance).
 //
 // Precision: W1, W2, W3, w4 are used as bfloat16 (round to nearest even);
 // the input layer runs on the VALU in FP32 (bfloat16 coordinates would be
@@ -87,6 +89,19 @@ __device__ inline float sigmoid(float z) {
 }
 
 __device__ inline float silu(float z) { return z * sigmoid(z); }
+
+// The network's share of the estimate: b t with t = tanh(m / b), evaluated
+// as clamp(1 - 2 / (1 + exp(2 m inv_b)), -1, 1) (so |share| <= b exactly),
+// inv_b = 1 / b; inv_b = 0 stands for b = +inf: the share is m, t = 0.
+__device__ inline float bounded_share(float m, float b, float inv_b, float& t) {
+    if (inv_b == 0.0f) {
+        t = 0.0f;
+        return m;
+    }
+    const float e = __builtin_amdgcn_exp2f((m * inv_b) * 2.88539008177792681472f);
+    t = fminf(fmaxf(1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + e), -1.0f), 1.0f);
+    return b * t;
+}
 
 __device__ inline float silu_grad_of(float z, float s) { return s * (1.0f + z * (1.0f - s)); }
 

@@ -21,16 +21,21 @@ from . import lsdf
 # A first phase of 1200 epochs over the samples, the learning rate decayed by
 # a cosine from 4e-3 to 4e-5; then two rounds that each add the 1/16 of the
 # samples the network fits worst (among those at least 3 cm from the
-# surface, where its answers are used) four more times and train 600 epochs
+# surface, where its answers are used) four more times and train 800 epochs
 # over the enlarged set, at 1.5e-3 and then 1e-3 decayed a hundredfold.
 BATCH = 8192
 EPOCHS = 1200
 LR = 4e-3
 LR_FINAL = 4e-5
-MINE_ROUNDS = ((1.5e-3, 600), (1e-3, 600))
+MINE_ROUNDS = ((1.5e-3, 800), (1e-3, 800))
 MINE_FRACTION = 1 / 16
 MINE_REPEAT = 4
 MINE_MIN_LABEL = 0.03
+# The remainder bound of each link's network: 1.25 times the largest
+# |label - E| over its training samples (E the distance to the core box),
+# rounded up to whole centimetres.
+BOUND_FACTOR = 1.25
+BOUND_QUANTUM = 0.01
 
 
 def labels_for_samples(meshes, grids: lsdf.GridSet, samples: torch.Tensor) -> torch.Tensor:
@@ -82,15 +87,39 @@ def train(params: torch.Tensor, domains, samples: torch.Tensor, labels: torch.Te
     return np.array(history)
 
 
+def _domain_arrays(domains, L):
+    """(centre, half, core_half, bound) as float32 arrays [L][3], [L][3],
+    [L][3], [L] from a 3- or 4-tuple (no bound: +inf)."""
+    cen, half, core = (np.asarray(a, dtype=np.float32).reshape(L, 3) for a in domains[:3])
+    bound = np.broadcast_to(np.asarray(domains[3] if len(domains) > 3 else np.inf, dtype=np.float32), (L,))
+    return cen, half, core, np.ascontiguousarray(bound)
+
+
+def remainder_bounds(domains, samples: torch.Tensor, labels: torch.Tensor) -> np.ndarray:
+    """Per link, the remainder bound B of the recipe: BOUND_FACTOR times the
+    largest |label - E| over the link's samples, rounded up to BOUND_QUANTUM
+    (E from the library's own evaluation: a zero network gives E exactly)."""
+    L, N = int(samples.shape[0]), int(samples.shape[1])
+    cen, half, core, _ = _domain_arrays(domains, L)
+    zero = torch.zeros(lsdf.LSDF_MLP_PARAMS, dtype=torch.float32, device=samples.device)
+    E = torch.empty(N, dtype=torch.float32, device=samples.device)
+    out = np.empty(L)
+    for i in range(L):
+        lsdf.mlp_eval(zero, (cen[i], half[i], core[i]), samples[i], out=E)
+        r = float((labels[i] - E).abs().max())
+        out[i] = math.ceil(BOUND_FACTOR * r / BOUND_QUANTUM) * BOUND_QUANTUM
+    return out
+
+
 def fit(params: torch.Tensor, domains, samples: torch.Tensor, labels: torch.Tensor, *, log_every: int = 0,
         log=print):
     """The library's training recipe (constants above) on every link's
-    network at once; domains = (centre, half, core_half) arrays [L][3];
-    params [L][33665] is updated in place.  Returns the
+    network at once; domains = (centre, half, core_half[, bound]) arrays
+    [L][3] (and [L]); params [L][33665] is updated in place.  Returns the
     per-epoch mean loss [epochs][L] of all phases."""
     L, N = int(samples.shape[0]), int(samples.shape[1])
-    cen, half, core = (np.asarray(a, dtype=np.float32).reshape(L, 3) for a in domains)
-    doms = lsdf.make_domains(cen, half, core)
+    cen, half, core, bound = _domain_arrays(domains, L)
+    doms = lsdf.make_domains(cen, half, core, bound)
     hist = [train(params, doms, samples, labels, epochs=EPOCHS, batch=BATCH, lr=LR, lr_final=LR_FINAL,
                   log_every=log_every, log=log)]
     k = int(N * MINE_FRACTION)
@@ -98,7 +127,7 @@ def fit(params: torch.Tensor, domains, samples: torch.Tensor, labels: torch.Tens
     for r, (lr, epochs) in enumerate(MINE_ROUNDS):
         grown_s, grown_y = [], []
         for i in range(L):
-            lsdf.mlp_eval(params[i], (cen[i], half[i], core[i]), samples[i], out=est)
+            lsdf.mlp_eval(params[i], (cen[i], half[i], core[i], bound[i]), samples[i], out=est)
             err = torch.where(labels[i] >= MINE_MIN_LABEL, (est - labels[i]).abs(), torch.zeros_like(est))
             worst = torch.topk(err, k).indices
             grown_s.append(torch.cat([samples[i]] + [samples[i][worst]] * MINE_REPEAT))

@@ -42,7 +42,8 @@ class lsdf_grid(ct.Structure):
 
 
 class lsdf_mlp_domain(ct.Structure):
-    _fields_ = [("centre", ct.c_float * 3), ("half", ct.c_float * 3), ("core_half", ct.c_float * 3)]
+    _fields_ = [("centre", ct.c_float * 3), ("half", ct.c_float * 3), ("core_half", ct.c_float * 3),
+                ("bound", ct.c_float)]
 
 
 LSDF_SCHED_DEFAULT, LSDF_SCHED_XCD_SLICES, LSDF_SCHED_INTERLEAVED = 0, 1, 2
@@ -709,27 +710,30 @@ def build_robot_grids(meshes, lo, hi, n, device="cuda", stream=None, dtype=torch
 # learned per-link SDF surrogate
 # ---------------------------------------------------------------------------
 
-def make_domains(centre, half, core_half):
+def make_domains(centre, half, core_half, bound=float("inf")):
     """ctypes array of lsdf_mlp_domain from [L][3] centres, half extents of
-    the network domains and half extents of the core boxes."""
+    the network domains and half extents of the core boxes, and the remainder
+    bounds (a scalar or [L]; +inf: the network's share unbounded)."""
     centre = np.asarray(centre, dtype=np.float32).reshape(-1, 3)
     half = np.asarray(half, dtype=np.float32).reshape(-1, 3)
     core = np.asarray(core_half, dtype=np.float32).reshape(-1, 3)
     if half.shape != centre.shape or core.shape != centre.shape:
         raise ValueError("centre, half and core_half must all be [L][3]")
+    bd = np.broadcast_to(np.asarray(bound, dtype=np.float32), (centre.shape[0],))
     arr = (lsdf_mlp_domain * centre.shape[0])()
     for i in range(centre.shape[0]):
         for a in range(3):
             arr[i].centre[a] = float(centre[i, a])
             arr[i].half[a] = float(half[i, a])
             arr[i].core_half[a] = float(core[i, a])
+        arr[i].bound = float(bd[i])
     return arr
 
 
 def mlp_eval(params: torch.Tensor, domain, points: torch.Tensor, out=None, stream=None) -> torch.Tensor:
-    """The surrogate's estimates (network + core distance) of one link at
-    link-frame points [N][3] (lsdf_mlp_eval); domain = (centre, half,
-    core_half) or a one-element lsdf_mlp_domain array."""
+    """The surrogate's estimates (bounded network share + core distance) of
+    one link at link-frame points [N][3] (lsdf_mlp_eval); domain = (centre,
+    half, core_half[, bound]) or a one-element lsdf_mlp_domain array."""
     lib = load_library()
     _require(params, "params", torch.float32, (LSDF_MLP_PARAMS,))
     if points.dim() != 2 or points.shape[1] != 3:

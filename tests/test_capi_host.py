@@ -167,6 +167,12 @@ def test_mlp_argument_errors(lib):
     assert lib.lsdf_mlp_eval(FAKE, bad, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG
     assert lib.lsdf_mlp_eval(FAKE, bad_core, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG
     assert lib.lsdf_mlp_eval(FAKE, nan_core, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG
+    for bad_bound in (0.0, -0.1, float("nan")):   # the remainder bound: > 0 or +inf
+        d = B.make_domains([[0, 0, 0]], [[1, 1, 1]], [[0, 0, 0]], bad_bound)
+        assert lib.lsdf_mlp_eval(FAKE, d, FAKE, 10, FAKE, None) == B.LSDF_E_INVALID_ARG, bad_bound
+    for ok_bound in (0.05, float("inf")):
+        d = B.make_domains([[0, 0, 0]], [[1, 1, 1]], [[0, 0, 0]], ok_bound)
+        assert lib.lsdf_mlp_eval(FAKE, d, FAKE, 0, FAKE, None) == B.LSDF_OK, ok_bound
     assert lib.lsdf_mlp_eval(FAKE, dom, FAKE, -1, FAKE, None) == B.LSDF_E_SHAPE
     assert lib.lsdf_mlp_eval(FAKE, dom, FAKE, 0, FAKE, None) == B.LSDF_OK
     # training: B not a multiple of 512, NULL moments, t = 0, workspace too small or misaligned

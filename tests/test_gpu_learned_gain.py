@@ -6,8 +6,9 @@ grown by a 5 cm pad; the paper sizes this range in Sec. III-A and IV-C), and
 a point outside every box contributes nothing, so a link with no point in its
 box reports +inf ("at least the pad away").  The network's domain reaches
 1 m past the box, so the learned query gives a finite clearance there.  The
-estimate is the network plus the distance to the link's core box (its mesh's
-bounding box).  The networks are trained on the GPU by the library's own
+estimate is the distance to the link's core box (its mesh's bounding box)
+plus the network's share, bounded by the link's remainder bound (so that
+the query skips, exactly, the points that cannot hold a minimum).  The networks are trained on the GPU by the library's own
 kernels (labels, forward, backward, Adam) with the library's recipe
 (learned.fit), and judged against the oracle's exact field: the grid value
 inside the box, the brute-force mesh distance outside it (orc_judge_min).
@@ -47,20 +48,22 @@ def trained():
                                   for i, m in enumerate(w.robot.links)]).astype(np.float32), device=dev)
     say(f"training 7 networks on {SAMPLES} samples each with the library's recipe")
     labels = learned.labels_for_samples(w.robot.links, gs, S)
+    bound = learned.remainder_bounds((cen, half, core), S, labels)
+    say(f"remainder bounds (m): {np.round(bound, 3).tolist()}")
     params = torch.as_tensor(synth.mlp_init(w.L, synth.BASE_SEED + 5).astype(np.float32), device=dev)
-    hist = learned.fit(params, (cen, half, core), S, labels, log_every=300, log=say)
+    hist = learned.fit(params, (cen, half, core, bound), S, labels, log_every=400, log=say)
     torch.cuda.synchronize()
-    return w, gs, params, cen, half, core, hist
+    return w, gs, params, cen, half, (core, bound), hist
 
 
 def test_trained_network_answers_beyond_the_grid_box(orc, trained):
     from paper_2309_12543_amd import lsdf
-    w, gs, params, cen, half, core, hist = trained
+    w, gs, params, cen, half, (core, bound), hist = trained
     dev = params.device
     T = lsdf.fk_batch(w.robot.dh, torch.as_tensor(w.q, dtype=torch.float32, device=dev), base_T=w.robot.base_T)
     pts = torch.as_tensor(w.points, dtype=torch.float32, device=dev)
     lg = lsdf.query_min_distance(T, gs, pts, link_dist=True)[2].cpu().numpy().astype(np.float64)
-    lm = lsdf.query_min_distance_mlp(T, gs, params, (cen, half, core), pts, margin=MARGIN,
+    lm = lsdf.query_min_distance_mlp(T, gs, params, (cen, half, core, bound), pts, margin=MARGIN,
                                      link_dist=True)[2].cpu().numpy().astype(np.float64)
     sel = np.arange(0, w.C, 5)
     say(f"judging {len(sel)} waypoints with the oracle")

@@ -56,34 +56,43 @@ def normalise(points, cen, half):
     return ((points.astype(np.float32) - cen.astype(np.float32)) * inv).astype(np.float64)
 
 
-def test_mlp_eval_matches_twin(B, orc, tiny):
-    """Estimates (network + core distance) over the whole domain against the
-    oracle's bfloat16 twin and its double network, each plus the oracle's
-    core distance in double."""
+@pytest.mark.parametrize("bound", [np.inf, 0.2])
+def test_mlp_eval_matches_twin(B, orc, tiny, bound):
+    """Estimates (the network's share, unbounded or bounded by 0.2, plus the
+    core distance) over the whole domain against the oracle's bfloat16 twin
+    and its double network, each plus the oracle's core distance in double."""
     cen, half, core = domains_of(tiny)
     P = params_f32(1, 0)[0]
     rng = np.random.default_rng(40)
     pts = rng.uniform(cen[2] - half[2], cen[2] + half[2], size=(3001, 3)).astype(np.float32)
     say("mlp_eval N=3001")
-    got = B.mlp_eval(dev(P), (cen[2:3], half[2:3], core[2:3]), dev(pts)).cpu().numpy().astype(np.float64)
+    got = B.mlp_eval(dev(P), (cen[2:3], half[2:3], core[2:3], bound), dev(pts)).cpu().numpy().astype(np.float64)
     torch.cuda.synchronize()
     p64 = pts.astype(np.float64)
-    twin = orc.mlp_value(P.astype(np.float64), p64, cen[2], half[2], core[2], bf16=True)
-    full = orc.mlp_value(P.astype(np.float64), p64, cen[2], half[2], core[2], bf16=False)
+    twin = orc.mlp_value(P.astype(np.float64), p64, cen[2], half[2], core[2], bf16=True, bound=bound)
+    full = orc.mlp_value(P.astype(np.float64), p64, cen[2], half[2], core[2], bf16=False, bound=bound)
     E = orc.mlp_value(np.zeros_like(P, dtype=np.float64), p64, cen[2], half[2], core[2])
     assert (E > 0.3).mean() > 0.5                                   # the core term is exercised
-    scale = max(1.0, np.abs(twin - E).max())
+    # a GPU-twin difference inside the network scales with the unbounded
+    # output, and a bounded share moves by at most as much
+    raw = orc.mlp_value(P.astype(np.float64), p64, cen[2], half[2], core[2], bf16=True)
+    scale = max(1.0, np.abs(raw - E).max())
     e_twin, e_full = np.abs(got - twin).max(), np.abs(got - full).max()
     say(f"max |gpu - bf16 twin| = {e_twin:.3g}, max |gpu - double net| = {e_full:.3g}, network output scale "
         f"{scale:.3g}, core distance up to {E.max():.3f} m")
     assert e_twin <= TOL_EVAL * scale
     assert e_full <= 5e-2 * scale
+    if np.isfinite(bound):
+        assert np.all(np.abs(got - E) <= bound * (1 + 1e-6))         # the share never exceeds its bound
+        assert (np.abs(twin - E) > 0.5 * bound).mean() > 0.1        # and the bound is reached
     # the core term alone: a zero network gives the FP32 core distance
-    z = B.mlp_eval(dev(np.zeros_like(P)), (cen[2:3], half[2:3], core[2:3]), dev(pts)).cpu().numpy().astype(np.float64)
+    z = B.mlp_eval(dev(np.zeros_like(P)), (cen[2:3], half[2:3], core[2:3], bound),
+                   dev(pts)).cpu().numpy().astype(np.float64)
     assert np.abs(z - E).max() <= 4e-7 * max(1.0, E.max())
 
 
-def test_mlp_loss_grad_matches_twin(B, orc, tiny):
+@pytest.mark.parametrize("bound", [np.inf, 0.3])
+def test_mlp_loss_grad_matches_twin(B, orc, tiny, bound):
     cen, half, core = domains_of(tiny)
     L, N, Bt = 2, 1536, 1024
     P = params_f32(L, 1)
@@ -94,17 +103,19 @@ def test_mlp_loss_grad_matches_twin(B, orc, tiny):
     E = [orc.mlp_value(np.zeros(P.shape[1]), samples[i].astype(np.float64), cen[i], half[i], core[i])
          for i in range(L)]
     # labels 0.3 away from the estimates, so that sign(m - y) is the same everywhere
-    labels = np.stack([orc.mlp_forward(P[i].astype(np.float64), X[i], bf16=True) + E[i]
-                       + rng.choice([-0.3, 0.3], size=N) for i in range(L)]).astype(np.float32)
+    share = [orc.mlp_forward(P[i].astype(np.float64), X[i], bf16=True) for i in range(L)]
+    if np.isfinite(bound):
+        share = [bound * np.tanh(v / bound) for v in share]
+    labels = np.stack([share[i] + E[i] + rng.choice([-0.3, 0.3], size=N) for i in range(L)]).astype(np.float32)
     bidx = np.stack([rng.permutation(N)[:Bt] for _ in range(L)]).astype(np.int32)
     say(f"mlp_loss_grad L={L} N={N} B={Bt}")
-    loss, grad = B.mlp_loss_grad(dev(P), (cen[:L], half[:L], core[:L]), dev(samples), dev(labels), Bt,
+    loss, grad = B.mlp_loss_grad(dev(P), (cen[:L], half[:L], core[:L], bound), dev(samples), dev(labels), Bt,
                                  dev(bidx, torch.int32))
     loss, grad = loss.cpu().numpy().astype(np.float64), grad.cpu().numpy().astype(np.float64)
     for i in range(L):
         Xi, Yi, Ei = X[i][bidx[i]], labels[i][bidx[i]].astype(np.float64), E[i][bidx[i]]
-        l_twin, g_twin = orc.mlp_loss_grad(P[i].astype(np.float64), Xi, Yi, bf16=True, offset=Ei)
-        l_full, g_full = orc.mlp_loss_grad(P[i].astype(np.float64), Xi, Yi, bf16=False, offset=Ei)
+        l_twin, g_twin = orc.mlp_loss_grad(P[i].astype(np.float64), Xi, Yi, bf16=True, offset=Ei, bound=bound)
+        l_full, g_full = orc.mlp_loss_grad(P[i].astype(np.float64), Xi, Yi, bf16=False, offset=Ei, bound=bound)
         cos_t = g_twin @ grad[i] / np.linalg.norm(g_twin) / np.linalg.norm(grad[i])
         cos_f = g_full @ grad[i] / np.linalg.norm(g_full) / np.linalg.norm(grad[i])
         rel_t = np.abs(grad[i] - g_twin).max() / np.abs(g_twin).max()
@@ -277,6 +288,17 @@ def _shift_to_margin(orc, w, T32, pts, P, cen, half, core, margin, q=0.4, s=1.0)
     return P, tol
 
 
+def _bounded_tol(tol_raw, net, bound):
+    """Per-pair tolerance of a bounded share B tanh(net / B) from the
+    tolerance tol_raw of the network's output net: the share moves by at
+    most its largest slope over [net - tol_raw, net + tol_raw] times
+    tol_raw, plus the FP32 evaluation of tanh."""
+    if not np.isfinite(bound):
+        return tol_raw
+    near0 = np.sign(net) * np.maximum(np.abs(net) - tol_raw, 0.0)
+    return tol_raw * (1.0 - np.tanh(near0 / bound) ** 2) + 1e-6
+
+
 def _pair_intervals(em, eg, sure, maybe, margin, tol):
     """Per pair, the interval [lo, hi] of values the learned query may give:
     the oracle decides with the twin network's m, the GPU with its own m
@@ -360,12 +382,15 @@ def _check_minima(ld, lo, hi, where):
     return int(exact.sum())
 
 
-def test_query_mlp_finite_margin_minima_match_oracle(B, orc, tiny, tiny_grids):
+@pytest.mark.parametrize("bound", [np.inf, 0.03])
+def test_query_mlp_finite_margin_minima_match_oracle(B, orc, tiny, tiny_grids, bound):
     """Margin 5 cm, every point of the tiny workload in one call, with a
     random network whose output is scaled to vary a few centimetres around
     the margin: some per-link minima are decided by a grid value (then they
     are that value exactly), others by a network value, and every one must
-    lie within the oracle's per-pair intervals."""
+    lie within the oracle's per-pair intervals.  The oracle evaluates every
+    pair; with a finite bound the GPU skips the tiles that cannot hold a
+    minimum, so equal minima show that the skipping is exact."""
     sel = np.arange(0, tiny.C, 5)
     T32 = _poses(orc, tiny, sel)
     cen, half, core = domains_of(tiny)
@@ -374,27 +399,40 @@ def test_query_mlp_finite_margin_minima_match_oracle(B, orc, tiny, tiny_grids):
     gs = _grid_set(B, tiny, tiny_grids)
     margin = 0.05
     P, tolf = _shift_to_margin(orc, tiny, T32, pts[:300], params_f32(7, 8), cen, half, core, margin, q=0.5, s=0.05)
+    bounds = None if np.isinf(bound) else np.full(tiny.L, bound)
+    _, em_raw, _ = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P.astype(np.float64), cen,
+                                 half, margin, each=True, core_k=core)
     _, em, eg = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P.astype(np.float64), cen, half,
-                              margin, each=True, core_k=core)
+                              margin, each=True, core_k=core, bounds=bounds)
     E = _core_each(orc, tiny, T32, pts, cen, half, core)
     sure, maybe = _domain_bands(T32, cen, half, pts)
-    say(f"query_mlp margin={margin} C={len(sel)} M={tiny.M}")
-    ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half, core), dev(pts), margin=margin,
+    say(f"query_mlp margin={margin} bound={bound} C={len(sel)} M={tiny.M}")
+    ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half, core, bound), dev(pts), margin=margin,
                                   link_dist=True)[2].cpu().numpy().astype(np.float64)
-    tol = tolf(em, E)
+    tol = _bounded_tol(tolf(em_raw, E), em_raw - E, bound)
     lo, hi = _pair_intervals(em, eg, sure, maybe, margin, tol)
     n_exact = _check_minima(ld, lo, hi, "tiny")
     n_net = int((np.isfinite(hi.min(-1)) & (lo.min(-1) < hi.min(-1))).sum())
     say(f"  {n_exact} of {ld.size} minima decided by a grid pair (exact), {n_net} by network values")
     assert n_exact > 0 and n_net > 0
+    if np.isfinite(bound):
+        # the pairs the GPU may skip: E - B above the smallest E + B of the
+        # pairs that cannot fall back (the first kernel's bound), in double
+        nf = sure & (E - bound >= margin)
+        U = np.where(nf, E + bound, np.inf).min(-1, keepdims=True)
+        skippable = sure & (E - bound > np.maximum(U, margin))
+        say(f"  {skippable.sum() / sure.sum():.2f} of the in-domain pairs lie beyond the skipping bound")
+        assert skippable.sum() > 0.3 * sure.sum()
 
 
-def test_query_mlp_finite_margin_learned_scale_sampled(B, orc):
+@pytest.mark.parametrize("bound", [np.inf, 0.1])
+def test_query_mlp_finite_margin_learned_scale_sampled(B, orc, bound):
     """The learned workload at full size (500 waypoints x 100,000 points x 7
     links) at margin 5 cm in the benchmark's launch configuration, with a
-    random network scaled to vary a few centimetres around the margin:
-    sampled per-link minima against the oracle's per-pair intervals over all
-    100,000 points of that link."""
+    random network scaled to vary a few centimetres around the margin,
+    unbounded and bounded (the GPU then skips the tiles that cannot hold a
+    minimum): sampled per-link minima against the oracle's per-pair intervals
+    over all 100,000 points of that link."""
     w = synth.make_workload("learned")
     cen, half, core = domains_of(w)
     g32 = [g.astype(np.float32) for g in orc.workload_grids(w)]
@@ -404,20 +442,23 @@ def test_query_mlp_finite_margin_learned_scale_sampled(B, orc):
     margin = 0.05
     s = 0.05
     P, tolf = _shift_to_margin(orc, w, T32[::100], pts[::50], params_f32(7, 9), cen, half, core, margin, q=0.5, s=s)
-    say(f"query_mlp learned scale C={w.C} M={w.M} margin={margin}")
-    ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half, core), dev(pts), margin=margin,
+    say(f"query_mlp learned scale C={w.C} M={w.M} margin={margin} bound={bound}")
+    ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half, core, bound), dev(pts), margin=margin,
                                   link_dist=True)[2].cpu().numpy().astype(np.float64)
     n_exact = 0
     for c, i in [(0, 1), (123, 4), (250, 0), (377, 6), (499, 3)]:
         Tci = T32[c:c + 1, i:i + 1]
-        _, em, eg = orc.query_mlp(Tci, w.grid_lo[i:i + 1], w.grid_hi[i:i + 1], w.grid_n[i:i + 1], [g32[i]], pts,
-                                  P[i:i + 1].astype(np.float64), cen[i:i + 1], half[i:i + 1], margin, each=True,
-                                  core_k=core[i:i + 1])
-        _, E, _ = orc.query_mlp(Tci, w.grid_lo[i:i + 1], w.grid_hi[i:i + 1], w.grid_n[i:i + 1], [g32[i]], pts,
-                                np.zeros((1, P.shape[1])), cen[i:i + 1], half[i:i + 1], -np.inf, each=True,
+        args = (Tci, w.grid_lo[i:i + 1], w.grid_hi[i:i + 1], w.grid_n[i:i + 1], [g32[i]], pts)
+        bnd = None if np.isinf(bound) else [bound]
+        _, em, eg = orc.query_mlp(*args, P[i:i + 1].astype(np.float64), cen[i:i + 1], half[i:i + 1], margin,
+                                  each=True, core_k=core[i:i + 1], bounds=bnd)
+        _, em_raw, _ = orc.query_mlp(*args, P[i:i + 1].astype(np.float64), cen[i:i + 1], half[i:i + 1], margin,
+                                     each=True, core_k=core[i:i + 1])
+        _, E, _ = orc.query_mlp(*args, np.zeros((1, P.shape[1])), cen[i:i + 1], half[i:i + 1], -np.inf, each=True,
                                 core_k=core[i:i + 1])
         sure, maybe = _domain_bands(Tci, cen[i:i + 1], half[i:i + 1], pts)
-        tol = TOL_EVAL * np.maximum(s, np.abs(em - E - np.float64(P[i, -1]))) + 1e-6
+        tol = _bounded_tol(TOL_EVAL * np.maximum(s, np.abs(em_raw - E - np.float64(P[i, -1]))) + 1e-6, em_raw - E,
+                           bound)
         lo, hi = _pair_intervals(em, eg, sure, maybe, margin, tol)
         below = (em < margin) & sure
         say(f"  c={c} link={i}: {sure.sum()} in-domain pairs, {(below & np.isfinite(eg)).sum()} take the grid, "
