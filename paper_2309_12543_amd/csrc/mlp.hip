@@ -21,7 +21,8 @@ constexpr int kBlocksPerCu = 2;             // 69 KB of LDS per block
 // per CU
 constexpr int kQueryBlock = 768;
 constexpr int kQueryWaves = kQueryBlock / 64;
-constexpr int kTileChunk = 8;               // consecutive 32-pair tiles a wave takes at a time
+constexpr int kTileChunk = 8;               // 32-pair tiles a wave takes at a time: 256 points of one configuration
+constexpr int kChunkPts = kTileChunk * TILE;
 
 struct Domain {
     float cen[3];
@@ -47,6 +48,16 @@ __device__ inline bool pair_frame(const float (&R)[9], const float (&tr)[3], con
         mx = fmaxf(mx, fabsf(xh[a]));
     }
     return mx <= 1.0f;
+}
+
+// Whether every point of sphere (x, y, z, radius) has E - B above thr at this
+// pose: E at the centre (pair_frame's and core_distance's arithmetic) less
+// the radius, less B, above thr.
+__device__ inline bool sphere_beyond(const float4& sph, const float (&R)[9], const float (&tr)[3], const Domain& dm,
+                                     float thr) {
+    float u[3], xh[3];
+    pair_frame(R, tr, dm, sph.x, sph.y, sph.z, u, xh);
+    return (core_distance(u[0], u[1], u[2], dm.core) - sph.w) - dm.bound > thr;
 }
 
 __device__ inline float wave_min(float v) {
@@ -123,6 +134,8 @@ struct QueryMlpArgs {
     const float* points;
     uint32_t* keys;
     const float* ubound;     // [C][L] upper bounds U of the first kernel, or NULL (no bound: no skipping)
+    const float4* tile_sph;  // [ceil(M / 32)] spheres bounding each tile's points (when ubound != NULL)
+    const float4* chunk_sph; // [ceil(M / 256)] spheres bounding each chunk's points
     int64_t M;
     int64_t tiles_per_link;
     int32_t tiles_per_c;
@@ -141,16 +154,19 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // every workgroup takes every link in turn (its weights staged once per
-    // link), and a link's tiles in chunks of kTileChunk consecutive tiles (one
-    // configuration's points, mostly) are dealt round-robin to all waves of
-    // the grid: the tiles a bounded query must evaluate cluster (points near
-    // a link, at configurations near the obstacle, and some links far more
-    // than others), and dealing small chunks over the whole grid spreads them
-    const int64_t waves = (int64_t)gridDim.x * kQueryWaves;
-    const int64_t nchunks = (p.tiles_per_link + kTileChunk - 1) / kTileChunk;
+    // link); a link's chunks (kTileChunk tiles, 256 points of one
+    // configuration) are dealt round-robin to the workgroups, and a
+    // workgroup's waves take its chunks one at a time from a counter in LDS:
+    // the tiles a bounded query must evaluate cluster (points near a link, at
+    // configurations near the obstacle), so a fixed share per wave would
+    // leave the workgroup waiting on its busiest wave at every link
+    __shared__ int s_next;
+    const int64_t groups = (p.M + kChunkPts - 1) / kChunkPts;   // chunks per configuration
+    const int64_t nchunks = (int64_t)p.C * groups;
     for (int i = 0; i < p.L; ++i) {
         const float* P = p.params + (int64_t)i * NPARAM;
-        __syncthreads();   // every wave is done with the previous link's weights
+        __syncthreads();   // every wave is done with the previous link's weights and chunks
+        if (threadIdx.x == 0) s_next = 0;
         stage_weights(sW2, P + OFF_W2, false);
         stage_weights(sW3, P + OFF_W3, false);
         stage_small(&sp, P);
@@ -169,10 +185,14 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
             if (lane == 0 && w < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(w));
             best = INFINITY;
         };
-        for (int64_t ch = (int64_t)blockIdx.x * kQueryWaves + wave; ch < nchunks; ch += waves)
-        for (int64_t t = ch * kTileChunk; t < min((ch + 1) * kTileChunk, p.tiles_per_link); ++t) {
-            const int c = (int)(t / p.tiles_per_c);
-            const int64_t j0 = (t - (int64_t)c * p.tiles_per_c) * TILE;
+        for (;;) {
+            int slot = 0;
+            if (lane == 0) slot = atomicAdd(&s_next, 1);
+            slot = __builtin_amdgcn_readfirstlane(__shfl(slot, 0, 64));
+            const int64_t ch = (int64_t)blockIdx.x + (int64_t)slot * gridDim.x;
+            if (ch >= nchunks) break;
+            const int c = (int)(ch / groups);
+            const int64_t grp = ch - (int64_t)c * groups;
             if (c != cur) {
                 if (cur >= 0) flush(cur);
                 cur = c;
@@ -184,6 +204,14 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
                 }
                 thr = p.ubound ? fmaxf(p.ubound[(int64_t)c * p.L + i], p.margin) : INFINITY;
             }
+            // a chunk (then a tile) whose bounding sphere keeps every pair's
+            // E - B above thr is skipped whole: E is 1-Lipschitz in the
+            // link-frame point, so E >= E(centre) - radius over the sphere
+            // (the radius is widened far beyond the FP32 rounding of E)
+            if (p.ubound && sphere_beyond(p.chunk_sph[grp], R, tr, dm, thr)) continue;
+        for (int64_t k = grp * kTileChunk; k < min((grp + 1) * kTileChunk, (int64_t)p.tiles_per_c); ++k) {
+            if (p.ubound && sphere_beyond(p.tile_sph[k], R, tr, dm, thr)) continue;
+            const int64_t j0 = k * TILE;
             float xh[NT][3], px[NT][3], e[NT];
             bool indom[NT];
             bool any = false;
@@ -224,8 +252,56 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
                 }
             }
         }
+        }
         if (cur >= 0) flush(cur);
     }
+}
+
+// Bounding spheres of the learned query's point tiles (32 points) and chunks
+// (256 points), one thread per tile: the centre of the points' box and the
+// largest distance to it, widened by a relative 1e-5 and by 1e-4 m, which
+// covers the FP32 rounding of the pose and of E (about 1e-6 m on clouds a few
+// metres across) many times over.  A chunk's sphere bounds its tiles'
+// spheres (eight adjacent lanes combine by shuffles).
+__global__ __launch_bounds__(256) void mlp_sphere_kernel(const float* __restrict__ points, int64_t M,
+                                                         float4* tile_sph, float4* chunk_sph) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nt = (M + TILE - 1) / TILE;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t j0 = k * TILE, j1 = min(j0 + TILE, M);
+    for (int64_t j = j0; j < j1; ++j)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], points[3 * j + a]);
+            hi[a] = fmaxf(hi[a], points[3 * j + a]);
+        }
+    float cen[3];
+    for (int a = 0; a < 3; ++a) cen[a] = 0.5f * (lo[a] + hi[a]);
+    float r2 = 0.0f;
+    for (int64_t j = j0; j < j1; ++j) {
+        const float dx = points[3 * j] - cen[0], dy = points[3 * j + 1] - cen[1], dz = points[3 * j + 2] - cen[2];
+        r2 = fmaxf(r2, fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+    }
+    const float r = fmaf(sqrtf(r2), 1.00001f, 1e-4f);
+    if (k < nt) tile_sph[k] = make_float4(cen[0], cen[1], cen[2], r);
+    // the chunk: box of the eight tiles' boxes, then the farthest tile sphere
+    float clo[3], chi[3];
+    for (int a = 0; a < 3; ++a) {
+        clo[a] = lo[a];
+        chi[a] = hi[a];
+        for (int o = 1; o < kTileChunk; o <<= 1) {
+            clo[a] = fminf(clo[a], __shfl_xor(clo[a], o, 64));
+            chi[a] = fmaxf(chi[a], __shfl_xor(chi[a], o, 64));
+        }
+    }
+    float cc[3];
+    for (int a = 0; a < 3; ++a) cc[a] = 0.5f * (clo[a] + chi[a]);
+    float rr = 0.0f;
+    if (k < nt) {
+        const float dx = cen[0] - cc[0], dy = cen[1] - cc[1], dz = cen[2] - cc[2];
+        rr = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) + r;
+    }
+    for (int o = 1; o < kTileChunk; o <<= 1) rr = fmaxf(rr, __shfl_xor(rr, o, 64));
+    if (k < nt && k % kTileChunk == 0) chunk_sph[k / kTileChunk] = make_float4(cc[0], cc[1], cc[2], fmaf(rr, 1.00001f, 1e-4f));
 }
 
 // First kernel of a bounded learned query: per (configuration c, link i),
@@ -901,6 +977,18 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
                                dim3(kBoundBlock), 0, s, b);
             if ((rc = check_launch("query_min_distance_mlp bounds")) != LSDF_OK) return rc;
             a.ubound = ub;
+            // the tile and chunk spheres, after the upper bounds
+            const int64_t nt = (M + TILE - 1) / TILE;
+            float4* tsph = reinterpret_cast<float4*>(reinterpret_cast<char*>(ub) + ((size_t)C * L * 4 + 255) / 256 * 256);
+            float4* csph = tsph + (nt + 15) / 16 * 16;
+            const size_t used = static_cast<size_t>(reinterpret_cast<char*>(csph + (nt + kTileChunk - 1) / kTileChunk) -
+                                                    static_cast<char*>(workspace));
+            if (used > need) return fail(LSDF_E_SHAPE, "query_mlp: workspace layout exceeds %zu bytes", need);
+            hipLaunchKernelGGL(mlp_sphere_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, points, M, tsph,
+                               csph);
+            if ((rc = check_launch("query_min_distance_mlp spheres")) != LSDF_OK) return rc;
+            a.tile_sph = tsph;
+            a.chunk_sph = csph;
         }
         hipEvent_t ev0, ev1;
         take_kernel_events(&ev0, &ev1);
