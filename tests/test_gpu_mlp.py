@@ -524,3 +524,32 @@ def test_query_mlp_learned_scale_sampled(B, orc):
     dn, ln = d.cpu().numpy().astype(np.float64), l.cpu().numpy()
     want_l = np.where(np.isfinite(ld.min(axis=1)), ld.argmin(axis=1), -1)
     assert np.array_equal(dn, ld.min(axis=1)) and np.array_equal(ln, want_l)
+
+
+@pytest.mark.parametrize("M", [1, 31, 33, 257, 300])
+def test_query_mlp_bounded_ragged_sizes(B, orc, tiny, tiny_grids, M):
+    """The bounded query (skipping on) at cloud sizes that leave partial
+    tiles and chunks (1, 31, 33, 257 and 300 points) and 3 configurations:
+    per-link minima against the oracle's per-pair intervals (every pair
+    evaluated there)."""
+    T32 = orc.fk(tiny.robot.dh, tiny.q[:3], tiny.robot.base_T).astype(np.float32)
+    cen, half, core = domains_of(tiny)
+    pts = tiny.points[::3][:M].astype(np.float32)
+    g32 = [g.astype(np.float32) for g in tiny_grids]
+    gs = _grid_set(B, tiny, tiny_grids)
+    margin, bound, s = 0.05, 0.04, 0.05
+    P, tolf = _shift_to_margin(orc, tiny, T32, tiny.points[:300].astype(np.float32), params_f32(7, 11), cen, half, core,
+                               margin, q=0.5, s=s)
+    _, em_raw, _ = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P.astype(np.float64), cen,
+                                 half, margin, each=True, core_k=core)
+    _, em, eg = orc.query_mlp(T32, tiny.grid_lo, tiny.grid_hi, tiny.grid_n, g32, pts, P.astype(np.float64), cen, half,
+                              margin, each=True, core_k=core, bounds=np.full(tiny.L, bound))
+    E = _core_each(orc, tiny, T32, pts, cen, half, core)
+    sure, maybe = _domain_bands(T32, cen, half, pts)
+    say(f"query_mlp bounded M={M} C=3")
+    ld = B.query_min_distance_mlp(dev(T32), gs, dev(P), (cen, half, core, bound), dev(pts), margin=margin,
+                                  link_dist=True)[2].cpu().numpy().astype(np.float64)
+    tol = _bounded_tol(tolf(em_raw, E), em_raw - E, bound)
+    lo, hi = _pair_intervals(em, eg, sure, maybe, margin, tol)
+    _check_minima(ld, lo, hi, f"M={M}")
+    assert np.array_equal(np.isfinite(ld), np.isfinite(lo.min(-1)) | np.isfinite(hi.min(-1)))
