@@ -180,6 +180,7 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
         GridMap gm{};
         float R[9] = {}, tr[3] = {};
         float thr = INFINITY;   // tiles whose pairs all have E - B above this are skipped
+        float ub_c = INFINITY;  // the current configuration's upper bound U
         auto flush = [&](int c) {
             const float w = wave_min(best);
             if (lane == 0 && w < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(w));
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
             const int c = (int)(ch / groups);
             const int64_t grp = ch - (int64_t)c * groups;
             if (c != cur) {
-                if (cur >= 0) flush(cur);
+                if (cur >= 0 && !p.ubound) flush(cur);   // (a bounded query flushes every chunk)
                 cur = c;
                 const float* T = p.link_T + ((int64_t)c * p.L + i) * 12;
                 gm = grid_map(lg, T);
@@ -202,56 +203,69 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
                     for (int s = 0; s < 3; ++s) R[3 * r + s] = T[4 * r + s];
                     tr[r] = T[4 * r + 3];
                 }
-                thr = p.ubound ? fmaxf(p.ubound[(int64_t)c * p.L + i], p.margin) : INFINITY;
+                if (p.ubound) ub_c = p.ubound[(int64_t)c * p.L + i];
+            }
+            if (p.ubound) {
+                // the threshold also falls to the smallest value found so far
+                // for (c, i) by any wave (the key; a stale read is larger, so
+                // still a bound of the minimum from above)
+                float lim = ub_c;
+                const uint32_t kv =
+                    __hip_atomic_load(&p.keys[(int64_t)c * p.L + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (kv) lim = fminf(lim, lsdf::from_ordered_bits(~kv));
+                thr = fmaxf(lim, p.margin);
             }
             // a chunk (then a tile) whose bounding sphere keeps every pair's
             // E - B above thr is skipped whole: E is 1-Lipschitz in the
             // link-frame point, so E >= E(centre) - radius over the sphere
             // (the radius is widened far beyond the FP32 rounding of E)
             if (p.ubound && sphere_beyond(p.chunk_sph[grp], R, tr, dm, thr)) continue;
-        for (int64_t k = grp * kTileChunk; k < min((grp + 1) * kTileChunk, (int64_t)p.tiles_per_c); ++k) {
-            if (p.ubound && sphere_beyond(p.tile_sph[k], R, tr, dm, thr)) continue;
-            const int64_t j0 = k * TILE;
-            float xh[NT][3], px[NT][3], e[NT];
-            bool indom[NT];
-            bool any = false;
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int64_t j = j0 + 16 * nt + (lane & 15);
-                const int64_t jj = min(j, p.M - 1);
-                px[nt][0] = p.points[3 * jj + 0];
-                px[nt][1] = p.points[3 * jj + 1];
-                px[nt][2] = p.points[3 * jj + 2];
-                float u[3];
-                const bool in = pair_frame(R, tr, dm, px[nt][0], px[nt][1], px[nt][2], u, xh[nt]);
-                e[nt] = core_distance(u[0], u[1], u[2], dm.core);
-                indom[nt] = (j < p.M) && in;
-                // a pair with E - B above thr cannot hold the minimum (its
-                // value exceeds the upper bound U of some pair that cannot
-                // fall back)
-                any |= indom[nt] && (e[nt] - dm.bound <= thr);
-            }
-            if (!__ballot(any)) continue;
-            float m[NT];
-            forward_tile<NT>(sW2, sW3, &sp, xh, m);
-            if (lane < 16) {
+            for (int64_t k = grp * kTileChunk; k < min((grp + 1) * kTileChunk, (int64_t)p.tiles_per_c); ++k) {
+                if (p.ubound && sphere_beyond(p.tile_sph[k], R, tr, dm, thr)) continue;
+                const int64_t j0 = k * TILE;
+                float xh[NT][3], px[NT][3], e[NT];
+                bool indom[NT];
+                bool any = false;
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
-                    if (!indom[nt]) continue;
-                    // below the margin the grid's value replaces the estimate;
-                    // a point outside the grid box keeps the estimate, since
-                    // the grid has no value there
-                    float tb;
-                    const float est = bounded_share(m[nt], dm.bound, dm.inv_bound, tb) + e[nt];
-                    float v = est;
-                    if (est < p.margin) {
-                        const float g = sample_or_inf<CUBIC, DT>(G, lg, gm, px[nt][0], px[nt][1], px[nt][2]);
-                        if (g < INFINITY) v = g;
+                    const int64_t j = j0 + 16 * nt + (lane & 15);
+                    const int64_t jj = min(j, p.M - 1);
+                    px[nt][0] = p.points[3 * jj + 0];
+                    px[nt][1] = p.points[3 * jj + 1];
+                    px[nt][2] = p.points[3 * jj + 2];
+                    float u[3];
+                    const bool in = pair_frame(R, tr, dm, px[nt][0], px[nt][1], px[nt][2], u, xh[nt]);
+                    e[nt] = core_distance(u[0], u[1], u[2], dm.core);
+                    indom[nt] = (j < p.M) && in;
+                    // a pair with E - B above thr cannot hold the minimum (its
+                    // value exceeds the value of some pair: a found minimum,
+                    // or the upper bound U of a pair that cannot fall back)
+                    any |= indom[nt] && (e[nt] - dm.bound <= thr);
+                }
+                if (!__ballot(any)) continue;
+                float m[NT];
+                forward_tile<NT>(sW2, sW3, &sp, xh, m);
+                if (lane < 16) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        if (!indom[nt]) continue;
+                        // below the margin the grid's value replaces the estimate;
+                        // a point outside the grid box keeps the estimate, since
+                        // the grid has no value there
+                        float tb;
+                        const float est = bounded_share(m[nt], dm.bound, dm.inv_bound, tb) + e[nt];
+                        float v = est;
+                        if (est < p.margin) {
+                            const float g = sample_or_inf<CUBIC, DT>(G, lg, gm, px[nt][0], px[nt][1], px[nt][2]);
+                            if (g < INFINITY) v = g;
+                        }
+                        best = fminf(best, v);
                     }
-                    best = fminf(best, v);
                 }
             }
-        }
+            // this chunk's minimum goes to the key at once, so that later
+            // chunks of (c, i), on any wave, skip against it
+            if (p.ubound) flush(c);
         }
         if (cur >= 0) flush(cur);
     }
