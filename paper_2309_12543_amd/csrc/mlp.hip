@@ -136,6 +136,7 @@ struct QueryMlpArgs {
     const float* ubound;     // [C][L] upper bounds U of the first kernel, or NULL (no bound: no skipping)
     const float4* tile_sph;  // [ceil(M / 32)] spheres bounding each tile's points (when ubound != NULL)
     const float4* chunk_sph; // [ceil(M / 256)] spheres bounding each chunk's points
+    const int32_t* seed;     // [C][L] the chunk holding the pair that gave U (-1: none), taken first
     int64_t M;
     int64_t tiles_per_link;
     int32_t tiles_per_c;
@@ -163,6 +164,11 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
     __shared__ int s_next;
     const int64_t groups = (p.M + kChunkPts - 1) / kChunkPts;   // chunks per configuration
     const int64_t nchunks = (int64_t)p.C * groups;
+    // a bounded query first takes, per configuration, the chunk that holds the
+    // pair that gave U (slots below C), so that the keys hold a small value
+    // early and the other chunks skip against it; every chunk then follows
+    // (a seed chunk a second time: same values, the minimum unchanged)
+    const int64_t nseed = p.seed ? p.C : 0;
     for (int i = 0; i < p.L; ++i) {
         const float* P = p.params + (int64_t)i * NPARAM;
         __syncthreads();   // every wave is done with the previous link's weights and chunks
@@ -190,10 +196,18 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
             int slot = 0;
             if (lane == 0) slot = atomicAdd(&s_next, 1);
             slot = __builtin_amdgcn_readfirstlane(__shfl(slot, 0, 64));
-            const int64_t ch = (int64_t)blockIdx.x + (int64_t)slot * gridDim.x;
-            if (ch >= nchunks) break;
-            const int c = (int)(ch / groups);
-            const int64_t grp = ch - (int64_t)c * groups;
+            const int64_t vs = (int64_t)blockIdx.x + (int64_t)slot * gridDim.x;
+            if (vs >= nseed + nchunks) break;
+            int c;
+            int64_t grp;
+            if (vs < nseed) {
+                c = (int)vs;
+                grp = p.seed[vs * p.L + i];
+                if (grp < 0) continue;
+            } else {
+                c = (int)((vs - nseed) / groups);
+                grp = (vs - nseed) - (int64_t)c * groups;
+            }
             if (c != cur) {
                 if (cur >= 0 && !p.ubound) flush(cur);   // (a bounded query flushes every chunk)
                 cur = c;
@@ -335,6 +349,7 @@ struct BoundArgs {
     const float* link_T;
     const float* points;
     float* ubound;           // [C][L]
+    int32_t* seed;           // [C][L] chunk (256 points) of a pair that gave U, -1 if U = +inf
     int64_t M;
     int32_t C;
     int32_t L;
@@ -346,6 +361,7 @@ __global__ __launch_bounds__(kBoundBlock) void mlp_bound_kernel(BoundArgs p) {
     const int c0 = blockIdx.x * kBoundConfigs;
     const Domain& dm = p.dom[i];
     float R[kBoundConfigs][9], tr[kBoundConfigs][3], ub[kBoundConfigs];
+    int ag[kBoundConfigs];
 #pragma unroll
     for (int k = 0; k < kBoundConfigs; ++k) {
         const int c = min(c0 + k, p.C - 1);
@@ -355,6 +371,7 @@ __global__ __launch_bounds__(kBoundBlock) void mlp_bound_kernel(BoundArgs p) {
             tr[k][r] = T[4 * r + 3];
         }
         ub[k] = INFINITY;
+        ag[k] = -1;
     }
     for (int64_t j = threadIdx.x; j < p.M; j += kBoundBlock) {
         const float x = p.points[3 * j + 0], y = p.points[3 * j + 1], z = p.points[3 * j + 2];
@@ -363,21 +380,36 @@ __global__ __launch_bounds__(kBoundBlock) void mlp_bound_kernel(BoundArgs p) {
             float u[3], xh[3];
             if (!pair_frame(R[k], tr[k], dm, x, y, z, u, xh)) continue;
             const float e = core_distance(u[0], u[1], u[2], dm.core);
-            if (e - dm.bound >= p.margin) ub[k] = fminf(ub[k], e + dm.bound);
+            if (e - dm.bound >= p.margin && e + dm.bound < ub[k]) {
+                ub[k] = e + dm.bound;
+                ag[k] = (int)(j / kChunkPts);
+            }
         }
     }
     __shared__ float s_ub[kBoundConfigs][kBoundBlock / 64];
+    __shared__ int s_ag[kBoundConfigs];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x < kBoundConfigs) s_ag[threadIdx.x] = INT32_MAX;
 #pragma unroll
     for (int k = 0; k < kBoundConfigs; ++k) {
         const float w = wave_min(ub[k]);
         if (lane == 0) s_ub[k][wave] = w;
     }
     __syncthreads();
+    // the block minimum, and the lowest chunk holding a pair that gives it
+#pragma unroll
+    for (int k = 0; k < kBoundConfigs; ++k) {
+        float v = INFINITY;
+        for (int w = 0; w < kBoundBlock / 64; ++w) v = fminf(v, s_ub[k][w]);
+        if (v < INFINITY && ub[k] == v) atomicMin(&s_ag[k], ag[k]);
+    }
+    __syncthreads();
     if (threadIdx.x < kBoundConfigs && c0 + (int)threadIdx.x < p.C) {
         float v = INFINITY;
         for (int w = 0; w < kBoundBlock / 64; ++w) v = fminf(v, s_ub[threadIdx.x][w]);
-        p.ubound[(int64_t)(c0 + threadIdx.x) * p.L + i] = v;
+        const int64_t o = (int64_t)(c0 + threadIdx.x) * p.L + i;
+        p.ubound[o] = v;
+        p.seed[o] = v < INFINITY ? s_ag[threadIdx.x] : -1;
     }
 }
 
@@ -978,11 +1010,20 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
             // the upper bounds, after the keys in the workspace (which holds
             // the plain query's tables too, far more than C L words)
             float* ub = reinterpret_cast<float*>(static_cast<char*>(workspace) + ((size_t)C * L * 4 + 255) / 256 * 256);
+            // then the tile and chunk spheres and the seed chunks
+            const int64_t nt = (M + TILE - 1) / TILE;
+            float4* tsph = reinterpret_cast<float4*>(reinterpret_cast<char*>(ub) + ((size_t)C * L * 4 + 255) / 256 * 256);
+            float4* csph = tsph + (nt + 15) / 16 * 16;
+            int32_t* seed = reinterpret_cast<int32_t*>(csph + (nt + kTileChunk - 1) / kTileChunk);
+            const size_t used = static_cast<size_t>(reinterpret_cast<char*>(seed + (int64_t)C * L) -
+                                                    static_cast<char*>(workspace));
+            if (used > need) return fail(LSDF_E_SHAPE, "query_mlp: workspace layout exceeds %zu bytes", need);
             BoundArgs b{};
             for (int i = 0; i < L; ++i) b.dom[i] = a.dom[i];
             b.link_T = link_T;
             b.points = points;
             b.ubound = ub;
+            b.seed = seed;
             b.M = M;
             b.C = C;
             b.L = L;
@@ -990,19 +1031,13 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
             hipLaunchKernelGGL(mlp_bound_kernel, dim3((unsigned)((C + kBoundConfigs - 1) / kBoundConfigs), L),
                                dim3(kBoundBlock), 0, s, b);
             if ((rc = check_launch("query_min_distance_mlp bounds")) != LSDF_OK) return rc;
-            a.ubound = ub;
-            // the tile and chunk spheres, after the upper bounds
-            const int64_t nt = (M + TILE - 1) / TILE;
-            float4* tsph = reinterpret_cast<float4*>(reinterpret_cast<char*>(ub) + ((size_t)C * L * 4 + 255) / 256 * 256);
-            float4* csph = tsph + (nt + 15) / 16 * 16;
-            const size_t used = static_cast<size_t>(reinterpret_cast<char*>(csph + (nt + kTileChunk - 1) / kTileChunk) -
-                                                    static_cast<char*>(workspace));
-            if (used > need) return fail(LSDF_E_SHAPE, "query_mlp: workspace layout exceeds %zu bytes", need);
             hipLaunchKernelGGL(mlp_sphere_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, points, M, tsph,
                                csph);
             if ((rc = check_launch("query_min_distance_mlp spheres")) != LSDF_OK) return rc;
+            a.ubound = ub;
             a.tile_sph = tsph;
             a.chunk_sph = csph;
+            a.seed = seed;
         }
         hipEvent_t ev0, ev1;
         take_kernel_events(&ev0, &ev1);
