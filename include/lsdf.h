@@ -431,10 +431,12 @@ int lsdf_mlp_eval(const float* params, const lsdf_mlp_domain* domain, const floa
  * the grid value) or -inf (none does).  A pair that takes the grid value gets
  * exactly the bits lsdf_query_min_distance would give it.  With a finite
  * bound B_i a first kernel finds, per (c, i), U = the smallest E + B_i over
- * the in-domain pairs with E - B_i >= margin (pairs that cannot fall back),
- * and the network is evaluated only for 32-pair tiles holding a pair with
- * E - B_i <= max(U, margin): every other pair's value exceeds U, so the
- * per-link minima are those of evaluating every pair. */
+ * a sample of the in-domain pairs with E - B_i >= margin (pairs that cannot
+ * fall back; the sample: the first point of every 32-point tile), and the
+ * network is evaluated only for 32-pair tiles holding a pair with
+ * E - B_i <= max(min(U, the smallest value found so far), margin): every
+ * other pair's value exceeds a value some pair has, so the per-link minima
+ * are those of evaluating every pair. */
 int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t L, const lsdf_grid* grids,
                                 const void* grid_buf, const float* mlp_params, const lsdf_mlp_domain* domains,
                                 float margin, const float* points, int64_t M, float* out_dist, int32_t* out_link,

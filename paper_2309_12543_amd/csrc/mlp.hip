@@ -333,14 +333,16 @@ __global__ __launch_bounds__(256) void mlp_sphere_kernel(const float* __restrict
 }
 
 // First kernel of a bounded learned query: per (configuration c, link i),
-// U = the smallest E + B over the in-domain pairs with E - B >= margin (pairs
-// whose estimate, at least E - B, cannot fall below the margin and so cannot
-// take the grid's value), +inf if none.  Every such pair's value is at most
-// its E + B, so U bounds the minimum from above, and a pair with E - B > U
-// cannot hold it.  A workgroup takes one link and kBoundConfigs
-// configurations (their poses in scalar registers) and strides over the
-// points; the pair arithmetic is pair_frame's and core_distance's, as in
-// the query.
+// U = the smallest E + B over a sample of the in-domain pairs with
+// E - B >= margin (pairs whose estimate, at least E - B, cannot fall below
+// the margin and so cannot take the grid's value): the first point of every
+// 32-point tile; +inf if none.  Every such pair's value is at most its
+// E + B, so U bounds the minimum from above (over any sample of pairs), and a
+// pair with E - B > U cannot hold it.  Also the chunk holding the sampled
+// pair that gave U (the query takes it first).  A workgroup takes one link
+// and kBoundConfigs configurations (their poses in scalar registers) and
+// strides over the tiles; the pair arithmetic is pair_frame's and
+// core_distance's, as in the query.
 constexpr int kBoundBlock = 256;
 constexpr int kBoundConfigs = 4;
 
@@ -373,7 +375,7 @@ __global__ __launch_bounds__(kBoundBlock) void mlp_bound_kernel(BoundArgs p) {
         ub[k] = INFINITY;
         ag[k] = -1;
     }
-    for (int64_t j = threadIdx.x; j < p.M; j += kBoundBlock) {
+    for (int64_t j = (int64_t)threadIdx.x * TILE; j < p.M; j += (int64_t)kBoundBlock * TILE) {
         const float x = p.points[3 * j + 0], y = p.points[3 * j + 1], z = p.points[3 * j + 2];
 #pragma unroll
         for (int k = 0; k < kBoundConfigs; ++k) {
