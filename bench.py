@@ -698,7 +698,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the clearance query is measured on a single MI355X "
-              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+              "(sharding waypoints over GPUs is designed, not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

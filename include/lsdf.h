@@ -381,9 +381,9 @@ int lsdf_build_link_sdf(const float* verts, int32_t nv, const int32_t* tris, int
  * bound B (B = +inf: E + m).  E carries the distance's growth far from the
  * link, so the network only fits a bounded, slowly varying remainder, and
  * since the estimate lies within B of E a query skips, exactly, the points
- * that cannot hold a link's minimum.  It answers queries beyond the grid box (the far field); the
- * grid stays the answer for every pair whose estimate is below a safety
- * margin, and the judge of the network's error.  The paper's own network
+ * that cannot hold a link's minimum.  It answers queries beyond the grid box
+ * (the far field); the grid stays the answer for every pair in the box whose
+ * estimate is below a safety margin.  The paper's own network
  * (Sec. III-B-1) is a different one (it approximates the grid transform);
  * its training recipe (L1 loss, Adam, Sec. IV-B) is reused here.
  *
