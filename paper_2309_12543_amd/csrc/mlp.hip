@@ -166,8 +166,8 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
     const int64_t nchunks = (int64_t)p.C * groups;
     // a bounded query first takes, per configuration, the chunk that holds the
     // pair that gave U (slots below C), so that the keys hold a small value
-    // early and the other chunks skip against it; every chunk then follows
-    // (a seed chunk a second time: same values, the minimum unchanged)
+    // early and the other chunks skip against it; every other chunk then
+    // follows (the seed slot of (c, i) processes its chunk in any case)
     const int64_t nseed = p.seed ? p.C : 0;
     for (int i = 0; i < p.L; ++i) {
         const float* P = p.params + (int64_t)i * NPARAM;
@@ -187,6 +187,7 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
         float R[9] = {}, tr[3] = {};
         float thr = INFINITY;   // tiles whose pairs all have E - B above this are skipped
         float ub_c = INFINITY;  // the current configuration's upper bound U
+        int64_t seed_c = -1;    // and its seed chunk
         auto flush = [&](int c) {
             const float w = wave_min(best);
             if (lane == 0 && w < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(w));
@@ -218,7 +219,9 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
                     tr[r] = T[4 * r + 3];
                 }
                 if (p.ubound) ub_c = p.ubound[(int64_t)c * p.L + i];
+                if (p.seed) seed_c = p.seed[(int64_t)c * p.L + i];
             }
+            if (vs >= nseed && grp == seed_c) continue;   // taken in the seed slots
             if (p.ubound) {
                 // the threshold also falls to the smallest value found so far
                 // for (c, i) by any wave (the key; a stale read is larger, so
