@@ -433,7 +433,8 @@ int lsdf_mlp_eval(const float* params, const lsdf_mlp_domain* domain, const floa
  * bound B_i a first kernel finds, per (c, i), U = the smallest E + B_i over
  * a sample of the in-domain pairs with E - B_i >= margin (pairs that cannot
  * fall back; the sample: the first point of every 32-point tile), and the
- * network is evaluated only for 32-pair tiles holding a pair with
+ * network is evaluated only for 32-pair tiles (or the 16-pair half of one)
+ * holding a pair with
  * E - B_i <= max(min(U, the smallest value found so far), margin): every
  * other pair's value exceeds a value some pair has, so the per-link minima
  * are those of evaluating every pair. */

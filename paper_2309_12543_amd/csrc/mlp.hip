@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
                 const int64_t j0 = k * TILE;
                 float xh[NT][3], px[NT][3], e[NT];
                 bool indom[NT];
-                bool any = false;
+                bool any[NT];
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
                     const int64_t j = j0 + 16 * nt + (lane & 15);
@@ -257,11 +257,27 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
                     // a pair with E - B above thr cannot hold the minimum (its
                     // value exceeds the value of some pair: a found minimum,
                     // or the upper bound U of a pair that cannot fall back)
-                    any |= indom[nt] && (e[nt] - dm.bound <= thr);
+                    any[nt] = __ballot(indom[nt] && (e[nt] - dm.bound <= thr)) != 0;
                 }
-                if (!__ballot(any)) continue;
+                static_assert(NT == 2, "a tile of two 16-pair halves");
+                if (!any[0] && !any[1]) continue;
                 float m[NT];
-                forward_tile<NT>(sW2, sW3, &sp, xh, m);
+                if (any[0] && any[1]) {
+                    forward_tile<NT>(sW2, sW3, &sp, xh, m);
+                } else {
+                    // only one half may hold the minimum: the network runs on
+                    // that half alone (each 16-pair half is its own MFMA
+                    // column group, so its values are the same bits), and the
+                    // other half's pairs are skipped like a whole tile's
+                    const bool h0 = any[0];
+                    const float xs[1][3] = {{h0 ? xh[0][0] : xh[1][0], h0 ? xh[0][1] : xh[1][1],
+                                             h0 ? xh[0][2] : xh[1][2]}};
+                    float m1[1];
+                    forward_tile<1>(sW2, sW3, &sp, xs, m1);
+                    m[0] = m1[0];
+                    m[1] = m1[0];
+                    if (h0) indom[1] = false; else indom[0] = false;
+                }
                 if (lane < 16) {
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) {
