@@ -136,7 +136,8 @@ struct QueryMlpArgs {
     const float* ubound;     // [C][L] upper bounds U of the first kernel, or NULL (no bound: no skipping)
     const float4* tile_sph;  // [ceil(M / 32)] spheres bounding each tile's points (when ubound != NULL)
     const float4* chunk_sph; // [ceil(M / 256)] spheres bounding each chunk's points
-    const int32_t* seed;     // [C][L] the chunk holding the pair that gave U (-1: none), taken first
+    const int32_t* seed;     // [2][C][L] the chunks holding the pair that gave U and the sampled pair
+                             // nearest the core box (-1: none), taken first
     int64_t M;
     int64_t tiles_per_link;
     int32_t tiles_per_c;
@@ -165,10 +166,12 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
     const int64_t groups = (p.M + kChunkPts - 1) / kChunkPts;   // chunks per configuration
     const int64_t nchunks = (int64_t)p.C * groups;
     // a bounded query first takes, per configuration, the chunk that holds the
-    // pair that gave U (slots below C), so that the keys hold a small value
-    // early and the other chunks skip against it; every other chunk then
-    // follows (the seed slot of (c, i) processes its chunk in any case)
-    const int64_t nseed = p.seed ? p.C : 0;
+    // pair that gave U (slots below C), then the chunk holding the sampled
+    // pair nearest the core box (slots C to 2 C: where a minimum that falls
+    // back to the grid lies), so that the keys hold a small value early and
+    // the other chunks skip against it; every other chunk then follows (the
+    // seed slots of (c, i) process their chunks in any case)
+    const int64_t nseed = p.seed ? 2 * (int64_t)p.C : 0;
     for (int i = 0; i < p.L; ++i) {
         const float* P = p.params + (int64_t)i * NPARAM;
         __syncthreads();   // every wave is done with the previous link's weights and chunks
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
         float R[9] = {}, tr[3] = {};
         float thr = INFINITY;   // tiles whose pairs all have E - B above this are skipped
         float ub_c = INFINITY;  // the current configuration's upper bound U
-        int64_t seed_c = -1;    // and its seed chunk
+        int64_t seed_c = -1, near_c = -1;   // and its seed chunks
         auto flush = [&](int c) {
             const float w = wave_min(best);
             if (lane == 0 && w < INFINITY) atomicMax(&p.keys[(int64_t)c * p.L + i], ~lsdf::ordered_bits(w));
@@ -202,9 +205,10 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
             int c;
             int64_t grp;
             if (vs < nseed) {
-                c = (int)vs;
+                c = (int)(vs < p.C ? vs : vs - p.C);
                 grp = p.seed[vs * p.L + i];
-                if (grp < 0) continue;
+                // the near chunk when it is not the first one already
+                if (grp < 0 || (vs >= p.C && grp == p.seed[(int64_t)c * p.L + i])) continue;
             } else {
                 c = (int)((vs - nseed) / groups);
                 grp = (vs - nseed) - (int64_t)c * groups;
@@ -219,9 +223,12 @@ __global__ __launch_bounds__(kQueryBlock) __attribute__((amdgpu_waves_per_eu(3, 
                     tr[r] = T[4 * r + 3];
                 }
                 if (p.ubound) ub_c = p.ubound[(int64_t)c * p.L + i];
-                if (p.seed) seed_c = p.seed[(int64_t)c * p.L + i];
+                if (p.seed) {
+                    seed_c = p.seed[(int64_t)c * p.L + i];
+                    near_c = p.seed[((int64_t)p.C + c) * p.L + i];
+                }
             }
-            if (vs >= nseed && grp == seed_c) continue;   // taken in the seed slots
+            if (vs >= nseed && (grp == seed_c || grp == near_c)) continue;   // taken in the seed slots
             if (p.ubound) {
                 // the threshold also falls to the smallest value found so far
                 // for (c, i) by any wave (the key; a stale read is larger, so
@@ -370,7 +377,8 @@ struct BoundArgs {
     const float* link_T;
     const float* points;
     float* ubound;           // [C][L]
-    int32_t* seed;           // [C][L] chunk (256 points) of a pair that gave U, -1 if U = +inf
+    int32_t* seed;           // [2][C][L] chunk (256 points) of a pair that gave U, -1 if U = +inf; then
+                             // that of the sampled in-domain pair with the smallest E, -1 if none
     int64_t M;
     int32_t C;
     int32_t L;
@@ -381,8 +389,8 @@ __global__ __launch_bounds__(kBoundBlock) void mlp_bound_kernel(BoundArgs p) {
     const int i = blockIdx.y;
     const int c0 = blockIdx.x * kBoundConfigs;
     const Domain& dm = p.dom[i];
-    float R[kBoundConfigs][9], tr[kBoundConfigs][3], ub[kBoundConfigs];
-    int ag[kBoundConfigs];
+    float R[kBoundConfigs][9], tr[kBoundConfigs][3], ub[kBoundConfigs], en[kBoundConfigs];
+    int ag[kBoundConfigs], ng[kBoundConfigs];
 #pragma unroll
     for (int k = 0; k < kBoundConfigs; ++k) {
         const int c = min(c0 + k, p.C - 1);
@@ -393,6 +401,8 @@ __global__ __launch_bounds__(kBoundBlock) void mlp_bound_kernel(BoundArgs p) {
         }
         ub[k] = INFINITY;
         ag[k] = -1;
+        en[k] = INFINITY;
+        ng[k] = -1;
     }
     for (int64_t j = (int64_t)threadIdx.x * TILE; j < p.M; j += (int64_t)kBoundBlock * TILE) {
         const float x = p.points[3 * j + 0], y = p.points[3 * j + 1], z = p.points[3 * j + 2];
@@ -405,32 +415,50 @@ __global__ __launch_bounds__(kBoundBlock) void mlp_bound_kernel(BoundArgs p) {
                 ub[k] = e + dm.bound;
                 ag[k] = (int)(j / kChunkPts);
             }
+            if (e < en[k]) {
+                en[k] = e;
+                ng[k] = (int)(j / kChunkPts);
+            }
         }
     }
-    __shared__ float s_ub[kBoundConfigs][kBoundBlock / 64];
-    __shared__ int s_ag[kBoundConfigs];
+    __shared__ float s_ub[kBoundConfigs][kBoundBlock / 64], s_en[kBoundConfigs][kBoundBlock / 64];
+    __shared__ int s_ag[kBoundConfigs], s_ng[kBoundConfigs];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x < kBoundConfigs) s_ag[threadIdx.x] = INT32_MAX;
+    if (threadIdx.x < kBoundConfigs) {
+        s_ag[threadIdx.x] = INT32_MAX;
+        s_ng[threadIdx.x] = INT32_MAX;
+    }
 #pragma unroll
     for (int k = 0; k < kBoundConfigs; ++k) {
-        const float w = wave_min(ub[k]);
-        if (lane == 0) s_ub[k][wave] = w;
+        const float w = wave_min(ub[k]), we = wave_min(en[k]);
+        if (lane == 0) {
+            s_ub[k][wave] = w;
+            s_en[k][wave] = we;
+        }
     }
     __syncthreads();
-    // the block minimum, and the lowest chunk holding a pair that gives it
+    // the block minima, and the lowest chunk holding a pair that gives each
 #pragma unroll
     for (int k = 0; k < kBoundConfigs; ++k) {
-        float v = INFINITY;
-        for (int w = 0; w < kBoundBlock / 64; ++w) v = fminf(v, s_ub[k][w]);
+        float v = INFINITY, ve = INFINITY;
+        for (int w = 0; w < kBoundBlock / 64; ++w) {
+            v = fminf(v, s_ub[k][w]);
+            ve = fminf(ve, s_en[k][w]);
+        }
         if (v < INFINITY && ub[k] == v) atomicMin(&s_ag[k], ag[k]);
+        if (ve < INFINITY && en[k] == ve) atomicMin(&s_ng[k], ng[k]);
     }
     __syncthreads();
     if (threadIdx.x < kBoundConfigs && c0 + (int)threadIdx.x < p.C) {
-        float v = INFINITY;
-        for (int w = 0; w < kBoundBlock / 64; ++w) v = fminf(v, s_ub[threadIdx.x][w]);
+        float v = INFINITY, ve = INFINITY;
+        for (int w = 0; w < kBoundBlock / 64; ++w) {
+            v = fminf(v, s_ub[threadIdx.x][w]);
+            ve = fminf(ve, s_en[threadIdx.x][w]);
+        }
         const int64_t o = (int64_t)(c0 + threadIdx.x) * p.L + i;
         p.ubound[o] = v;
         p.seed[o] = v < INFINITY ? s_ag[threadIdx.x] : -1;
+        p.seed[(int64_t)p.C * p.L + o] = ve < INFINITY ? s_ng[threadIdx.x] : -1;
     }
 }
 
@@ -1036,7 +1064,7 @@ LSDF_API int lsdf_query_min_distance_mlp(const float* link_T, int32_t C, int32_t
             float4* tsph = reinterpret_cast<float4*>(reinterpret_cast<char*>(ub) + ((size_t)C * L * 4 + 255) / 256 * 256);
             float4* csph = tsph + (nt + 15) / 16 * 16;
             int32_t* seed = reinterpret_cast<int32_t*>(csph + (nt + kTileChunk - 1) / kTileChunk);
-            const size_t used = static_cast<size_t>(reinterpret_cast<char*>(seed + (int64_t)C * L) -
+            const size_t used = static_cast<size_t>(reinterpret_cast<char*>(seed + 2 * (int64_t)C * L) -
                                                     static_cast<char*>(workspace));
             if (used > need) return fail(LSDF_E_SHAPE, "query_mlp: workspace layout exceeds %zu bytes", need);
             BoundArgs b{};
